@@ -1,0 +1,205 @@
+"""ctypes view of oracle/liboracle.so -- the sequential FP64 Sherman-Morrison
+oracle of arXiv:1708.00744 (eq. (1) ratio, eq. (2) update, LU for fresh
+determinants).  Test infrastructure only: the product path never imports it.
+
+Every function here is argument marshalling; the arithmetic is in
+oracle/dsu_oracle.c.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+
+def _declare(L):
+    L.orc_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
+    L.orc_philox4x64_10.restype = None
+    L.orc_uniform53.argtypes = [C.c_uint64]
+    L.orc_uniform53.restype = C.c_double
+    L.orc_move_randoms.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, _dp, C.POINTER(C.c_double)]
+    L.orc_move_randoms.restype = None
+    L.orc_pw_kvectors.argtypes = [C.c_int, _ip]
+    L.orc_pw_kvectors.restype = C.c_int
+    L.orc_pw_row.argtypes = [C.c_int, _ip, C.c_double, _dp, _dp]
+    L.orc_pw_row.restype = None
+    L.orc_pw_matrix.argtypes = [C.c_int, _ip, C.c_double, _dp, _dp]
+    L.orc_pw_matrix.restype = None
+    L.orc_lu.argtypes = [C.c_int, _dp, _ip, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.orc_lu.restype = C.c_int
+    L.orc_slogdet.argtypes = [C.c_int, _dp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.orc_slogdet.restype = C.c_int
+    L.orc_inverse.argtypes = [C.c_int, _dp, _dp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.orc_inverse.restype = C.c_int
+    L.orc_residual.argtypes = [C.c_int, _dp, _dp]
+    L.orc_residual.restype = C.c_double
+    L.orc_sm_ratio.argtypes = [C.c_int, _dp, C.c_int, _dp]
+    L.orc_sm_ratio.restype = C.c_double
+    L.orc_sm_accept.argtypes = [C.c_int, _dp, C.c_void_p, C.c_int, _dp, C.c_double, _dp]
+    L.orc_sm_accept.restype = None
+    vp = C.c_void_p
+    L.orc_walker_run.argtypes = [C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_int, C.c_double,
+                                 C.c_int, C.c_int, C.c_int, _dp,
+                                 vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.orc_walker_run.restype = C.c_int
+    L.orc_walkers_run.argtypes = [C.c_int, C.c_int, C.c_double, _u64p, _u64p, vp, C.c_double,
+                                  C.c_int, C.c_int, C.c_int, _dp, vp, vp, vp, vp, vp, _ip]
+    L.orc_walkers_run.restype = C.c_int
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def philox4x64_10(ctr, key):
+    out = np.zeros(4, np.uint64)
+    lib().orc_philox4x64_10(np.ascontiguousarray(ctr, np.uint64), np.ascontiguousarray(key, np.uint64), out)
+    return out
+
+
+def uniform53(x):
+    return lib().orc_uniform53(int(x))
+
+
+def move_randoms(seed, walker, sweep, slot):
+    g = np.zeros(3)
+    u = C.c_double()
+    lib().orc_move_randoms(seed, walker, sweep, slot, g, C.byref(u))
+    return g, u.value
+
+
+def pw_kvectors(n):
+    out = np.zeros((n, 4), np.int32)
+    rc = lib().orc_pw_kvectors(n, out)
+    if rc != 0:
+        raise ValueError("bad n")
+    return out
+
+
+def pw_row(kv, L, r):
+    n = kv.shape[0]
+    row = np.zeros(n)
+    lib().orc_pw_row(n, np.ascontiguousarray(kv, np.int32), float(L), np.ascontiguousarray(r, np.float64), row)
+    return row
+
+
+def pw_matrix(kv, L, pos):
+    n = kv.shape[0]
+    a = np.zeros((n, n))
+    lib().orc_pw_matrix(n, np.ascontiguousarray(kv, np.int32), float(L), np.ascontiguousarray(pos, np.float64), a)
+    return a
+
+
+def slogdet(a):
+    a = np.ascontiguousarray(a, np.float64)
+    ld, s = C.c_double(), C.c_int()
+    rc = lib().orc_slogdet(a.shape[0], a, C.byref(ld), C.byref(s))
+    if rc != 0:
+        return 0, -np.inf
+    return s.value, ld.value
+
+
+def inverse(a):
+    """(Ainv, sign, logdet); raises on an exactly singular matrix."""
+    a = np.ascontiguousarray(a, np.float64)
+    n = a.shape[0]
+    inv = np.zeros((n, n))
+    ld, s = C.c_double(), C.c_int()
+    rc = lib().orc_inverse(n, a, inv, C.byref(ld), C.byref(s))
+    if rc != 0:
+        raise np.linalg.LinAlgError("singular")
+    return inv, s.value, ld.value
+
+
+def residual(ainv, a):
+    return lib().orc_residual(a.shape[0], np.ascontiguousarray(ainv), np.ascontiguousarray(a))
+
+
+def sm_ratio(ainv, e, phi):
+    return lib().orc_sm_ratio(ainv.shape[0], np.ascontiguousarray(ainv), int(e), np.ascontiguousarray(phi, np.float64))
+
+
+def sm_accept(ainv, a, e, phi, r):
+    """In place: Ainv <- eq. (2) update, A[e,:] <- phi (if a is not None)."""
+    n = ainv.shape[0]
+    assert ainv.flags.c_contiguous and ainv.dtype == np.float64
+    if a is not None:
+        assert a.flags.c_contiguous and a.dtype == np.float64
+    work = np.zeros(2 * n)
+    lib().orc_sm_accept(n, ainv, _ptr(a), int(e), np.ascontiguousarray(phi, np.float64), float(r), work)
+
+
+class WalkerTrace:
+    """Everything orc_walker_run reports for one walker determinant."""
+
+    def __init__(self, n, sweeps):
+        self.ratio = np.zeros(sweeps * n)
+        self.u = np.zeros(sweeps * n)
+        self.accepted = np.zeros(sweeps * n, np.uint8)
+        self.logdet_run = np.zeros(sweeps)
+        self.sign_run = np.zeros(sweeps, np.int32)
+        self.logdet_fresh = np.zeros(sweeps)
+        self.sign_fresh = np.zeros(sweeps, np.int32)
+        self.residual = np.zeros(sweeps)
+        self.pos = np.zeros((n, 3))
+        self.ainv = np.zeros((n, n))
+        self.n_accepted = np.zeros(1, np.int64)
+
+
+def walker_run(n, L, seed, walker, spin, sigma, pos, sweeps, first_sweep=0, force_accept=False,
+               residual=True, fresh=True):
+    """Run `sweeps` Metropolis sweeps of one determinant (eq. (1) + eq. (2))."""
+    t = WalkerTrace(n, sweeps)
+    pos = np.ascontiguousarray(pos, np.float64).reshape(n, 3)
+    rc = lib().orc_walker_run(n, float(L), int(seed), int(walker), int(spin), float(sigma), int(first_sweep),
+                              int(sweeps), int(bool(force_accept)), pos,
+                              _ptr(t.ratio), _ptr(t.u), _ptr(t.accepted), _ptr(t.logdet_run), _ptr(t.sign_run),
+                              _ptr(t.logdet_fresh) if fresh else None, _ptr(t.sign_fresh) if fresh else None,
+                              _ptr(t.residual) if residual else None, _ptr(t.pos), _ptr(t.ainv),
+                              _ptr(t.n_accepted))
+    if rc != 0:
+        raise np.linalg.LinAlgError("singular start")
+    return t
+
+
+def walkers_run(n, L, seeds, walker_ids, spins, sigma, pos, sweeps, first_sweep=0, force_accept=False):
+    """Independent determinants in OpenMP threads.  Returns (ratio[w, sweeps*n],
+    accepted, logdet_run[w, sweeps], pos_out, n_accepted, threads_used)."""
+    nw = len(seeds)
+    seeds = np.ascontiguousarray(seeds, np.uint64)
+    walker_ids = np.ascontiguousarray(walker_ids, np.uint64)
+    spins = np.ascontiguousarray(spins, np.int32)
+    pos = np.ascontiguousarray(pos, np.float64).reshape(nw, n * 3)
+    ratio = np.zeros((nw, sweeps * n))
+    acc = np.zeros((nw, sweeps * n), np.uint8)
+    ld = np.zeros((nw, sweeps))
+    pos_out = np.zeros((nw, n * 3))
+    nacc = np.zeros(nw, np.int64)
+    status = np.zeros(nw, np.int32)
+    threads = lib().orc_walkers_run(nw, n, float(L), seeds, walker_ids, _ptr(spins), float(sigma), int(first_sweep),
+                                    int(sweeps), int(bool(force_accept)), pos, _ptr(ratio), _ptr(acc), _ptr(ld),
+                                    _ptr(pos_out), _ptr(nacc), status)
+    if np.any(status != 0):
+        raise np.linalg.LinAlgError("singular start")
+    return ratio, acc, ld, pos_out.reshape(nw, n, 3), nacc, threads

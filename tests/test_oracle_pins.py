@@ -1,0 +1,334 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each check ties one oracle function to mathematics the paper fixes, to a
+closed form, to exact rational arithmetic, or to an independent library
+routine, so that a dropped term, a wrong sign, a wrong index or a transposed
+operand inside the oracle fails at least one of them.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_00744_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- helpers
+def frac_det(m):
+    """Exact determinant of a small integer/rational matrix (Fraction Gaussian
+    elimination; independent of the oracle's floating-point LU)."""
+    a = [[Fraction(x) for x in row] for row in m]
+    n = len(a)
+    det = Fraction(1)
+    for k in range(n):
+        p = next((i for i in range(k, n) if a[i][k] != 0), None)
+        if p is None:
+            return Fraction(0)
+        if p != k:
+            a[k], a[p] = a[p], a[k]
+            det = -det
+        det *= a[k][k]
+        for i in range(k + 1, n):
+            f = a[i][k] / a[k][k]
+            for j in range(k, n):
+                a[i][j] -= f * a[k][j]
+    return det
+
+
+def frac_inverse(m):
+    n = len(m)
+    a = [[Fraction(x) for x in row] + [Fraction(int(i == j)) for j in range(n)] for i, row in enumerate(m)]
+    for k in range(n):
+        p = next(i for i in range(k, n) if a[i][k] != 0)
+        a[k], a[p] = a[p], a[k]
+        piv = a[k][k]
+        a[k] = [x / piv for x in a[k]]
+        for i in range(n):
+            if i != k and a[i][k] != 0:
+                f = a[i][k]
+                a[i] = [x - f * y for x, y in zip(a[i], a[k])]
+    return [[a[i][n + j] for j in range(n)] for i in range(n)]
+
+
+def nonsingular_integer_matrix(seed, n):
+    for s in range(seed, seed + 1000):
+        m = inputs.integer_matrix(s, n)
+        if frac_det(m.astype(int).tolist()) != 0:
+            return m
+    raise RuntimeError
+
+
+# ------------------------------------------------------------------ Philox
+@pytest.mark.parametrize("key,ctr", [((0, 0), (0, 0, 0, 0)), ((123456789, 987654321), (5, 7, 11, 13)),
+                                     ((2**64 - 1, 2**63), (2**64 - 2, 2**64 - 1, 3, 2**40))])
+def test_philox_matches_numpy(key, ctr):
+    # numpy's Philox is Philox4x64-10 and advances its 256-bit counter
+    # (word 0 least significant) before the first block, so its raw words
+    # are blocks ctr + 1, ctr + 2, ...
+    k = np.array(key, np.uint64)
+    raw = np.random.Philox(key=k, counter=np.array(ctr, np.uint64)).random_raw(8)
+    big = sum(int(w) << (64 * i) for i, w in enumerate(ctr))
+    for b in range(2):
+        v = (big + 1 + b) % (1 << 256)
+        c = np.array([(v >> (64 * i)) & (2**64 - 1) for i in range(4)], np.uint64)
+        np.testing.assert_array_equal(oracle.philox4x64_10(c, k), raw[4 * b:4 * b + 4])
+
+
+def test_uniform53_range():
+    assert oracle.uniform53(0) == 0.0
+    assert oracle.uniform53(2**64 - 1) == 1.0 - 2.0**-53
+    assert oracle.uniform53(2**63) == 0.5
+
+
+def test_move_randoms_distribution():
+    from scipy import stats
+    g = np.array([oracle.move_randoms(7, 3, s, e)[0] for s in range(4) for e in range(1500)])
+    u = np.array([oracle.move_randoms(7, 3, s, e)[1] for s in range(4) for e in range(1500)])
+    for c in range(3):
+        assert stats.kstest(g[:, c], "norm").pvalue > 1e-3
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+    # the three Gaussians of a move are independent of each other and of u
+    cc = np.corrcoef(np.column_stack([g, u]).T)
+    assert np.max(np.abs(cc - np.eye(4))) < 0.05
+    # the stream is keyed: a different walker gives a different move
+    assert not np.allclose(oracle.move_randoms(7, 3, 0, 0)[0], oracle.move_randoms(7, 4, 0, 0)[0])
+
+
+# -------------------------------------------------------------- plane waves
+def _r3_golden():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "lattice_shells.txt")) if not l.startswith("#")]
+    return {int(s): int(c) for s, c in rows}
+
+
+def test_lattice_shell_counts():
+    r3 = _r3_golden()
+    # brute-force count of the golden numbers themselves
+    for s, c in r3.items():
+        m = int(math.isqrt(s)) + 1
+        bf = sum(1 for x in range(-m, m + 1) for y in range(-m, m + 1) for z in range(-m, m + 1)
+                 if x * x + y * y + z * z == s)
+        assert bf == c
+    # cumulative orbital counts at closed shells: 1, 7, 19, 27, 33, 57, 81, 81, 93, 123, ...
+    closed = np.cumsum([r3[s] for s in range(21)])
+    kv = oracle.pw_kvectors(int(closed[-1]))
+    n2 = kv[:, 0] ** 2 + kv[:, 1] ** 2 + kv[:, 2] ** 2
+    for s in range(21):
+        assert int(np.sum(n2 <= s)) == closed[s], s
+    # every orbital's shell is non-decreasing and each +-n pair appears once as cos, once as sin
+    assert np.all(np.diff(n2) >= 0)
+    reps = {}
+    for nx, ny, nz, kind in kv[1:]:
+        reps.setdefault((nx, ny, nz), []).append(kind)
+        first = nx if nx != 0 else (ny if ny != 0 else nz)
+        assert first > 0
+    assert all(sorted(v) == [1, 2] for v in reps.values())
+    assert tuple(kv[0]) == (0, 0, 0, 0)
+
+
+def test_shell_cut_and_order():
+    # N = 64 cuts shell |n|^2 = 6 (57 orbitals close |n|^2 = 5)
+    kv = oracle.pw_kvectors(64)
+    n2 = kv[:, 0] ** 2 + kv[:, 1] ** 2 + kv[:, 2] ** 2
+    assert np.sum(n2 <= 5) == 57 and np.all(n2[57:] == 6)
+    # within the cut shell: representatives ascending in (nx, ny, nz), cos then sin
+    tail = [tuple(r) for r in kv[57:]]
+    # |n|^2 = 6 has no zero component: (1,-2,-1), (1,-2,1), (1,-1,-2), (1,-1,2), ...
+    assert tail == [(1, -2, -1, 1), (1, -2, -1, 2), (1, -2, 1, 1), (1, -2, 1, 2),
+                    (1, -1, -2, 1), (1, -1, -2, 2), (1, -1, 2, 1)]
+    # prefix property: the first n orbitals do not depend on how many are asked for
+    assert np.array_equal(oracle.pw_kvectors(1024)[:64], kv)
+
+
+def test_plane_wave_orthogonality():
+    # On an M^3 uniform grid of the box, distinct plane waves are orthogonal,
+    # |1|^2 sums to M^3 and |cos|^2 = |sin|^2 sum to M^3 / 2 (for 2n not a
+    # multiple of M).  Catches a wrong 2 pi / L, a duplicated vector or a
+    # cos/sin mix-up.
+    n, L, M = 81, 7.3, 11
+    kv = oracle.pw_kvectors(n)
+    g = (np.arange(M) + 0.25) * (L / M)
+    pts = np.array(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1).T
+    A = np.array([oracle.pw_row(kv, L, p) for p in pts])
+    S = A.T @ A / M**3
+    want = np.diag([1.0] + [0.5] * (n - 1))
+    np.testing.assert_allclose(S, want, atol=1e-12)
+
+
+def test_plane_wave_values():
+    kv = oracle.pw_kvectors(7)
+    L = 10.0
+    r = np.array([1.25, 2.5, 5.0])
+    row = oracle.pw_row(kv, L, r)
+    # n = (0,0,1): phase = 2 pi * 5 / 10 = pi ; n = (0,1,0): pi/2 ; n = (1,0,0): pi/4
+    np.testing.assert_allclose(row, [1, -1, 0, 0, 1, math.sqrt(0.5), math.sqrt(0.5)], atol=1e-15)
+    # periodicity in the box
+    np.testing.assert_allclose(oracle.pw_row(kv, L, r + np.array([L, -2 * L, 3 * L])), row, atol=1e-13)
+
+
+# ---------------------------------------------------------- LU / inverse
+@pytest.mark.parametrize("n", [1, 2, 5, 64])
+def test_lu_matches_numpy(n):
+    a = inputs.dense_matrix(11 + n, n)
+    s, ld = oracle.slogdet(a)
+    s_np, ld_np = np.linalg.slogdet(a)
+    assert s == s_np
+    assert abs(ld - ld_np) < 1e-11 * max(1.0, abs(ld_np))
+    inv, s2, ld2 = oracle.inverse(a)
+    np.testing.assert_allclose(inv, np.linalg.inv(a), rtol=1e-9, atol=1e-11)
+    assert oracle.residual(inv, a) < 1e-11
+
+
+def test_lu_exact_small():
+    for seed in range(5):
+        m = nonsingular_integer_matrix(100 + 10 * seed, 5)
+        d = frac_det(m.astype(int).tolist())
+        s, ld = oracle.slogdet(m)
+        assert s == (1 if d > 0 else -1)
+        assert abs(ld - math.log(abs(float(d)))) < 1e-12
+        inv, _, _ = oracle.inverse(m)
+        exact = np.array([[float(x) for x in r] for r in frac_inverse(m.astype(int).tolist())])
+        np.testing.assert_allclose(inv, exact, rtol=1e-12, atol=1e-13)
+
+
+def test_lu_singular_detected():
+    a = inputs.dense_matrix(1, 6)
+    a[3] = a[1]
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.inverse(np.vstack([a[:5], np.zeros((1, 6))]))
+    s, ld = oracle.slogdet(np.zeros((3, 3)))
+    assert s == 0 and ld == -np.inf
+
+
+def test_lu_pivot_tie_break_same_result():
+    # equal-magnitude pivot candidates: the inverse and determinant are unique
+    a = np.array([[1.0, 2.0, 3.0], [-1.0, 0.5, 2.0], [1.0, -4.0, 1.0]])
+    inv, s, ld = oracle.inverse(a)
+    np.testing.assert_allclose(inv, np.linalg.inv(a), rtol=1e-13, atol=1e-14)
+    assert s == int(np.sign(np.linalg.det(a)))
+
+
+# --------------------------------------------------- eq. (1) and eq. (2)
+@pytest.mark.parametrize("n", [1, 2, 3, 6])
+def test_sm_exact_rational_chain(n):
+    """Ratio of eq. (1) equals the exact det(A_new)/det(A); after a chain of
+    accepted moves the eq. (2) inverse equals the exact rational inverse."""
+    a = nonsingular_integer_matrix(40 + n, n)
+    ainv, _, _ = oracle.inverse(a)
+    am = a.copy()
+    exact_m = a.astype(int).tolist()
+    det_prev = frac_det(exact_m)
+    order = inputs.electron_order(3 + n, n, 3 * n)
+    prop = inputs.rows(5 + n, 3 * n, n, kind="integer")
+    done = 0
+    for e, phi in zip(order, prop):
+        new_m = [r[:] for r in exact_m]
+        new_m[e] = [int(x) for x in phi]
+        det_new = frac_det(new_m)
+        r = oracle.sm_ratio(ainv, e, phi)
+        exact_r = det_new / det_prev
+        assert abs(r - float(exact_r)) <= 1e-11 * max(1.0, abs(float(exact_r))), (e, r, exact_r)
+        if det_new == 0:
+            continue  # a move to a singular matrix is never accepted
+        oracle.sm_accept(ainv, am, e, phi, r)
+        exact_m, det_prev = new_m, det_new
+        done += 1
+    assert done >= n
+    exact_inv = np.array([[float(x) for x in r] for r in frac_inverse(exact_m)])
+    np.testing.assert_allclose(ainv, exact_inv, rtol=1e-9, atol=1e-10)
+    np.testing.assert_array_equal(am, np.array(exact_m, dtype=float))
+
+
+def test_sm_special_cases():
+    n, L = 33, 10.0
+    kv = oracle.pw_kvectors(n)
+    pos = inputs.positions(1, 0, n, L)
+    a = oracle.pw_matrix(kv, L, pos)
+    ainv, _, _ = oracle.inverse(a)
+    # null move: the electron stays put -> R = 1
+    for e in (0, 7, n - 1):
+        assert abs(oracle.sm_ratio(ainv, e, a[e]) - 1.0) < 1e-11
+    # Pauli: moving e onto electron f's position makes two equal rows -> R = 0
+    for e, f in ((0, 1), (5, 30)):
+        assert abs(oracle.sm_ratio(ainv, e, a[f])) < 1e-11
+    # a row that is a combination of other rows -> 0 as well
+    assert abs(oracle.sm_ratio(ainv, 4, 2 * a[3] - a[9])) < 1e-10
+
+
+def test_sm_update_matches_fresh_inverse():
+    n = 64
+    a = inputs.dense_matrix(21, n)
+    ainv, _, _ = oracle.inverse(a)
+    rows = inputs.rows(22, 40, n)
+    order = inputs.electron_order(23, n, 40)
+    for e, phi in zip(order, rows):
+        phi = 0.7 * a[e] + 0.3 * phi  # keep the matrix well conditioned
+        r = oracle.sm_ratio(ainv, e, phi)
+        s0, l0 = np.linalg.slogdet(a)
+        a_new = a.copy(); a_new[e] = phi
+        s1, l1 = np.linalg.slogdet(a_new)
+        assert abs(r - s0 * s1 * math.exp(l1 - l0)) < 1e-10 * max(1, abs(r))
+        oracle.sm_accept(ainv, a, e, phi, r)
+    np.testing.assert_allclose(ainv, np.linalg.inv(a), rtol=1e-8, atol=1e-10)
+
+
+def test_planted_transpose_is_caught():
+    # A transposed inverse (a plausible slip) must fail the exact-ratio pin.
+    a = nonsingular_integer_matrix(77, 4)
+    ainv, _, _ = oracle.inverse(a)
+    phi = inputs.rows(78, 1, 4, kind="integer")[0]
+    m2 = a.astype(int).tolist(); m2[1] = [int(x) for x in phi]
+    exact = float(frac_det(m2) / frac_det(a.astype(int).tolist()))
+    assert abs(oracle.sm_ratio(ainv, 1, phi) - exact) < 1e-12
+    assert abs(oracle.sm_ratio(np.ascontiguousarray(ainv.T), 1, phi) - exact) > 1e-6
+
+
+# ------------------------------------------------- the Metropolis walker
+def test_walker_run_sweep_checks():
+    """Sec. III protocol: after each full sweep the running determinant equals
+    a direct calculation, and the maintained inverse still inverts A."""
+    n, L = 64, 10.0
+    pos = inputs.positions(1, 0, n, L)
+    t = oracle.walker_run(n, L, seed=1, walker=0, spin=0, sigma=0.5, pos=pos, sweeps=3)
+    # direct LU of the starting matrix
+    s0, l0 = np.linalg.slogdet(oracle.pw_matrix(oracle.pw_kvectors(n), L, pos))
+    for s in range(3):
+        assert t.sign_run[s] == t.sign_fresh[s]
+        assert abs(t.logdet_run[s] - t.logdet_fresh[s]) < 1e-9
+        assert t.residual[s] < 1e-9
+    # telescoping: sum of ln|R| over accepted moves = log|det| change
+    acc = t.accepted.astype(bool)
+    assert abs(np.sum(np.log(np.abs(t.ratio[acc]))) - (t.logdet_fresh[-1] - l0)) < 1e-9
+    # Metropolis rule u < R^2
+    np.testing.assert_array_equal(acc, t.u < t.ratio**2)
+    assert 0.3 < acc.mean() < 0.95
+    # final state is consistent: A(pos_out) inverted by ainv
+    a_end = oracle.pw_matrix(oracle.pw_kvectors(n), L, t.pos)
+    np.testing.assert_allclose(t.ainv, np.linalg.inv(a_end), rtol=1e-7, atol=1e-9)
+
+
+def test_walker_run_is_restartable():
+    # two runs of 1 sweep chained == one run of 2 sweeps (counter keyed on sweep)
+    n, L = 40, 10.0
+    pos = inputs.positions(9, 2, n, L)
+    full = oracle.walker_run(n, L, 9, 2, 0, 0.4, pos, sweeps=2, residual=False, fresh=False)
+    a = oracle.walker_run(n, L, 9, 2, 0, 0.4, pos, sweeps=1, residual=False, fresh=False)
+    b = oracle.walker_run(n, L, 9, 2, 0, 0.4, a.pos, sweeps=1, first_sweep=1, residual=False, fresh=False)
+    np.testing.assert_array_equal(full.accepted, np.concatenate([a.accepted, b.accepted]))
+    np.testing.assert_allclose(full.ratio[n:], b.ratio, rtol=1e-9, atol=1e-12)
+
+
+def test_walkers_run_matches_single():
+    n, L = 32, 10.0
+    pos = np.stack([inputs.positions(5, w, n, L) for w in range(3)])
+    ratio, acc, ld, pos_out, nacc, threads = oracle.walkers_run(n, L, [5, 5, 5], [0, 1, 2], [0, 1, 0], 0.3, pos, 2)
+    for w in range(3):
+        t = oracle.walker_run(n, L, 5, w, [0, 1, 0][w], 0.3, pos[w], 2, residual=False, fresh=False)
+        np.testing.assert_array_equal(acc[w], t.accepted)
+        np.testing.assert_array_equal(ratio[w], t.ratio)
+        np.testing.assert_array_equal(ld[w], t.logdet_run)
+    assert threads >= 1
