@@ -1,0 +1,229 @@
+/*
+ * dsu.h -- C ABI of libdsu, the MI355X (gfx950) delayed Slater-determinant
+ * update library (McDaniel, D'Azevedo, Li, Wong, Kent, arXiv:1708.00744).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrix convention: the Slater matrix A has one ROW per electron,
+ *    A[i][j] = phi_j(r_i), FP64, row-major.  This is the transpose of the
+ *    paper's layout (Sec. I puts electrons in columns); determinants and
+ *    ratios are identical.  Moving electron e replaces row e of A.
+ *  - The library keeps the transposed inverse BT = (A^{-1})^T on the device,
+ *    so column e of A^{-1} (needed by the ratio, eq. (1)) is a contiguous row.
+ *  - Every call returns DSU_OK (0) or a negative status; on error the object
+ *    is unchanged and dsu_last_error() returns a thread-local message.
+ *    No call throws across the ABI.
+ *  - Ownership: the caller keeps every array it passes; the library copies
+ *    what it needs during the call.  All device memory behind a handle is
+ *    owned by the library and released by the matching *_destroy.
+ *  - Pointers named *_host are host memory; *_dev are device memory.
+ *  - Calls on one handle must be serialised by the caller; distinct handles
+ *    may be used from distinct threads.
+ *  - Streams: `hip_stream` is a hipStream_t (e.g. torch's
+ *    current_stream().cuda_stream) or NULL, in which case the handle creates
+ *    its own non-blocking stream of default priority.  Work is stream
+ *    ordered; calls that return numbers to the host synchronise that stream.
+ */
+#ifndef DSU_H
+#define DSU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------- status codes */
+enum {
+    DSU_OK = 0,
+    DSU_EINVAL = -1,     /* bad argument (size, index, pointer, enum)          */
+    DSU_ENOMEM = -2,     /* device or host allocation failed                    */
+    DSU_ESINGULAR = -3,  /* matrix singular, or a zero / non-finite ratio     */
+    DSU_ESTATE = -4,     /* call not valid in the handle's current state        */
+    DSU_EDEVICE = -5,    /* a HIP runtime call failed                           */
+    DSU_EBUDGET = -6     /* request does not fit the pool's device-memory budget */
+};
+
+/* Precision forms. */
+enum {
+    DSU_FP64 = 0,        /* inverse, ratios and flushes in FP64                 */
+    DSU_FP32_MIXED = 1   /* BT, ratios, flushes in FP32 (FP32 accumulation);
+                            A, log-determinant, K x K bordering and every
+                            recompute of the inverse in FP64                  */
+};
+
+/* What counts toward the delay K (Sec. II, handling of rejected moves). */
+enum {
+    DSU_FLUSH_K_ACCEPTED = 0, /* flush after K accepted moves                   */
+    DSU_FLUSH_K_PROPOSED = 1  /* flush after K proposals; a rejected move takes
+                                 a slot but contributes nothing (a zero-rank
+                                 term), so every flush is uniform work          */
+};
+
+/* Flush kernel selection for the single-walker form. */
+enum {
+    DSU_FLUSH_AUTO = 0,  /* VALU for k <= 4, matrix cores above                  */
+    DSU_FLUSH_VALU = 1,  /* vector-ALU rank-k kernel                             */
+    DSU_FLUSH_MFMA = 2   /* fused matrix-core (MFMA) rank-k kernel               */
+};
+
+#define DSU_MAX_K 256    /* largest supported delay */
+
+const char *dsu_last_error(void);
+/* Library version (major*10000 + minor*100 + patch). */
+int dsu_version(void);
+
+/* Bytes of device memory one determinant of size n needs in the batched
+ * form (inverse, delayed buffers, window scratch), excluding the shared
+ * recompute workspace.  0 on a bad argument. */
+size_t dsu_footprint_bytes(int32_t n, int32_t k_delay, int32_t precision);
+
+/* ======================================================================
+ * Single walker, host-driven: the paper's procedure one call per step.
+ * ====================================================================== */
+typedef struct dsu_walker dsu_walker;
+
+/* Create a walker from the Slater matrix `slater_host` (n*n FP64, row i =
+ * electron i).  Computes A^{-1} and log|det A| in FP64 on the device
+ * (blocked Gauss-Jordan with partial pivoting: the explicit route of
+ * Sec. I).  k_delay in [1, DSU_MAX_K]; k_delay = 1 is plain Sherman-Morrison,
+ * eq. (2).  DSU_ESINGULAR if A is singular. */
+int dsu_walker_create(int32_t n, int32_t k_delay, int32_t precision, int32_t policy,
+                      const double *slater_host, void *hip_stream, dsu_walker **out);
+int dsu_walker_destroy(dsu_walker *w);
+
+/* Ratio det(A_new)/det(A) for replacing row `electron` by `phi_host` (n FP64
+ * values): eq. (1) against the stale inverse, corrected for the k pending
+ * accepted moves by the generalised lemma, eq. (3) (look-ahead,
+ * R = r0 - p^T C_k^{-1} q).  The proposal stays pending until dsu_accept or
+ * dsu_reject; a new proposal replaces it.  If `electron` already has a pending
+ * accepted move, the pending moves are flushed first.  Synchronises. */
+int dsu_propose_ratio(dsu_walker *w, int32_t electron, const double *phi_host, double *ratio_out);
+/* Same, with the row already on the device in the walker's precision
+ * (double for DSU_FP64, float for DSU_FP32_MIXED), n values. */
+int dsu_propose_ratio_dev(dsu_walker *w, int32_t electron, const void *phi_dev, double *ratio_out);
+
+/* Accept the pending proposal: queue it in the delayed buffer (Sec. II),
+ * border the K x K inverse, update A's row and the running log-determinant.
+ * When the delay limit is reached the queued moves are applied en bloc by
+ * the Woodbury formula, eq. (4).  DSU_ESTATE without a pending proposal;
+ * DSU_ESINGULAR (walker unchanged) if the proposal's ratio is 0 or not finite. */
+int dsu_accept(dsu_walker *w);
+/* Drop the pending proposal.  Under DSU_FLUSH_K_PROPOSED it still takes a
+ * slot toward K. */
+int dsu_reject(dsu_walker *w);
+/* Apply the k pending moves now (eq. (4)); no-op when k = 0. */
+int dsu_flush(dsu_walker *w);
+/* Recompute A^{-1} from scratch in FP64 (Sec. III's direct calculation).  If
+ * `slater_host_or_null` is given it replaces A first.  Pending moves are
+ * already part of A, so the delayed buffer is cleared.  Writes the fresh
+ * log|det| and sign when the pointers are non-NULL; `drift_out` (optional)
+ * receives running-minus-fresh log|det| before re-basing. */
+int dsu_recompute_inverse(dsu_walker *w, const double *slater_host_or_null, double *logdet_out,
+                          int32_t *sign_out, double *drift_out);
+/* Flush, then copy A^{-1} (natural layout, n*n FP64) to the host. */
+int dsu_get_inverse(dsu_walker *w, double *out_host);
+/* Running log|det A| and its sign (FP64, maintained from accepted ratios). */
+int dsu_get_logdet(dsu_walker *w, double *logdet, int32_t *sign);
+/* Number of accepted moves waiting in the delayed buffer. */
+int dsu_walker_pending(dsu_walker *w, int32_t *k_out);
+/* Choose the flush kernel (DSU_FLUSH_*) -- for the VALU/MFMA crossover study. */
+int dsu_walker_set_flush_kernel(dsu_walker *w, int32_t mode);
+
+/* ======================================================================
+ * Batched form: many walker determinants of one size n, proposals drawn on
+ * the device, lock-step windows of K proposals per determinant.
+ * ====================================================================== */
+typedef struct dsu_batch dsu_batch;
+
+/* Create a batch of `walkers` walkers with `spins` (1 or 2) determinants of
+ * size n each.  Per walker: RNG key (seeds[w], walker_ids[w]) -- Philox4x64-10
+ * counter = (sweep, spin*n + electron, block, 0) --, Gaussian step sigma[w],
+ * and initial positions positions_host[w][spin][n][3] in the periodic cubic
+ * box of side box_L (orbitals: plane waves cos/sin(k.r), k = 2 pi n / L, by
+ * shells of |n|^2).  Builds each A and inverts it in FP64 on the device.
+ * recompute_every: FP64 recompute of every inverse after that many sweeps of
+ * a walker (0 = never).  Policy is DSU_FLUSH_K_PROPOSED (lock-step windows). */
+int dsu_batch_create(int32_t walkers, int32_t n, int32_t spins, int32_t k_delay, int32_t precision,
+                     double box_L, const uint64_t *seeds, const uint64_t *walker_ids, const double *sigma,
+                     const double *positions_host, int32_t recompute_every, void *hip_stream, dsu_batch **out);
+int dsu_batch_destroy(dsu_batch *b);
+/* Run `sweeps` Monte Carlo sweeps on every walker: per sweep and determinant,
+ * electrons 0..n-1 in windows of K: propose, look-ahead ratio (eq. (3)),
+ * Metropolis decision u < R^2 (or accept all with force_accept, the paper's
+ * 100% acceptance test mode), then the en-bloc Woodbury update (eq. (4)).
+ * Stream ordered: returns once the work is enqueued; dsu_batch_sync waits. */
+int dsu_batch_sweep(dsu_batch *b, int32_t sweeps, int32_t force_accept);
+int dsu_batch_sync(dsu_batch *b);
+/* FP64 recompute of every inverse now; drift_out (optional, walkers*spins)
+ * receives running-minus-fresh log|det| before re-basing. */
+int dsu_batch_recompute(dsu_batch *b, double *drift_out);
+/* Per determinant d = w*spins + s: running log|det|, sign, accepted moves,
+ * completed sweeps.  Any pointer may be NULL.  Synchronises. */
+int dsu_batch_stats(dsu_batch *b, double *logdet, int32_t *sign, int64_t *accepted, int64_t *sweeps_done);
+/* Current positions of determinant d (n*3 FP64). */
+int dsu_batch_get_positions(dsu_batch *b, int32_t det, double *out_host);
+/* A^{-1} of determinant d, natural layout (n*n FP64, from the device copy). */
+int dsu_batch_get_inverse(dsu_batch *b, int32_t det, double *out_host);
+/* Record per-move ratios and decisions for the next `sweeps` sweeps
+ * (0 disables).  dsu_batch_get_trace copies determinant d's record:
+ * ratio[sweeps*n] (FP64) and accepted[sweeps*n]. */
+int dsu_batch_set_trace(dsu_batch *b, int32_t sweeps);
+int dsu_batch_get_trace(dsu_batch *b, int32_t det, double *ratio_host, uint8_t *accepted_host);
+/* Kernel timing: when enabled, HIP events bracket every launch on the
+ * batch's stream; dsu_batch_kernel_time returns (count, total ms) for one
+ * phase: 0 proposals, 1 look-ahead products, 2 decisions, 3 flush,
+ * 4 recompute. */
+int dsu_batch_set_timing(dsu_batch *b, int32_t enable);
+int dsu_batch_kernel_time(dsu_batch *b, int32_t phase, int64_t *launches, double *total_ms);
+/* Capture one sweep into a hipGraph and replay it for dsu_batch_sweep
+ * (enable = 1) or launch kernels directly (0). */
+int dsu_batch_use_graph(dsu_batch *b, int32_t enable);
+
+/* ======================================================================
+ * Serving: a pool of walkers of mixed n admitted by a device-memory budget,
+ * continuously batched (one lock-step batch per n, on its own stream).
+ * ====================================================================== */
+typedef struct dsu_server dsu_server;
+
+typedef struct {
+    uint64_t request_id;
+    int32_t n;              /* determinant size per spin                          */
+    int32_t spins;          /* 1 or 2 determinants per walker                     */
+    uint64_t seed;          /* RNG key word 0 (request seed); word 1 = request_id */
+    double sigma;           /* Gaussian step                                      */
+    int32_t sweeps;         /* sweeps to run                                      */
+    double arrival_s;       /* arrival time, seconds after dsu_server_run starts   */
+    const double *positions;/* spins*n*3 FP64 initial positions (host)           */
+} dsu_request;
+
+typedef struct {
+    uint64_t request_id;
+    int32_t status;         /* DSU_OK, or DSU_EBUDGET if it can never fit         */
+    int32_t sweeps_done;
+    double admit_s;         /* time admitted (s after start)                      */
+    double finish_s;        /* time its last sweep completed                      */
+    double logdet[2];       /* per spin, running log|det|                         */
+    int32_t sign[2];
+    int64_t accepted;       /* accepted moves over all spins and sweeps           */
+} dsu_result;
+
+/* budget_bytes: device memory the pool may use for walker state; requests
+ * wait until enough is free.  recompute_every as in dsu_batch_create. */
+int dsu_server_create(int32_t k_delay, int32_t precision, double box_L, size_t budget_bytes,
+                      int32_t recompute_every, dsu_server **out);
+int dsu_server_destroy(dsu_server *s);
+/* Serve `count` requests in arrival order (wall clock): admit by budget,
+ * sweep all resident walkers (one batch per n, concurrently), retire
+ * finished ones.  Fills results[count].  sweep_latency_ms (optional,
+ * capacity latency_cap) receives every per-walker sweep latency: the time
+ * between consecutive sweep completions of a walker (the first measured from
+ * its admission); *latency_count is the number written. */
+int dsu_server_run(dsu_server *s, const dsu_request *reqs, int32_t count, dsu_result *results,
+                   double *sweep_latency_ms, int64_t latency_cap, int64_t *latency_count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSU_H */

@@ -1,0 +1,178 @@
+// dsu_internal.hpp -- shared declarations of libdsu's HIP kernels and host code.
+//
+// Layout conventions (all device buffers of one determinant):
+//   np  = n rounded up to a multiple of 64; every n x n array is stored np x np,
+//         row-major, zero padded (the padded rows/columns of BT stay zero through
+//         every update, see the flush kernel).
+//   kp  = delay K rounded up to a multiple of 16 (one MFMA tile).
+//   BT  = (A^{-1})^T, np x np, precision T (double or float).
+//   U   = the window's proposed orbital rows, kp x np, T.
+//   Vg  = stale BT rows of the window's electrons, kp x np, T.
+//   Cfl = zero-embedded inverse of the window's C matrix (eq. (3)), kp x kp, FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsu {
+
+constexpr int kRowBlock = 64;    // rows of BT per flush workgroup
+constexpr int kThreads = 256;    // 4 wave64 per workgroup
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// ----------------------------------------------------------------- MFMA
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mma;
+template <> struct Mma<float> {
+    typedef f32x4 acc_t;
+    // v_mfma_f32_16x16x4_f32: D(16x16) += A(16x4) B(4x16); lane l supplies
+    // A[l%16][l/16] and B[l/16][l%16]; D[4*(l/16)+i][l%16] lands in acc[i].
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mma<double> {
+    typedef f64x4 acc_t;
+    // v_mfma_f64_16x16x4_f64: same operand and result layout as above.
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+// --------------------------------------------------- descriptors (device)
+// One rank-k update target: BT <- BT - ((BT U^T - E) C^T) Vg   (eq. (4),
+// transposed and row-local).  idx[j] = electron of slot j (-1 = unused).
+template <typename T> struct FlushDesc {
+    T *bt;
+    const T *u;
+    const T *vg;
+    const double *cinv;
+    const int *idx;
+    int ldc;
+};
+
+// One explicit rank-k update M <- M - W Q  (Gauss-Jordan panel update).
+struct RankDesc {
+    double *m;        // np x np
+    const double *w;  // np x kp
+    const double *q;  // kp x np
+};
+
+// Per-determinant running state of the batched form (device memory).
+struct DetState {
+    double logdet;
+    int sign;
+    int bad;              // count of zero / non-finite ratios met
+    long long accepted;
+    long long sweep;      // completed sweeps (RNG counter word 0)
+    long long trace_pos;  // next trace slot
+};
+
+// One determinant of the batched form.
+template <typename T> struct DetDesc {
+    T *bt;           // np x np
+    T *u;            // kp x np
+    T *vg;           // kp x np
+    T *gpart;        // nsplit x kp x kp (G^T partial sums: gpart[b][a] = BT[e0+b,:].U[a,:])
+    double *cfl;     // kp x kp
+    double *cwork;   // kp x (kp+1) when the bordered inverse does not fit LDS
+    double *gwork;   // kp x (kp+1) when G does not fit LDS
+    double *prop;    // kp x 4 : proposed position (x, y, z) and Metropolis uniform
+    double *pos;     // n x 3
+    int *idx;        // kp
+    DetState *st;
+    double *trace_r; // optional per-move ratio record
+    uint8_t *trace_a;
+    long long trace_cap;
+    uint64_t seed, wid;
+    double sigma;
+    int spin;
+};
+
+// ------------------------------------------------------- launchers (host)
+// All launchers return hipSuccess or the launch error.
+
+// Flush (eq. (4)) of `ndesc` determinants with `kslots` delayed slots
+// (<= kp of the descriptors' buffers); mode 0 = MFMA fused, 1 = VALU.
+template <typename T>
+hipError_t launch_flush(const FlushDesc<T> *descs_dev, int ndesc, int n, int np, int kslots, int mode,
+                        hipStream_t s);
+// M <- M - W Q for `ndesc` matrices, rank kslots (<= 64).
+hipError_t launch_rank_update(const RankDesc *descs_dev, int ndesc, int np, int kslots, hipStream_t s);
+
+// FP64 inversion by blocked Gauss-Jordan with partial pivoting.
+struct GjDesc {
+    double *m;        // np x np work (in: A^T padded with identity; out: inverse scrambled)
+    double *panel;    // np x nb
+    double *w;        // np x nb
+    double *q;        // nb x np
+    int *piv;         // n pivots
+    int *perm;        // np final column permutation
+    double *logdet;   // out
+    int *sign;        // out
+    int *status;      // out: 0 or -3 singular
+};
+hipError_t launch_gj_invert(const GjDesc *descs_dev, const RankDesc *rank_dev, int ndesc, int n, int np,
+                            int nb, hipStream_t s);
+// BT[i][j] = T(M[i][perm[j]]) for i, j < n, zero padding elsewhere.
+template <typename T>
+hipError_t launch_cast_perm(const GjDesc *gj_dev, T *const *bt_dev, int ndesc, int n, int np, hipStream_t s);
+// M = A^T (A row-major n x n, padded with identity to np).
+hipError_t launch_load_transpose(const double *const *a_dev, double *const *m_dev, int ndesc, int n, int np,
+                                 int lda, hipStream_t s);
+// M = A^T with A built from plane waves at the positions.
+hipError_t launch_build_pw_transpose(const double *const *pos_dev, double *const *m_dev, int ndesc, int n,
+                                     int np, const int4 *kvec, double twopi_over_l, hipStream_t s);
+// out[i][j] = BT[j][i] (natural A^{-1}, FP64, n x n).
+template <typename T>
+hipError_t launch_untranspose(const T *bt, double *out, int n, int np, hipStream_t s);
+
+// Single-walker device state (one walker, precision T behind the void*).
+#define DSU_KMAX_LDS 256
+struct WalkerDev {
+    void *bt;          // np x np, T
+    void *u;           // kp x np, T
+    void *vg;          // kp x np, T
+    double *a;         // np x np, FP64 Slater matrix
+    void *phi;         // np, T: pending proposal row
+    double *phi64;     // np, FP64 copy of the proposal row
+    double *cinv;      // kp x (kp+1): C_k^{-1} in pending order
+    double *dots;      // 1 + 2 kp: r0, p[0..k), q[0..k)
+    double *t;         // kp: C_k^{-1} q
+    double *ratio;     // device copy of R
+    double *ratio_host;// pinned host memory (mapped): R for the caller
+    int *idx;          // kp pending electrons
+    unsigned *counter; // blocks finished (last-block reduction)
+    int ldc;           // kp + 1
+};
+
+// Single-walker look-ahead ratio and accept (bordering).
+template <typename T>
+hipError_t launch_walker_propose(WalkerDev *wd, int n, int np, int k, int e, hipStream_t s);
+template <typename T>
+hipError_t launch_walker_accept(WalkerDev *wd, int n, int np, int k, int kp, int e, hipStream_t s);
+// Row copy into a padded device row: mode 0 FP64->FP64, 1 FP64->float, 2 float->FP64.
+hipError_t launch_row_to(const double *src, void *dst, int mode, int n, int np, hipStream_t s);
+
+// Batched window kernels.
+template <typename T>
+hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int kp, int e0, int kw,
+                              const int4 *kvec, double twopi_over_l, double box_l, hipStream_t s);
+template <typename T>
+hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int n, int np, int kp, int e0, int kw, int nsplit,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int n, int kp, int e0, int kw, int nsplit,
+                                int force_accept, int last_window, hipStream_t s);
+template <typename T>
+hipError_t launch_window_flush(const DetDesc<T> *d, const FlushDesc<T> *fd, int ndesc, int n, int np, int kw,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_reset_state(const DetDesc<T> *d, const GjDesc *gj, double *drift, int ndesc, hipStream_t s);
+
+// Host-side plane-wave table: orbitals by shells of |n|^2 (see kvec.cpp).
+int build_kvectors(int n, int4 *out /* n entries: nx, ny, nz, kind */);
+
+}  // namespace dsu

@@ -1,0 +1,383 @@
+// k_batch.hip -- kernels of the batched (device-driven) form.
+//
+// A window is K consecutive proposals of one determinant (electrons e0..e0+kw-1
+// of the current sweep).  Every electron moves at most once per window, so all
+// kw proposed rows are known before any decision is made: a proposal only
+// depends on its electron's position at the start of the window and on the
+// random stream.  The look-ahead quantities of eq. (3) for the whole window
+// are then entries of one small product,
+//     G[a][b] = phi_a . BT[e0 + b, :]        (kw x kw, on matrix cores)
+// and the sequential part -- the Metropolis decisions in proposal order with
+// the bordered inverse of C -- needs only G:
+//     for accepted set S:  R_a = G[a][a] - G[a][S] C_S^{-1} G[S][a]
+// which equals det(A_new)/det(A) of the one-move-at-a-time method (Sec. II).
+// Rejected proposals keep their slot (uniform work, Sec. II's second variant)
+// but their rows and columns of the flush's C^{-1} are zero.
+#include "dsu_internal.hpp"
+#include "tiles.hpp"
+
+namespace dsu {
+
+// ------------------------------------------------------------ random stream
+// Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64 x 64 -> 128-bit
+// products; the high halves are xor-ed with the other two counter words and
+// the round key; the key advances by the Weyl increments after each round.
+struct P4 { uint64_t w[4]; };
+
+__device__ __forceinline__ P4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                            uint64_t k1) {
+    const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+    const uint64_t inc0 = 0x9E3779B97F4A7C15ull, inc1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo_a = m0 * c0, hi_a = __umul64hi(m0, c0);
+        const uint64_t lo_b = m1 * c2, hi_b = __umul64hi(m1, c2);
+        const uint64_t n0 = hi_b ^ c1 ^ k0, n2 = hi_a ^ c3 ^ k1;
+        c0 = n0; c1 = lo_b; c2 = n2; c3 = lo_a;
+        k0 += inc0; k1 += inc1;
+    }
+    return P4{{c0, c1, c2, c3}};
+}
+
+__device__ __forceinline__ double unit53(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+// Gaussian step and Metropolis uniform of one proposal.  Box-Muller (1958) on
+// the first pair (x, y) and the second pair's cosine branch (z); uniform from
+// block 1.  Counter = (sweep, spin*n + e, block, 0); key = (seed, walker).
+__device__ __forceinline__ void move_draw(uint64_t seed, uint64_t wid, uint64_t sweep, uint64_t slot, double g[3],
+                                          double &u) {
+#pragma clang fp contract(off)
+    const P4 a = philox4x64_10(sweep, slot, 0, 0, seed, wid);
+    const P4 b = philox4x64_10(sweep, slot, 1, 0, seed, wid);
+    const double twopi = 6.283185307179586476925286766559;
+    const double r1 = sqrt(-2.0 * log(1.0 - unit53(a.w[0])));
+    const double t1 = twopi * unit53(a.w[1]);
+    const double r2 = sqrt(-2.0 * log(1.0 - unit53(a.w[2])));
+    const double t2 = twopi * unit53(a.w[3]);
+    g[0] = r1 * cos(t1);
+    g[1] = r1 * sin(t1);
+    g[2] = r2 * cos(t2);
+    u = unit53(b.w[0]);
+}
+
+// Plane-wave orbital: 1, cos(k.r) or sin(k.r), k = (2 pi / L)(nx, ny, nz).
+__device__ __forceinline__ double pw_orbital(int4 kv, double twopi_l, double x, double y, double z) {
+#pragma clang fp contract(off)
+    if (kv.w == 0) return 1.0;
+    const double t = ((double)kv.x * x + (double)kv.y * y) + (double)kv.z * z;
+    const double ph = twopi_l * t;
+    return kv.w == 1 ? cos(ph) : sin(ph);
+}
+
+// ------------------------------------------------------- window proposals
+// grid (ndesc, nsplit): every block draws the window's kw moves (cheap) and
+// fills its column range of U (proposed orbital rows, zero past kw and n) and
+// Vg (the stale BT rows e0..e0+kw-1, zero past kw).  Block 0 of a determinant
+// also stores the proposals for the decision kernel.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__restrict__ descs, int n, int np, int kp,
+                                                          int e0, int kw, const int4 *__restrict__ kvec,
+                                                          double twopi_l) {
+#pragma clang fp contract(off)
+    __shared__ double s_r[DSU_KMAX_LDS][3];
+    const DetDesc<T> d = descs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const long long sweep = d.st->sweep;
+    for (int a = tid; a < kw; a += kThreads) {
+        double g[3], u;
+        const int e = e0 + a;
+        move_draw(d.seed, d.wid, (uint64_t)sweep, (uint64_t)d.spin * (uint64_t)n + (uint64_t)e, g, u);
+        const double x = d.pos[3 * e + 0] + d.sigma * g[0];
+        const double y = d.pos[3 * e + 1] + d.sigma * g[1];
+        const double z = d.pos[3 * e + 2] + d.sigma * g[2];
+        s_r[a][0] = x; s_r[a][1] = y; s_r[a][2] = z;
+        if (blockIdx.y == 0) {
+            d.prop[4 * a + 0] = x; d.prop[4 * a + 1] = y; d.prop[4 * a + 2] = z; d.prop[4 * a + 3] = u;
+        }
+    }
+    __syncthreads();
+    const int cols = np / gridDim.y;
+    const int c_begin = blockIdx.y * cols;
+    for (int v = tid; v < kp * cols; v += kThreads) {
+        const int a = v / cols, c = c_begin + v % cols;
+        T val = T(0), vgv = T(0);
+        if (a < kw) {
+            if (c < n) val = T(pw_orbital(kvec[c], twopi_l, s_r[a][0], s_r[a][1], s_r[a][2]));
+            vgv = d.bt[(size_t)(e0 + a) * np + c];
+        }
+        d.u[(size_t)a * np + c] = val;
+        d.vg[(size_t)a * np + c] = vgv;
+    }
+}
+
+template <typename T>
+hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int kp, int e0, int kw,
+                              const int4 *kvec, double twopi_over_l, double box_l, hipStream_t s) {
+    (void)box_l;
+    int nsplit = np / 256;
+    if (nsplit < 1) nsplit = 1;
+    while (np % nsplit) --nsplit;
+    hipLaunchKernelGGL((k_window_rows<T>), dim3(ndesc, nsplit), dim3(kThreads), 0, s, d, n, np, kp, e0, kw, kvec,
+                       twopi_over_l);
+    return hipGetLastError();
+}
+template hipError_t launch_window_rows<float>(const DetDesc<float> *, int, int, int, int, int, int, const int4 *,
+                                              double, double, hipStream_t);
+template hipError_t launch_window_rows<double>(const DetDesc<double> *, int, int, int, int, int, int, const int4 *,
+                                               double, double, hipStream_t);
+
+// ---------------------------------------------- window look-ahead products
+// gpart[s][b][a] = sum over the s-th column range of BT[e0+b, c] * U[a, c].
+// grid: ndesc * nsplit * nrb, nrb = 64-row blocks covering kp rows.  Same
+// matrix-core tiling as the flush's first product (64 rows x KP columns).
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_window_g(const DetDesc<T> *__restrict__ descs, int np, int kp, int e0,
+                                                       int nsplit, int nrb) {
+    constexpr int LDU = 128 / (int)sizeof(T) + 16 / (int)sizeof(T);
+    __shared__ __attribute__((aligned(16))) T lds[KP * LDU];
+    const int b = blockIdx.x;
+    const int d = b / (nsplit * nrb), rem = b % (nsplit * nrb);
+    const int s = rem / nrb, rb = rem % nrb;
+    const DetDesc<T> dd = descs[d];
+    const int cols = np / nsplit;
+    const int row0 = e0 + rb * 64;
+    int rows_valid = np - row0;
+    rows_valid = rows_valid < 0 ? 0 : (rows_valid > 64 ? 64 : rows_valid);
+    typename Mma<T>::acc_t acc[KP / 16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    rowblock_times_ut<T, KP>(dd.bt + (size_t)row0 * np, np, rows_valid, dd.u, np, s * cols, (s + 1) * cols, lds,
+                             acc);
+    T *out = dd.gpart + (size_t)s * kp * kp;
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int br = rb * 64 + 16 * wave + 4 * (lane >> 4) + i;
+            const int ac = 16 * t + (lane & 15);
+            if (br < kp) out[(size_t)br * kp + ac] = acc[t][i];
+        }
+}
+
+template <typename T>
+hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int n, int np, int kp, int e0, int kw, int nsplit,
+                           hipStream_t s) {
+    (void)n;
+    (void)kw;
+    const int nrb = kp > 64 ? kp / 64 : 1;
+    const dim3 grid(ndesc * nsplit * nrb);
+#define DSU_G(KPV)                                                                                          \
+    if (kp == KPV) {                                                                                        \
+        hipLaunchKernelGGL((k_window_g<T, KPV>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);    \
+        return hipGetLastError();                                                                           \
+    }
+    DSU_G(16) DSU_G(32) DSU_G(64) DSU_G(128) DSU_G(256)
+#undef DSU_G
+    return hipErrorInvalidValue;
+}
+template hipError_t launch_window_g<float>(const DetDesc<float> *, int, int, int, int, int, int, int, hipStream_t);
+template hipError_t launch_window_g<double>(const DetDesc<double> *, int, int, int, int, int, int, int, hipStream_t);
+
+// ------------------------------------------------------ window decisions
+// One workgroup (max(64, KP) threads) per determinant.  Thread i owns row i
+// of the bordered inverse C_S^{-1} (S = accepted proposals so far).
+template <int KP> struct DecideCfg {
+    static constexpr int threads = KP < 64 ? 64 : KP;
+    static constexpr int ld = KP + 1;
+    static constexpr bool g_lds = KP <= 64;
+    static constexpr bool c_lds = KP <= 128;
+    static constexpr int lds_g = g_lds ? KP * ld : 1;
+    static constexpr int lds_c = c_lds ? KP * ld : 1;
+};
+
+template <typename T, int KP>
+__global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const DetDesc<T> *__restrict__ descs,
+                                                                          int n, int kp, int e0, int kw, int nsplit,
+                                                                          int force_accept, int last_window) {
+    typedef DecideCfg<KP> C;
+    constexpr int LD = C::ld, NT = C::threads;
+    __shared__ double s_g[C::lds_g];
+    __shared__ double s_c[C::lds_c];
+    __shared__ double s_q[KP], s_p[KP], s_t[KP], s_b[KP], s_u[KP], s_red[NT / 64];
+    __shared__ int s_acc[KP], s_pos[KP];
+    __shared__ double s_ratio[KP];
+    __shared__ int s_ok[KP];
+    const DetDesc<T> d = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *G = C::g_lds ? s_g : d.gwork;
+    double *Cm = C::c_lds ? s_c : d.cwork;
+
+    // G[a][b] = sum_s gpart[s][b][a]  (fixed summation order: deterministic)
+    for (int v = tid; v < kw * kw; v += NT) {
+        const int a = v / kw, b = v % kw;
+        double acc = 0.0;
+        for (int s = 0; s < nsplit; ++s) acc += (double)d.gpart[((size_t)s * kp + b) * kp + a];
+        G[a * LD + b] = acc;
+    }
+    for (int a = tid; a < KP; a += NT) {
+        s_u[a] = a < kw ? d.prop[4 * a + 3] : 0.0;
+        s_pos[a] = -1;
+    }
+    __syncthreads();
+
+    int m = 0;
+    double logdet = 0.0;
+    int sgn = 1, bad = 0;
+    for (int a = 0; a < kw; ++a) {
+        if (tid < m) {
+            s_q[tid] = G[s_acc[tid] * LD + a];
+            s_p[tid] = G[a * LD + s_acc[tid]];
+        }
+        __syncthreads();
+        double part = 0.0;
+        if (tid < m) {
+            double t = 0.0, bb = 0.0;
+            const double *crow = Cm + tid * LD;
+            for (int j = 0; j < m; ++j) {
+                t += crow[j] * s_q[j];
+                bb += s_p[j] * Cm[j * LD + tid];
+            }
+            s_t[tid] = t;
+            s_b[tid] = bb;
+            part = s_p[tid] * t;
+        }
+        // block reduction of p.t
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        if (NT > 64) {
+            if (lane == 0) s_red[wave] = part;
+            __syncthreads();
+            part = 0.0;
+            for (int q = 0; q < NT / 64; ++q) part += s_red[q];
+        } else {
+            __syncthreads();
+        }
+        const double r = G[a * LD + a] - part;
+        const bool finite_nz = (r == r) && (r != 0.0) && (fabs(r) <= 1.7976931348623157e308);
+        const bool ok = finite_nz && (force_accept || s_u[a] < r * r);
+        if (!finite_nz) ++bad;
+        if (tid == 0) { s_ratio[a] = r; s_ok[a] = ok; }
+        if (ok) {
+            const double rinv = 1.0 / r;
+            if (tid < m) {
+                double *crow = Cm + tid * LD;
+                const double ti = s_t[tid] * rinv;
+                for (int j = 0; j < m; ++j) crow[j] += ti * s_b[j];
+                crow[m] = -ti;
+            } else if (tid == m) {
+                double *crow = Cm + m * LD;
+                for (int j = 0; j < m; ++j) crow[j] = -s_b[j] * rinv;
+                crow[m] = rinv;
+                s_acc[m] = a;
+                s_pos[a] = m;
+            }
+            logdet += log(fabs(r));
+            if (r < 0.0) sgn = -sgn;
+            ++m;
+        }
+        __syncthreads();
+    }
+
+    // zero-embedded C^{-1} for the flush, electrons, positions, state, trace
+    for (int v = tid; v < kp * kp; v += NT) {
+        const int i = v / kp, j = v % kp;
+        const int pi = i < KP ? s_pos[i] : -1, pj = j < KP ? s_pos[j] : -1;
+        d.cfl[v] = (pi >= 0 && pj >= 0) ? Cm[pi * LD + pj] : 0.0;
+    }
+    for (int a = tid; a < kp; a += NT) d.idx[a] = a < kw ? e0 + a : -1;
+    for (int v = tid; v < kw * 3; v += NT) {
+        const int a = v / 3, c = v % 3;
+        if (s_ok[a]) d.pos[3 * (e0 + a) + c] = d.prop[4 * a + c];
+    }
+    if (tid == 0) {
+        DetState *st = d.st;
+        if (d.trace_r) {
+            const long long p0 = st->trace_pos;
+            for (int a = 0; a < kw; ++a)
+                if (p0 + a < d.trace_cap) {
+                    d.trace_r[p0 + a] = s_ratio[a];
+                    d.trace_a[p0 + a] = (uint8_t)s_ok[a];
+                }
+            st->trace_pos = p0 + kw;
+        }
+        st->logdet += logdet;
+        st->sign *= sgn;
+        st->accepted += m;
+        st->bad += bad;
+        if (last_window) st->sweep += 1;
+    }
+}
+
+template <typename T>
+hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int n, int kp, int e0, int kw, int nsplit,
+                                int force_accept, int last_window, hipStream_t s) {
+#define DSU_D(KPV)                                                                                                \
+    if (kp == KPV) {                                                                                              \
+        hipLaunchKernelGGL((k_window_decide<T, KPV>), dim3(ndesc), dim3(DecideCfg<KPV>::threads), 0, s, d, n, kp, \
+                           e0, kw, nsplit, force_accept, last_window);                                            \
+        return hipGetLastError();                                                                                 \
+    }
+    DSU_D(16) DSU_D(32) DSU_D(64) DSU_D(128) DSU_D(256)
+#undef DSU_D
+    return hipErrorInvalidValue;
+}
+template hipError_t launch_window_decide<float>(const DetDesc<float> *, int, int, int, int, int, int, int, int,
+                                                hipStream_t);
+template hipError_t launch_window_decide<double>(const DetDesc<double> *, int, int, int, int, int, int, int, int,
+                                                 hipStream_t);
+
+template <typename T>
+hipError_t launch_window_flush(const DetDesc<T> *d, const FlushDesc<T> *fd, int ndesc, int n, int np, int kw,
+                               hipStream_t s) {
+    (void)d;
+    return launch_flush<T>(fd, ndesc, n, np, kw, 0, s);
+}
+template hipError_t launch_window_flush<float>(const DetDesc<float> *, const FlushDesc<float> *, int, int, int, int,
+                                               hipStream_t);
+template hipError_t launch_window_flush<double>(const DetDesc<double> *, const FlushDesc<double> *, int, int, int,
+                                                int, hipStream_t);
+
+// ------------------------------------------------- Slater matrix, FP64
+// M[j][i] = phi_j(r_i) for i, j < n (the transpose of A), identity padding.
+__global__ __launch_bounds__(kThreads) void k_build_pw_transpose(const double *const *__restrict__ pos_all,
+                                                                 double *const *__restrict__ m_all, int n, int np,
+                                                                 const int4 *__restrict__ kvec, double twopi_l) {
+    const double *pos = pos_all[blockIdx.z];
+    double *m = m_all[blockIdx.z];
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= np) return;
+    double v;
+    if (i < n && j < n) v = pw_orbital(kvec[j], twopi_l, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
+    else v = (i == j) ? 1.0 : 0.0;
+    m[(size_t)j * np + i] = v;
+}
+
+hipError_t launch_build_pw_transpose(const double *const *pos_dev, double *const *m_dev, int ndesc, int n, int np,
+                                     const int4 *kvec, double twopi_over_l, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_pw_transpose, dim3((np + kThreads - 1) / kThreads, np, ndesc), dim3(kThreads), 0, s,
+                       pos_dev, m_dev, n, np, kvec, twopi_over_l);
+    return hipGetLastError();
+}
+
+// After a recompute: drift = running - fresh, then re-base.
+template <typename T>
+__global__ void k_reset_state(const DetDesc<T> *__restrict__ d, const GjDesc *__restrict__ gj, double *drift,
+                              int ndesc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ndesc) return;
+    DetState *st = d[i].st;
+    const double fresh = *gj[i].logdet;
+    if (drift) drift[i] = st->logdet - fresh;
+    st->logdet = fresh;
+    st->sign = *gj[i].sign;
+}
+
+template <typename T>
+hipError_t launch_reset_state(const DetDesc<T> *d, const GjDesc *gj, double *drift, int ndesc, hipStream_t s) {
+    hipLaunchKernelGGL((k_reset_state<T>), dim3((ndesc + 63) / 64), dim3(64), 0, s, d, gj, drift, ndesc);
+    return hipGetLastError();
+}
+template hipError_t launch_reset_state<float>(const DetDesc<float> *, const GjDesc *, double *, int, hipStream_t);
+template hipError_t launch_reset_state<double>(const DetDesc<double> *, const GjDesc *, double *, int, hipStream_t);
+
+}  // namespace dsu

@@ -1,0 +1,410 @@
+// k_linalg.hip -- matrix kernels of libdsu for gfx950.
+//
+//  * k_flush_mfma: the en-bloc update of the inverse, Sherman-Morrison-Woodbury,
+//    eq. (4) of arXiv:1708.00744, written for the transposed inverse BT:
+//        Y  = BT U^T            (np x k)   U   = accepted new orbital rows
+//        Y' = Y - E             E[idx_j][j] = 1
+//        W  = Y' C^{-T}         C^{-1}     = inverse of I_k + V'A^{-1}U (eq. (3))
+//        BT = BT - W Vg         Vg         = stale BT rows of the moved electrons
+//    Row i of the new BT needs only row i of the old one, so each workgroup
+//    owns 64 rows and does the three products back to back on matrix cores
+//    (v_mfma_*_16x16x4), reading its rows of BT twice and writing them once.
+//  * k_flush_valu: the same update with vector ALUs, one wave per row (small k).
+//  * k_rank_update: M <- M - W Q (the trailing update of the Gauss-Jordan
+//    inversion), the third product of the flush on its own.
+//  * Gauss-Jordan inversion with partial pivoting in FP64, blocked by panels of
+//    nb columns: the O(N^3) explicit route the paper uses for direct checks.
+#include "dsu_internal.hpp"
+#include "tiles.hpp"
+
+namespace dsu {
+
+template <typename T, int KP> struct FlushLds {
+    static constexpr int LDY = KP + 16 / (int)sizeof(T);
+    static constexpr int p1 = KP * (128 / (int)sizeof(T) + 16 / (int)sizeof(T));
+    static constexpr int p2 = 64 * LDY;
+    static constexpr int p3 = KP * Phase3Cfg<T, KP>::LDV;
+    static constexpr int m12 = p1 > p2 ? p1 : p2;
+    static constexpr int elems = m12 > p3 ? m12 : p3;
+};
+
+// ---------------------------------------------------------------------------
+// Fused Woodbury flush, one 64-row block of one determinant per workgroup.
+// ---------------------------------------------------------------------------
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_flush_mfma(const FlushDesc<T> *__restrict__ descs, int np,
+                                                         int nblk, int kslots) {
+    __shared__ __attribute__((aligned(16))) T lds[FlushLds<T, KP>::elems];
+    constexpr int LDY = FlushLds<T, KP>::LDY;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int d = b / nblk, r0 = (b % nblk) * kRowBlock;
+    const FlushDesc<T> fd = descs[d];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    typename Mma<T>::acc_t acc[KP / 16];
+    rowblock_times_ut<T, KP>(fd.bt + (size_t)r0 * np, np, kRowBlock, fd.u, np, 0, np, lds, acc);
+
+    // Y block -> LDS, subtract E, then W = Y' C^{-T} on matrix cores.
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lds[(16 * wave + 4 * (lane >> 4) + i) * LDY + 16 * t + (lane & 15)] = acc[t][i];
+    __syncthreads();
+    for (int j = tid; j < kslots; j += kThreads) {
+        const int e = fd.idx[j];
+        if (e >= r0 && e < r0 + kRowBlock) lds[(e - r0) * LDY + j] -= T(1);
+    }
+    __syncthreads();
+    typename Mma<T>::acc_t wacc[KP / 16];
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t) wacc[t] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    for (int s = 0; s < KP / 4; ++s) {
+        const int jc = 4 * s + (lane >> 4);
+        const T a = lds[(16 * wave + (lane & 15)) * LDY + jc];
+#pragma unroll
+        for (int t = 0; t < KP / 16; ++t) {
+            const int lr = 16 * t + (lane & 15);
+            const T bb = (lr < kslots && jc < kslots) ? T(fd.cinv[(size_t)lr * fd.ldc + jc]) : T(0);
+            wacc[t] = Mma<T>::mma(a, bb, wacc[t]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lds[(16 * wave + 4 * (lane >> 4) + i) * LDY + 16 * t + (lane & 15)] = wacc[t][i];
+    __syncthreads();
+    T wa[KP / 4];
+#pragma unroll
+    for (int s = 0; s < KP / 4; ++s) wa[s] = -lds[(16 * wave + (lane & 15)) * LDY + 4 * s + (lane >> 4)];
+    __syncthreads();
+    rowblock_plus_wv<T, KP>(fd.bt + (size_t)r0 * np, np, np, fd.vg, np, wa, lds);
+}
+
+// ---------------------------------------------------------------------------
+// VALU flush: one wave per row of BT, k <= KMAX slots in registers.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kThreads) void k_flush_valu(const FlushDesc<T> *__restrict__ descs, int np, int kslots) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rows_per_det = np;
+    const int g = blockIdx.x * 4 + wave;
+    const int d = g / rows_per_det, row = g % rows_per_det;
+    const FlushDesc<T> fd = descs[d];
+    T *bt = fd.bt + (size_t)row * np;
+    T y[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) y[j] = T(0);
+    for (int c = lane; c < np; c += 64) {
+        const T x = bt[c];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+            if (j < kslots) y[j] += x * fd.u[(size_t)j * np + c];
+    }
+    T w[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+        y[j] = wave_sum(y[j]);
+        if (j < kslots && fd.idx[j] == row) y[j] -= T(1);
+    }
+#pragma unroll
+    for (int l = 0; l < KMAX; ++l) {
+        T s = T(0);
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+            if (l < kslots && j < kslots) s += T(fd.cinv[(size_t)l * fd.ldc + j]) * y[j];
+        w[l] = s;
+    }
+    for (int c = lane; c < np; c += 64) {
+        T x = bt[c];
+#pragma unroll
+        for (int l = 0; l < KMAX; ++l)
+            if (l < kslots) x -= w[l] * fd.vg[(size_t)l * np + c];
+        bt[c] = x;
+    }
+}
+
+template <typename T>
+hipError_t launch_flush(const FlushDesc<T> *descs_dev, int ndesc, int n, int np, int kslots, int mode,
+                        hipStream_t s) {
+    (void)n;
+    if (ndesc <= 0 || kslots <= 0) return hipSuccess;
+    if (mode == 1) {
+        const int blocks = ndesc * np / 4;
+#define DSU_VALU(KM)                                                                             \
+    if (kslots <= KM) {                                                                          \
+        hipLaunchKernelGGL((k_flush_valu<T, KM>), dim3(blocks), dim3(kThreads), 0, s, descs_dev, np, kslots); \
+        return hipGetLastError();                                                                \
+    }
+        DSU_VALU(1) DSU_VALU(2) DSU_VALU(4) DSU_VALU(8) DSU_VALU(16) DSU_VALU(32) DSU_VALU(64)
+#undef DSU_VALU
+        return hipErrorInvalidValue;
+    }
+    const int nblk = np / kRowBlock;
+    const dim3 grid(ndesc * nblk);
+#define DSU_MFMA(KPV)                                                                            \
+    if (kslots <= KPV) {                                                                         \
+        hipLaunchKernelGGL((k_flush_mfma<T, KPV>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk, kslots); \
+        return hipGetLastError();                                                                \
+    }
+    DSU_MFMA(16) DSU_MFMA(32) DSU_MFMA(64) DSU_MFMA(128) DSU_MFMA(256)
+#undef DSU_MFMA
+    return hipErrorInvalidValue;
+}
+template hipError_t launch_flush<float>(const FlushDesc<float> *, int, int, int, int, int, hipStream_t);
+template hipError_t launch_flush<double>(const FlushDesc<double> *, int, int, int, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// M <- M - W Q  (FP64), W np x KP (ld KP), Q KP x np.
+// ---------------------------------------------------------------------------
+template <int KP>
+__global__ __launch_bounds__(kThreads) void k_rank_update(const RankDesc *__restrict__ descs, int np, int nblk) {
+    __shared__ __attribute__((aligned(16))) double lds[KP * Phase3Cfg<double, KP>::LDV];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int d = b / nblk, r0 = (b % nblk) * kRowBlock;
+    const RankDesc rd = descs[d];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double wa[KP / 4];
+    const double *wr = rd.w + (size_t)(r0 + 16 * wave + (lane & 15)) * KP + (lane >> 4);
+#pragma unroll
+    for (int s = 0; s < KP / 4; ++s) wa[s] = -wr[4 * s];
+    rowblock_plus_wv<double, KP>(rd.m + (size_t)r0 * np, np, np, rd.q, np, wa, lds);
+}
+
+hipError_t launch_rank_update(const RankDesc *descs_dev, int ndesc, int np, int kslots, hipStream_t s) {
+    const int nblk = np / kRowBlock;
+    const dim3 grid(ndesc * nblk);
+    if (kslots == 16) hipLaunchKernelGGL((k_rank_update<16>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk);
+    else if (kslots == 32) hipLaunchKernelGGL((k_rank_update<32>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk);
+    else if (kslots == 64) hipLaunchKernelGGL((k_rank_update<64>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Blocked Gauss-Jordan inversion (FP64, in place, partial pivoting).
+// For a panel of columns R = [k0, k1): factor the panel with the unblocked
+// in-place Gauss-Jordan step (pivot = largest |entry| among rows >= k, lowest
+// index on ties), recording the row swaps.  The panel then holds the columns
+// R of the accumulated elimination matrix T.  The other columns follow from
+// the swapped pivot rows Q = M[R, :] as  M <- M - (E_R - T) Q.
+// After the last panel, column swaps in reverse pivot order unscramble the
+// inverse.  logdet = sum ln|pivot|, sign = swap parity * prod sign(pivot).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void argmax_combine(double &v, int &i, double v2, int i2) {
+    if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+}
+
+// One workgroup per determinant.  The panel P is column-major (P[j*np + i]).
+__global__ __launch_bounds__(kThreads) void k_gj_panel(const GjDesc *__restrict__ descs, int n, int np, int nb, int k0,
+                                                       int k1) {
+    __shared__ double s_v[kThreads / 64];
+    __shared__ int s_i[kThreads / 64];
+    __shared__ double s_row[64];
+    __shared__ int s_p;
+    const GjDesc g = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int w = k1 - k0;
+    double *P = g.panel;
+    for (int v = tid; v < np * w; v += kThreads) {
+        const int j = v / np, i = v % np;
+        P[(size_t)j * np + i] = g.m[(size_t)i * np + k0 + j];
+    }
+    if (k0 == 0 && tid == 0) { *g.logdet = 0.0; *g.sign = 1; *g.status = 0; }
+    __syncthreads();
+    for (int kk = 0; kk < w; ++kk) {
+        const int k = k0 + kk;
+        const double *pc = P + (size_t)kk * np;
+        double best = -1.0;
+        int bi = n;
+        for (int i = k + tid; i < n; i += kThreads) argmax_combine(best, bi, fabs(pc[i]), i);
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v2 = __shfl_xor(best, o, 64);
+            const int i2 = __shfl_xor(bi, o, 64);
+            argmax_combine(best, bi, v2, i2);
+        }
+        if (lane == 0) { s_v[wave] = best; s_i[wave] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double bv = s_v[0];
+            int bidx = s_i[0];
+            for (int q = 1; q < kThreads / 64; ++q) argmax_combine(bv, bidx, s_v[q], s_i[q]);
+            if (!(bv > 0.0)) { *g.status = -3; bidx = k; }
+            s_p = bidx;
+            g.piv[k] = bidx;
+        }
+        __syncthreads();
+        const int p = s_p;
+        if (p != k && tid < w) {
+            double *col = P + (size_t)tid * np;
+            const double t = col[k];
+            col[k] = col[p];
+            col[p] = t;
+        }
+        __syncthreads();
+        const double d = P[(size_t)kk * np + k];
+        if (tid == 0) {
+            if (d != 0.0) *g.logdet += log(fabs(d));
+            int sg = *g.sign;
+            if (p != k) sg = -sg;
+            if (d < 0.0) sg = -sg;
+            *g.sign = sg;
+        }
+        const double dinv = d != 0.0 ? 1.0 / d : 0.0;
+        if (tid < w) s_row[tid] = tid == kk ? dinv : P[(size_t)tid * np + k] * dinv;
+        __syncthreads();
+        // each thread owns whole rows: read the multiplier first, then update
+        for (int i = tid; i < np; i += kThreads) {
+            if (i == k) {
+                for (int j = 0; j < w; ++j) P[(size_t)j * np + i] = s_row[j];
+                continue;
+            }
+            const double f = P[(size_t)kk * np + i];
+            for (int j = 0; j < w; ++j) {
+                if (j == kk) P[(size_t)j * np + i] = -f * dinv;
+                else P[(size_t)j * np + i] -= f * s_row[j];
+            }
+        }
+        __syncthreads();
+    }
+    // W = E_R - T (np x nb row-major), zero columns beyond the panel width.
+    for (int v = tid; v < np * nb; v += kThreads) {
+        const int i = v / nb, j = v % nb;
+        g.w[v] = j < w ? ((i == k0 + j ? 1.0 : 0.0) - P[(size_t)j * np + i]) : 0.0;
+    }
+}
+
+// Apply the panel's row swaps to the non-panel columns, gather the pivot rows
+// into Q (zero in the panel columns), and store the factored panel into M.
+__global__ __launch_bounds__(kThreads) void k_gj_swap(const GjDesc *__restrict__ descs, int np, int nb, int k0,
+                                                      int k1) {
+    const GjDesc g = descs[blockIdx.y];
+    const int w = k1 - k0;
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= np) return;
+    if (c >= k0 && c < k1) {
+        for (int kk = 0; kk < nb; ++kk) g.q[(size_t)kk * np + c] = 0.0;
+        const double *col = g.panel + (size_t)(c - k0) * np;
+        for (int i = 0; i < np; ++i) g.m[(size_t)i * np + c] = col[i];
+        return;
+    }
+    for (int k = k0; k < k1; ++k) {
+        const int p = g.piv[k];
+        if (p != k) {
+            const double t = g.m[(size_t)k * np + c];
+            g.m[(size_t)k * np + c] = g.m[(size_t)p * np + c];
+            g.m[(size_t)p * np + c] = t;
+        }
+    }
+    for (int kk = 0; kk < nb; ++kk) g.q[(size_t)kk * np + c] = kk < w ? g.m[(size_t)(k0 + kk) * np + c] : 0.0;
+}
+
+// Final column permutation: idx = identity, then for k = n-1..0 swap idx[k], idx[piv[k]].
+__global__ void k_gj_perm(const GjDesc *__restrict__ descs, int n, int np) {
+    const GjDesc g = descs[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    for (int j = 0; j < np; ++j) g.perm[j] = j;
+    for (int k = n - 1; k >= 0; --k) {
+        const int p = g.piv[k];
+        const int t = g.perm[k];
+        g.perm[k] = g.perm[p];
+        g.perm[p] = t;
+    }
+}
+
+hipError_t launch_gj_invert(const GjDesc *descs_dev, const RankDesc *rank_dev, int ndesc, int n, int np, int nb,
+                            hipStream_t s) {
+    if (nb != 16 && nb != 32 && nb != 64) return hipErrorInvalidValue;
+    for (int k0 = 0; k0 < n; k0 += nb) {
+        const int k1 = k0 + nb < n ? k0 + nb : n;
+        hipLaunchKernelGGL(k_gj_panel, dim3(ndesc), dim3(kThreads), 0, s, descs_dev, n, np, nb, k0, k1);
+        hipLaunchKernelGGL(k_gj_swap, dim3((np + kThreads - 1) / kThreads, ndesc), dim3(kThreads), 0, s, descs_dev, np,
+                           nb, k0, k1);
+        hipError_t e = launch_rank_update(rank_dev, ndesc, np, nb, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_gj_perm, dim3(ndesc), dim3(64), 0, s, descs_dev, n, np);
+    return hipGetLastError();
+}
+
+// BT[i][j] = T(M[i][perm[j]]) inside n x n, zero padding.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cast_perm(const GjDesc *__restrict__ gj, T *const *__restrict__ bt, int n,
+                                                        int np) {
+    const int d = blockIdx.z;
+    const GjDesc g = gj[d];
+    T *out = bt[d];
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= np) return;
+    out[(size_t)i * np + j] = (i < n && j < n) ? T(g.m[(size_t)i * np + g.perm[j]]) : T(0);
+}
+
+template <typename T>
+hipError_t launch_cast_perm(const GjDesc *gj_dev, T *const *bt_dev, int ndesc, int n, int np, hipStream_t s) {
+    hipLaunchKernelGGL((k_cast_perm<T>), dim3((np + kThreads - 1) / kThreads, np, ndesc), dim3(kThreads), 0, s, gj_dev,
+                       bt_dev, n, np);
+    return hipGetLastError();
+}
+template hipError_t launch_cast_perm<float>(const GjDesc *, float *const *, int, int, int, hipStream_t);
+template hipError_t launch_cast_perm<double>(const GjDesc *, double *const *, int, int, int, hipStream_t);
+
+// M = A^T padded with the identity (32 x 32 tiles through LDS).
+__global__ __launch_bounds__(kThreads) void k_load_transpose(const double *const *__restrict__ a_all,
+                                                             double *const *__restrict__ m_all, int n, int np, int lda) {
+    __shared__ double tile[32][33];
+    const double *a = a_all[blockIdx.z];
+    double *m = m_all[blockIdx.z];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int i = by + r, j = bx + tx;  // read A[i][j]
+        tile[r][tx] = (i < n && j < n) ? a[(size_t)i * lda + j] : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int j = bx + r, i = by + tx;  // write M[j][i] = A[i][j]
+        if (j < np && i < np) m[(size_t)j * np + i] = tile[tx][r];
+    }
+}
+
+hipError_t launch_load_transpose(const double *const *a_dev, double *const *m_dev, int ndesc, int n, int np, int lda,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_load_transpose, dim3(np / 32, np / 32, ndesc), dim3(kThreads), 0, s, a_dev, m_dev, n, np, lda);
+    return hipGetLastError();
+}
+
+// out[i][j] = BT[j][i], n x n FP64.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_untranspose(const T *__restrict__ bt, double *__restrict__ out, int n,
+                                                          int np) {
+    __shared__ double tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = by + r, j = bx + tx;
+        tile[r][tx] = (i < n && j < n) ? double(bt[(size_t)i * np + j]) : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int j = bx + r, i = by + tx;
+        if (j < n && i < n) out[(size_t)j * n + i] = tile[tx][r];
+    }
+}
+
+template <typename T>
+hipError_t launch_untranspose(const T *bt, double *out, int n, int np, hipStream_t s) {
+    hipLaunchKernelGGL((k_untranspose<T>), dim3(np / 32, np / 32), dim3(kThreads), 0, s, bt, out, n, np);
+    return hipGetLastError();
+}
+template hipError_t launch_untranspose<float>(const float *, double *, int, int, hipStream_t);
+template hipError_t launch_untranspose<double>(const double *, double *, int, int, hipStream_t);
+
+}  // namespace dsu

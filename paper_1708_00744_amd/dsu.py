@@ -1,0 +1,283 @@
+"""ctypes binding of libdsu (include/dsu.h): argument marshalling only.
+
+Every step of the delayed-update path runs in the HIP kernels behind the C
+ABI; nothing here computes.  Importing this module does not need a GPU, but
+loading the library requires the built libdsu.so next to this file -- there is
+no fallback of any kind.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsu.so")
+
+OK, EINVAL, ENOMEM, ESINGULAR, ESTATE, EDEVICE, EBUDGET = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32_MIXED = 0, 1
+FLUSH_K_ACCEPTED, FLUSH_K_PROPOSED = 0, 1
+FLUSH_AUTO, FLUSH_VALU, FLUSH_MFMA = 0, 1, 2
+PHASE_ROWS, PHASE_G, PHASE_DECIDE, PHASE_FLUSH, PHASE_RECOMPUTE = 0, 1, 2, 3, 4
+MAX_K = 256
+
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESINGULAR: "ESINGULAR", ESTATE: "ESTATE", EDEVICE: "EDEVICE",
+          EBUDGET: "EBUDGET"}
+
+
+class DsuError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Request(C.Structure):
+    _fields_ = [("request_id", C.c_uint64), ("n", C.c_int32), ("spins", C.c_int32), ("seed", C.c_uint64),
+                ("sigma", C.c_double), ("sweeps", C.c_int32), ("arrival_s", C.c_double),
+                ("positions", C.POINTER(C.c_double))]
+
+
+class Result(C.Structure):
+    _fields_ = [("request_id", C.c_uint64), ("status", C.c_int32), ("sweeps_done", C.c_int32),
+                ("admit_s", C.c_double), ("finish_s", C.c_double), ("logdet", C.c_double * 2),
+                ("sign", C.c_int32 * 2), ("accepted", C.c_int64)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_vp, _i32, _i64, _dbl, _u64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64, C.c_size_t
+_pd, _pi32, _pi64, _pu64, _pu8 = (C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_uint64), C.POINTER(C.c_uint8))
+_pvp = C.POINTER(C.c_void_p)
+SIGNATURES = {
+    "dsu_last_error": (C.c_char_p, []),
+    "dsu_version": (C.c_int, []),
+    "dsu_footprint_bytes": (_sz, [_i32, _i32, _i32]),
+    "dsu_walker_create": (C.c_int, [_i32, _i32, _i32, _i32, _pd, _vp, _pvp]),
+    "dsu_walker_destroy": (C.c_int, [_vp]),
+    "dsu_propose_ratio": (C.c_int, [_vp, _i32, _pd, _pd]),
+    "dsu_propose_ratio_dev": (C.c_int, [_vp, _i32, _vp, _pd]),
+    "dsu_accept": (C.c_int, [_vp]),
+    "dsu_reject": (C.c_int, [_vp]),
+    "dsu_flush": (C.c_int, [_vp]),
+    "dsu_recompute_inverse": (C.c_int, [_vp, _pd, _pd, _pi32, _pd]),
+    "dsu_get_inverse": (C.c_int, [_vp, _pd]),
+    "dsu_get_logdet": (C.c_int, [_vp, _pd, _pi32]),
+    "dsu_walker_pending": (C.c_int, [_vp, _pi32]),
+    "dsu_walker_set_flush_kernel": (C.c_int, [_vp, _i32]),
+    "dsu_batch_create": (C.c_int, [_i32, _i32, _i32, _i32, _i32, _dbl, _pu64, _pu64, _pd, _pd, _i32, _vp, _pvp]),
+    "dsu_batch_destroy": (C.c_int, [_vp]),
+    "dsu_batch_sweep": (C.c_int, [_vp, _i32, _i32]),
+    "dsu_batch_sync": (C.c_int, [_vp]),
+    "dsu_batch_recompute": (C.c_int, [_vp, _pd]),
+    "dsu_batch_stats": (C.c_int, [_vp, _pd, _pi32, _pi64, _pi64]),
+    "dsu_batch_get_positions": (C.c_int, [_vp, _i32, _pd]),
+    "dsu_batch_get_inverse": (C.c_int, [_vp, _i32, _pd]),
+    "dsu_batch_set_trace": (C.c_int, [_vp, _i32]),
+    "dsu_batch_get_trace": (C.c_int, [_vp, _i32, _pd, _pu8]),
+    "dsu_batch_set_timing": (C.c_int, [_vp, _i32]),
+    "dsu_batch_kernel_time": (C.c_int, [_vp, _i32, _pi64, _pd]),
+    "dsu_batch_use_graph": (C.c_int, [_vp, _i32]),
+    "dsu_server_create": (C.c_int, [_i32, _i32, _dbl, _sz, _i32, _pvp]),
+    "dsu_server_destroy": (C.c_int, [_vp]),
+    "dsu_server_run": (C.c_int, [_vp, C.POINTER(Request), _i32, C.POINTER(Result), _pd, _i64, _pi64]),
+}
+
+
+def lib():
+    """Load libdsu.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1708_00744_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise DsuError(rc, lib().dsu_last_error().decode())
+    return rc
+
+
+def _dp(a):
+    return a.ctypes.data_as(_pd)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream  # torch.cuda.Stream
+
+
+def footprint_bytes(n, k_delay, precision=FP32_MIXED):
+    return int(lib().dsu_footprint_bytes(n, k_delay, precision))
+
+
+class Walker:
+    """Host-driven single walker (dsu_walker_*)."""
+
+    def __init__(self, slater, k_delay, precision=FP64, policy=FLUSH_K_ACCEPTED, stream=None):
+        a = _f64(slater)
+        n = a.shape[0]
+        if a.shape != (n, n):
+            raise ValueError("slater must be square")
+        self.n, self.k_delay, self.precision, self.policy = n, k_delay, precision, policy
+        h = C.c_void_p()
+        _check(lib().dsu_walker_create(n, k_delay, precision, policy, _dp(a), _stream_ptr(stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dsu_walker_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def propose(self, electron, row):
+        r = C.c_double()
+        _check(lib().dsu_propose_ratio(self._h, int(electron), _dp(_f64(row)), C.byref(r)))
+        return r.value
+
+    def propose_dev(self, electron, row_ptr):
+        r = C.c_double()
+        _check(lib().dsu_propose_ratio_dev(self._h, int(electron), C.c_void_p(row_ptr), C.byref(r)))
+        return r.value
+
+    def accept(self):
+        _check(lib().dsu_accept(self._h))
+
+    def reject(self):
+        _check(lib().dsu_reject(self._h))
+
+    def flush(self):
+        _check(lib().dsu_flush(self._h))
+
+    def recompute(self, slater=None):
+        ld, sg, dr = C.c_double(), C.c_int32(), C.c_double()
+        a = None if slater is None else _dp(_f64(slater))
+        _check(lib().dsu_recompute_inverse(self._h, a, C.byref(ld), C.byref(sg), C.byref(dr)))
+        return ld.value, sg.value, dr.value
+
+    def inverse(self):
+        out = np.empty((self.n, self.n))
+        _check(lib().dsu_get_inverse(self._h, _dp(out)))
+        return out
+
+    def logdet(self):
+        ld, sg = C.c_double(), C.c_int32()
+        _check(lib().dsu_get_logdet(self._h, C.byref(ld), C.byref(sg)))
+        return sg.value, ld.value
+
+    def pending(self):
+        k = C.c_int32()
+        _check(lib().dsu_walker_pending(self._h, C.byref(k)))
+        return k.value
+
+    def set_flush_kernel(self, mode):
+        _check(lib().dsu_walker_set_flush_kernel(self._h, mode))
+
+
+class Batch:
+    """Device-driven batch of walkers of one size n (dsu_batch_*)."""
+
+    def __init__(self, n, positions, seeds, walker_ids, sigma, k_delay, precision=FP32_MIXED, spins=1, box_l=10.0,
+                 recompute_every=0, stream=None):
+        seeds = np.ascontiguousarray(seeds, np.uint64)
+        walkers = len(seeds)
+        wids = np.ascontiguousarray(walker_ids, np.uint64)
+        sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, np.float64), (walkers,)))
+        pos = _f64(positions, (walkers * spins * n * 3,))
+        self.n, self.walkers, self.spins, self.ndet = n, walkers, spins, walkers * spins
+        self.k_delay, self.precision = k_delay, precision
+        h = C.c_void_p()
+        _check(lib().dsu_batch_create(walkers, n, spins, k_delay, precision, float(box_l),
+                                      seeds.ctypes.data_as(_pu64), wids.ctypes.data_as(_pu64), _dp(sig), _dp(pos),
+                                      int(recompute_every), _stream_ptr(stream), C.byref(h)))
+        self._h = h
+        self._trace_sweeps = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dsu_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def sweep(self, sweeps=1, force_accept=False):
+        _check(lib().dsu_batch_sweep(self._h, int(sweeps), int(bool(force_accept))))
+
+    def sync(self):
+        _check(lib().dsu_batch_sync(self._h))
+
+    def recompute(self):
+        drift = np.zeros(self.ndet)
+        _check(lib().dsu_batch_recompute(self._h, _dp(drift)))
+        return drift
+
+    def stats(self):
+        ld = np.zeros(self.ndet)
+        sg = np.zeros(self.ndet, np.int32)
+        acc = np.zeros(self.ndet, np.int64)
+        sw = np.zeros(self.ndet, np.int64)
+        _check(lib().dsu_batch_stats(self._h, _dp(ld), sg.ctypes.data_as(_pi32), acc.ctypes.data_as(_pi64),
+                                     sw.ctypes.data_as(_pi64)))
+        return {"logdet": ld, "sign": sg, "accepted": acc, "sweeps": sw}
+
+    def positions(self, det):
+        out = np.zeros((self.n, 3))
+        _check(lib().dsu_batch_get_positions(self._h, int(det), _dp(out)))
+        return out
+
+    def inverse(self, det):
+        out = np.zeros((self.n, self.n))
+        _check(lib().dsu_batch_get_inverse(self._h, int(det), _dp(out)))
+        return out
+
+    def set_trace(self, sweeps):
+        _check(lib().dsu_batch_set_trace(self._h, int(sweeps)))
+        self._trace_sweeps = int(sweeps)
+
+    def trace(self, det):
+        m = self._trace_sweeps * self.n
+        r = np.zeros(m)
+        a = np.zeros(m, np.uint8)
+        _check(lib().dsu_batch_get_trace(self._h, int(det), _dp(r), a.ctypes.data_as(_pu8)))
+        return r, a
+
+    def set_timing(self, enable):
+        _check(lib().dsu_batch_set_timing(self._h, int(bool(enable))))
+
+    def kernel_time(self, phase):
+        cnt, ms = C.c_int64(), C.c_double()
+        _check(lib().dsu_batch_kernel_time(self._h, int(phase), C.byref(cnt), C.byref(ms)))
+        return cnt.value, ms.value
+
+    def use_graph(self, enable):
+        _check(lib().dsu_batch_use_graph(self._h, int(bool(enable))))

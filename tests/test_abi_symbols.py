@@ -1,0 +1,55 @@
+"""Host-only checks of the C ABI: the library loads, exports every entry
+point include/dsu.h declares, and the binding's signature table matches."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1708_00744_amd import dsu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "dsu.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dsu_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for want in ["dsu_walker_create", "dsu_propose_ratio", "dsu_accept", "dsu_flush", "dsu_recompute_inverse",
+                 "dsu_batch_create", "dsu_batch_sweep", "dsu_server_run", "dsu_last_error"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(dsu.LIB_PATH):
+        pytest.skip("libdsu.so not built")
+    lib = ctypes.CDLL(dsu.LIB_PATH)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    assert sorted(dsu.SIGNATURES) == declared()
+
+
+def test_host_only_calls():
+    if not os.path.exists(dsu.LIB_PATH):
+        pytest.skip("libdsu.so not built")
+    L = dsu.lib()
+    assert L.dsu_version() >= 100
+    # footprint is pure host arithmetic
+    assert dsu.footprint_bytes(4096, 64, dsu.FP32_MIXED) > 4096 * 4096 * 4
+    assert dsu.footprint_bytes(4096, 64, dsu.FP64) > 4096 * 4096 * 8
+    assert dsu.footprint_bytes(0, 64, dsu.FP64) == 0
+    assert dsu.footprint_bytes(64, 257, dsu.FP64) == 0
+    # argument validation happens before any device call
+    h = ctypes.c_void_p()
+    assert L.dsu_walker_create(0, 4, 0, 0, None, None, ctypes.byref(h)) == dsu.EINVAL
+    assert b"n = 0" in L.dsu_last_error()
+    assert L.dsu_walker_create(8, 0, 0, 0, None, None, ctypes.byref(h)) == dsu.EINVAL
+    assert L.dsu_accept(None) == dsu.EINVAL
+    assert L.dsu_batch_sweep(None, 1, 0) == dsu.EINVAL

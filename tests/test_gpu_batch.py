@@ -1,0 +1,215 @@
+"""Parity of the batched, device-driven form (dsu_batch_*) with the oracle.
+
+Both sides draw the same moves: each implements Philox4x64-10 and Box-Muller
+on its own, keyed (seed, walker) with counter (sweep, spin*n + e, block, 0),
+and each evaluates the plane-wave orbitals itself.  Only the seeded initial
+positions are shared inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import marginal, rel_err, require_gpu
+from paper_1708_00744_amd import dsu, inputs
+
+pytestmark = pytest.mark.gpu
+
+L = 10.0
+FP64_TOL = 1e-10
+
+
+def make_batch(n, walkers, spins, K, precision, sigma, seed=1, recompute_every=0, graph=False):
+    pos = np.stack([inputs.positions(seed, w, spins * n, L).reshape(spins, n, 3) for w in range(walkers)])
+    seeds = [seed] * walkers
+    wids = list(range(walkers))
+    b = dsu.Batch(n, pos, seeds, wids, sigma, K, precision=precision, spins=spins, box_l=L,
+                  recompute_every=recompute_every)
+    if graph:
+        b.use_graph(True)
+    return b, pos
+
+
+def oracle_det(n, pos, w, s, sigma, sweeps, seed=1, force=False, residual=False):
+    return oracle.walker_run(n, L, seed, w, s, sigma, pos[w, s], sweeps, force_accept=force, residual=residual,
+                             fresh=False)
+
+
+def check_fp64_against_oracle(b, pos, n, walkers, spins, sigma, sweeps, seed=1):
+    st = b.stats()
+    for w in range(walkers):
+        for s in range(spins):
+            d = w * spins + s
+            t = oracle_det(n, pos, w, s, sigma, sweeps, seed)
+            r, a = b.trace(d)
+            assert rel_err(r, t.ratio).max() < FP64_TOL, (d, rel_err(r, t.ratio).max())
+            assert np.array_equal(a, t.accepted), d
+            assert st["accepted"][d] == t.n_accepted[0]
+            assert st["sign"][d] == t.sign_run[-1]
+            assert abs(st["logdet"][d] - t.logdet_run[-1]) < 1e-9
+            np.testing.assert_allclose(b.positions(d), t.pos, rtol=0, atol=1e-12)
+            np.testing.assert_allclose(b.inverse(d), t.ainv, rtol=1e-8, atol=1e-9)
+
+
+def test_c1_fp64_one_walker():
+    """N = 64, L = 10, K = 16, sigma = 0.05 L, one sweep (plus a second)."""
+    require_gpu()
+    n, K, sigma = 64, 16, 0.5
+    b, pos = make_batch(n, 1, 1, K, dsu.FP64, sigma)
+    b.set_trace(2)
+    b.sweep(2)
+    check_fp64_against_oracle(b, pos, n, 1, 1, sigma, 2)
+    acc = b.stats()["accepted"][0] / (2 * n)
+    assert 0.4 < acc < 0.9
+    b.close()
+
+
+@pytest.mark.parametrize("n,K,walkers,spins", [(100, 16, 2, 2), (50, 64, 3, 1), (200, 32, 2, 1), (130, 1, 1, 1),
+                                               (96, 128, 1, 1), (160, 256, 1, 1), (64, 20, 2, 2)])
+def test_fp64_ragged_and_k(n, K, walkers, spins):
+    require_gpu()
+    sigma = 0.3
+    b, pos = make_batch(n, walkers, spins, K, dsu.FP64, sigma, seed=5)
+    b.set_trace(2)
+    b.sweep(2)
+    check_fp64_against_oracle(b, pos, n, walkers, spins, sigma, 2, seed=5)
+    b.close()
+
+
+def test_force_accept_fp64():
+    require_gpu()
+    n, K = 80, 16
+    b, pos = make_batch(n, 1, 1, K, dsu.FP64, 0.2, seed=8)
+    b.set_trace(1)
+    b.sweep(1, force_accept=True)
+    r, a = b.trace(0)
+    t = oracle_det(n, pos, 0, 0, 0.2, 1, seed=8, force=True)
+    assert a.all() and rel_err(r, t.ratio).max() < FP64_TOL
+    b.close()
+
+
+def test_graph_replay_equals_eager():
+    require_gpu()
+    n, K = 128, 16
+    outs = []
+    for graph in (False, True):
+        b, _ = make_batch(n, 2, 1, K, dsu.FP32_MIXED, 0.25, seed=11, graph=graph)
+        b.set_trace(3)
+        for _ in range(3):
+            b.sweep(1)
+            b.sync()
+        outs.append((b.trace(0), b.trace(1), b.stats()))
+        b.close()
+    (e0, e1, es), (g0, g1, gs) = outs
+    for x, y in ((e0, g0), (e1, g1)):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+    assert np.array_equal(es["logdet"], gs["logdet"])
+
+
+def test_fp32_force_accept_error_bounds():
+    """FP32 inverse and products, 100% acceptance (the paper's test mode):
+    the decisions cannot differ, so every ratio is compared."""
+    require_gpu()
+    n, K, walkers = 256, 32, 4
+    sigma = 0.05
+    b, pos = make_batch(n, walkers, 1, K, dsu.FP32_MIXED, sigma, seed=21)
+    b.set_trace(2)
+    b.sweep(2, force_accept=True)
+    st = b.stats()
+    worst = 0.0
+    for w in range(walkers):
+        t = oracle_det(n, pos, w, 0, sigma, 2, seed=21, force=True)
+        r, a = b.trace(w)
+        assert a.all()
+        worst = max(worst, rel_err(r, t.ratio).max())
+        assert abs(st["logdet"][w] - t.logdet_run[-1]) < 1e-3
+        inv = b.inverse(w)
+        a_end = oracle.pw_matrix(oracle.pw_kvectors(n), L, t.pos)
+        assert np.abs(inv @ a_end - np.eye(n)).max() < 1e-3
+    print(f"fp32 worst ratio error {worst:.3e}", flush=True)
+    assert worst < 1e-4
+
+
+def test_fp32_decisions_match_until_marginal():
+    require_gpu()
+    n, K, walkers = 128, 32, 4
+    sigma = 0.2
+    b, pos = make_batch(n, walkers, 1, K, dsu.FP32_MIXED, sigma, seed=31)
+    b.set_trace(2)
+    b.sweep(2)
+    compared = 0
+    for w in range(walkers):
+        t = oracle_det(n, pos, w, 0, sigma, 2, seed=31)
+        r, a = b.trace(w)
+        diff = np.nonzero(a != t.accepted)[0]
+        upto = diff[0] if len(diff) else len(a)
+        if len(diff):
+            m = diff[0]
+            assert marginal(t.u[m], t.ratio[m], 1e-3), (w, m, r[m], t.ratio[m], t.u[m])
+        assert rel_err(r[:upto], t.ratio[:upto]).max() < 1e-4
+        compared += upto
+    assert compared > walkers * n
+
+
+def test_recompute_drift_and_reset():
+    require_gpu()
+    n, K = 192, 32
+    b, pos = make_batch(n, 2, 1, K, dsu.FP32_MIXED, 0.1, seed=41, recompute_every=2)
+    b.sweep(3, force_accept=True)  # recompute happens before sweep index 2
+    drift = b.recompute()
+    assert np.abs(drift).max() < 1e-3
+    for d in range(2):
+        t = oracle_det(n, pos, d, 0, 0.1, 3, seed=41, force=True)
+        np.testing.assert_allclose(b.positions(d), t.pos, atol=1e-12)
+        inv = b.inverse(d)
+        np.testing.assert_allclose(inv, t.ainv, rtol=1e-4, atol=1e-4 * np.abs(t.ainv).max())
+    st = b.stats()
+    assert np.all(st["sweeps"] == 3)
+    b.close()
+
+
+def test_bad_arguments():
+    require_gpu()
+    with pytest.raises(dsu.DsuError) as ex:
+        dsu.Batch(64, np.zeros((1, 64, 3)), [1], [0], 0.1, 0)
+    assert ex.value.code == dsu.EINVAL
+    with pytest.raises(dsu.DsuError) as ex:
+        # all electrons at one point: singular Slater matrix
+        dsu.Batch(64, np.zeros((1, 64, 3)), [1], [0], 0.1, 16)
+    assert ex.value.code == dsu.ESINGULAR
+
+
+def test_c4_shape_sampled():
+    """N = 4096, FP32, K = 64: the bench's launch configuration on two walkers.
+    Properties checked at full size: ratios of the first window against the
+    oracle's Sherman-Morrison, and after a sweep the inverse residual and the
+    running log-determinant against a direct (LAPACK) calculation."""
+    require_gpu()
+    n, K, walkers, sigma = 4096, 64, 2, 0.02
+    b, pos = make_batch(n, walkers, 1, K, dsu.FP32_MIXED, sigma, seed=1000)
+    b.set_trace(1)
+    b.sweep(1, force_accept=True)
+    st = b.stats()
+    kv = oracle.pw_kvectors(n)
+    for w in range(walkers):
+        r, a = b.trace(w)
+        # first window: the oracle applies 64 Sherman-Morrison steps from a fresh inverse
+        a0 = oracle.pw_matrix(kv, L, pos[w, 0])
+        ainv = np.linalg.inv(a0)
+        cur = pos[w, 0].copy()
+        for e in range(K):
+            g, _ = oracle.move_randoms(1000, w, 0, e)
+            rt = cur[e] + sigma * g
+            row = oracle.pw_row(kv, L, rt)
+            ro = oracle.sm_ratio(ainv, e, row)
+            assert rel_err(r[e], ro) < 1e-4, (w, e, r[e], ro)
+            oracle.sm_accept(ainv, a0, e, row, ro)
+            cur[e] = rt
+        p_end = b.positions(w)
+        a_end = oracle.pw_matrix(kv, L, p_end)
+        s_np, l_np = np.linalg.slogdet(a_end)
+        assert st["sign"][w] == s_np and abs(st["logdet"][w] - l_np) < 1e-2
+        inv = b.inverse(w)
+        res = np.abs(inv @ a_end - np.eye(n)).max()
+        print(f"walker {w}: residual {res:.2e}, logdet diff {st['logdet'][w] - l_np:.2e}", flush=True)
+        assert res < 1e-2
+    b.close()
