@@ -180,6 +180,10 @@ int dsu_batch_kernel_time(dsu_batch *b, int32_t phase, int64_t *launches, double
 /* Capture one sweep into a hipGraph and replay it for dsu_batch_sweep
  * (enable = 1) or launch kernels directly (0). */
 int dsu_batch_use_graph(dsu_batch *b, int32_t enable);
+/* Change the delay K of a live batch (1 <= k_delay <= the K it was created
+ * with; Sec. II: K is the tunable of the method).  Takes effect at the next
+ * sweep. */
+int dsu_batch_set_delay(dsu_batch *b, int32_t k_delay);
 
 /* ======================================================================
  * Serving: a pool of walkers of mixed n admitted by a device-memory budget,
@@ -209,11 +213,23 @@ typedef struct {
     int64_t accepted;       /* accepted moves over all spins and sweeps           */
 } dsu_result;
 
-/* budget_bytes: device memory the pool may use for walker state; requests
- * wait until enough is free.  recompute_every as in dsu_batch_create. */
+/* budget_bytes: device memory the pool may use for walker state (one arena,
+ * allocated here); requests wait until enough is free.  Each size n also
+ * gets a small recompute workspace outside the budget.  recompute_every as
+ * in dsu_batch_create. */
 int dsu_server_create(int32_t k_delay, int32_t precision, double box_L, size_t budget_bytes,
                       int32_t recompute_every, dsu_server **out);
 int dsu_server_destroy(dsu_server *s);
+/* Manual control.  dsu_server_add admits one walker now (its arrival_s is
+ * ignored): DSU_EBUDGET if it does not fit the free budget, DSU_EINVAL if it
+ * never can.  dsu_server_step runs one sweep of every resident walker (the
+ * sizes concurrently) and waits.  dsu_server_result reads a walker's result;
+ * with remove = 1 it also retires the walker and frees its memory.
+ * dsu_server_usage reports arena bytes in use and resident walkers. */
+int dsu_server_add(dsu_server *s, const dsu_request *req, int32_t *slot_out);
+int dsu_server_step(dsu_server *s);
+int dsu_server_result(dsu_server *s, int32_t slot, dsu_result *out, int32_t remove);
+int dsu_server_usage(dsu_server *s, size_t *used_bytes, int32_t *resident_walkers);
 /* Serve `count` requests in arrival order (wall clock): admit by budget,
  * sweep all resident walkers (one batch per n, concurrently), retire
  * finished ones.  Fills results[count].  sweep_latency_ms (optional,

@@ -406,3 +406,56 @@ int orc_walkers_run(int nw, int n, double L, const uint64_t *seeds, const uint64
     }
     return threads;
 }
+
+/* ------------------------------------------------------------------------ */
+/* A bounded sample of the same Metropolis loop: `nmoves` moves of sweep     */
+/* `sweep` starting at electron `e_first`, from a supplied state (positions, */
+/* A and Ainv, all updated in place).  Used to time the oracle on a slice of */
+/* a large workload whose O(N^3) set-up would dominate a full run.           */
+/* Returns the number of accepted moves.                                     */
+/* ------------------------------------------------------------------------ */
+int64_t orc_walker_moves(int n, double L, uint64_t seed, uint64_t walker, int spin, double sigma, int sweep,
+                         int e_first, int nmoves, int force_accept, double *pos, double *a, double *ainv,
+                         double *ratio_out)
+{
+    int *kv = (int *)malloc(sizeof(int) * 4 * (size_t)n);
+    double *phi = (double *)malloc(sizeof(double) * (size_t)n);
+    double *work = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    int64_t nacc = 0;
+    orc_pw_kvectors(n, kv);
+    for (int m = 0; m < nmoves; ++m) {
+        int e = (e_first + m) % n;
+        double g[3], u;
+        orc_move_randoms(seed, walker, (uint64_t)sweep, (uint64_t)spin * (uint64_t)n + (uint64_t)e, g, &u);
+        double rt[3] = {pos[3 * e + 0] + sigma * g[0], pos[3 * e + 1] + sigma * g[1], pos[3 * e + 2] + sigma * g[2]};
+        orc_pw_row(n, kv, L, rt, phi);
+        double r = orc_sm_ratio(n, ainv, e, phi);
+        if (ratio_out) ratio_out[m] = r;
+        if (force_accept || u < r * r) {
+            orc_sm_accept(n, ainv, a, e, phi, r, work);
+            pos[3 * e + 0] = rt[0]; pos[3 * e + 1] = rt[1]; pos[3 * e + 2] = rt[2];
+            ++nacc;
+        }
+    }
+    free(kv); free(phi); free(work);
+    return nacc;
+}
+
+/* orc_walker_moves for nw walkers at once, one OpenMP thread each; arrays are
+ * per-walker blocks.  Returns the number of threads used. */
+int orc_walkers_moves(int nw, int n, double L, const uint64_t *seeds, const uint64_t *walker_ids, double sigma,
+                      int sweep, int e_first, int nmoves, int force_accept, double *pos, double *a, double *ainv,
+                      int64_t *n_accepted)
+{
+    int threads = 1;
+#ifdef _OPENMP
+    threads = omp_get_max_threads();
+    if (threads > nw) threads = nw;
+#pragma omp parallel for schedule(static, 1) num_threads(threads)
+#endif
+    for (int w = 0; w < nw; ++w)
+        n_accepted[w] = orc_walker_moves(n, L, seeds[w], walker_ids[w], 0, sigma, sweep, e_first, nmoves, force_accept,
+                                         pos + (size_t)w * 3 * n, a + (size_t)w * n * n, ainv + (size_t)w * n * n,
+                                         NULL);
+    return threads;
+}

@@ -66,6 +66,12 @@ def _declare(L):
     L.orc_walkers_run.argtypes = [C.c_int, C.c_int, C.c_double, _u64p, _u64p, vp, C.c_double,
                                   C.c_int, C.c_int, C.c_int, _dp, vp, vp, vp, vp, vp, _ip]
     L.orc_walkers_run.restype = C.c_int
+    L.orc_walker_moves.argtypes = [C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_int, C.c_double, C.c_int,
+                                   C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, vp]
+    L.orc_walker_moves.restype = C.c_int64
+    L.orc_walkers_moves.argtypes = [C.c_int, C.c_int, C.c_double, _u64p, _u64p, C.c_double, C.c_int, C.c_int,
+                                    C.c_int, C.c_int, _dp, _dp, _dp, _i64p]
+    L.orc_walkers_moves.restype = C.c_int
 
 
 def _ptr(a):
@@ -203,3 +209,27 @@ def walkers_run(n, L, seeds, walker_ids, spins, sigma, pos, sweeps, first_sweep=
     if np.any(status != 0):
         raise np.linalg.LinAlgError("singular start")
     return ratio, acc, ld, pos_out.reshape(nw, n, 3), nacc, threads
+
+
+def walker_moves(n, L, seed, walker, spin, sigma, sweep, e_first, nmoves, pos, a, ainv, force_accept=False):
+    """In place on pos (n x 3), a, ainv: `nmoves` Metropolis moves from the given state.
+    Returns (ratios, accepted count)."""
+    for x in (pos, a, ainv):
+        assert x.flags.c_contiguous and x.dtype == np.float64
+    ratios = np.zeros(nmoves)
+    nacc = lib().orc_walker_moves(n, float(L), int(seed), int(walker), int(spin), float(sigma), int(sweep),
+                                  int(e_first), int(nmoves), int(bool(force_accept)), pos, a, ainv, _ptr(ratios))
+    return ratios, nacc
+
+
+def walkers_moves(n, L, seeds, walker_ids, sigma, sweep, e_first, nmoves, pos, a, ainv, force_accept=False):
+    """Many walkers (OpenMP): pos (w, n, 3), a and ainv (w, n, n), all in place.
+    Returns (accepted per walker, threads used)."""
+    nw = len(seeds)
+    for x in (pos, a, ainv):
+        assert x.flags.c_contiguous and x.dtype == np.float64
+    nacc = np.zeros(nw, np.int64)
+    threads = lib().orc_walkers_moves(nw, n, float(L), np.ascontiguousarray(seeds, np.uint64),
+                                      np.ascontiguousarray(walker_ids, np.uint64), float(sigma), int(sweep),
+                                      int(e_first), int(nmoves), int(bool(force_accept)), pos, a, ainv, nacc)
+    return nacc, threads

@@ -1,0 +1,600 @@
+// bucket.hip -- the lock-step engine of the batched form, and the dsu_batch
+// entry points built on it.
+//
+// Per sweep and window of K proposals (electrons e0..e0+kw-1), four launches
+// over every member determinant:
+//   rows   : draw the kw moves, evaluate the proposed orbital rows U and copy
+//            the stale inverse rows Vg                       (k_window_rows)
+//   G      : look-ahead products G = U BT[e0..]^T on matrix cores (k_window_g)
+//   decide : sequential Metropolis decisions with the bordered inverse of
+//            eq. (3)'s C matrix                               (k_window_decide)
+//   flush  : en-bloc Woodbury update of BT, eq. (4)          (k_flush_mfma)
+#include "bucket.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace dsu {
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static int choose_nsplit(int np) {
+    int s = np / 512;
+    if (s < 1) s = 1;
+    while (s > 1 && (np % s != 0 || (np / s) % 64 != 0)) --s;
+    return s;
+}
+
+BucketShape BucketShape::make(int n, int kmax, int prec) {
+    BucketShape s;
+    s.n = n;
+    s.np = round_up(n, 64);
+    s.kmax = kmax;
+    s.kp = kpad(kmax);
+    s.prec = prec;
+    s.nsplit = choose_nsplit(s.np);
+    return s;
+}
+
+// Piece sizes in carve order.
+static void pieces(const BucketShape &s, size_t out[11]) {
+    const size_t e = elem_size(s.prec), np = s.np, kp = s.kp;
+    out[0] = np * np * e;                           // bt
+    out[1] = kp * np * e;                           // u
+    out[2] = kp * np * e;                           // vg
+    out[3] = (size_t)s.nsplit * kp * kp * e;        // gpart
+    out[4] = kp * kp * 8;                           // cfl
+    out[5] = kp > 128 ? kp * (kp + 1) * 8 : 0;      // cwork
+    out[6] = kp > 64 ? kp * (kp + 1) * 8 : 0;       // gwork
+    out[7] = kp * 4 * 8;                            // prop
+    out[8] = (size_t)s.n * 3 * 8;                   // pos
+    out[9] = kp * 4;                                // idx
+    out[10] = sizeof(DetState);                     // st
+}
+
+size_t BucketShape::det_bytes() const {
+    size_t p[11], b = 0;
+    pieces(*this, p);
+    for (size_t x : p) b += align256(x);
+    return b;
+}
+
+DetSlot BucketShape::carve(char *base) const {
+    size_t p[11];
+    pieces(*this, p);
+    char *c = base;
+    void *ptr[11];
+    for (int i = 0; i < 11; ++i) {
+        ptr[i] = p[i] ? (void *)c : nullptr;
+        c += align256(p[i]);
+    }
+    DetSlot d;
+    d.bt = ptr[0];
+    d.u = ptr[1];
+    d.vg = ptr[2];
+    d.gpart = ptr[3];
+    d.cfl = (double *)ptr[4];
+    d.cwork = (double *)ptr[5];
+    d.gwork = (double *)ptr[6];
+    d.prop = (double *)ptr[7];
+    d.pos = (double *)ptr[8];
+    d.idx = (int *)ptr[9];
+    d.st = (DetState *)ptr[10];
+    return d;
+}
+
+int Bucket::init(const BucketShape &shape, int k_delay, double box_l, void *stream_or_null, int gj_group) {
+    sh = shape;
+    K = k_delay;
+    L = box_l;
+    twopi_l = 2.0 * M_PI / box_l;
+    CHK(make_stream(stream_or_null, &stream, &own_stream));
+    CHK(dalloc(&kvec, (size_t)sh.n));
+    std::vector<int4> kv(sh.n);
+    build_kvectors(sh.n, kv.data());
+    HIPCHK(hipMemcpy(kvec, kv.data(), sizeof(int4) * sh.n, hipMemcpyHostToDevice));
+    CHK(gj_.alloc(std::max(1, gj_group), sh.np, sh.n));
+    return DSU_OK;
+}
+
+void Bucket::release() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    drop_graph();
+    for (void *p : {(void *)kvec, ddesc_, fdesc_, sub_ddesc_, (void *)sub_pos_, (void *)sub_bt_, (void *)drift_})
+        dfree(p);
+    kvec = nullptr;
+    ddesc_ = fdesc_ = sub_ddesc_ = nullptr;
+    sub_pos_ = nullptr;
+    sub_bt_ = nullptr;
+    drift_ = nullptr;
+    cap_ = 0;
+    gj_.release();
+    for (auto &e : ev_free_) (void)hipEventDestroy(e);
+    for (auto &e : ev_used_) {
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    ev_free_.clear();
+    ev_used_.clear();
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+    stream = nullptr;
+}
+
+int Bucket::ensure_capacity(int n) {
+    if (n <= cap_) return DSU_OK;
+    int c = std::max(n, cap_ * 2);
+    for (void *p : {ddesc_, fdesc_, sub_ddesc_, (void *)sub_pos_, (void *)sub_bt_, (void *)drift_}) dfree(p);
+    const size_t dsz = std::max(sizeof(DetDesc<double>), sizeof(DetDesc<float>));
+    const size_t fsz = std::max(sizeof(FlushDesc<double>), sizeof(FlushDesc<float>));
+    CHK(dev_alloc(&ddesc_, dsz * c));
+    CHK(dev_alloc(&fdesc_, fsz * c));
+    CHK(dev_alloc(&sub_ddesc_, dsz * c));
+    CHK(dalloc(&sub_pos_, c));
+    CHK(dalloc(&sub_bt_, c));
+    CHK(dalloc(&drift_, c));
+    cap_ = c;
+    return DSU_OK;
+}
+
+template <typename T> static DetDesc<T> to_desc(const DetSlot &s) {
+    DetDesc<T> d;
+    d.bt = (T *)s.bt;
+    d.u = (T *)s.u;
+    d.vg = (T *)s.vg;
+    d.gpart = (T *)s.gpart;
+    d.cfl = s.cfl;
+    d.cwork = s.cwork;
+    d.gwork = s.gwork;
+    d.prop = s.prop;
+    d.pos = s.pos;
+    d.idx = s.idx;
+    d.st = s.st;
+    d.trace_r = s.trace_r;
+    d.trace_a = s.trace_a;
+    d.trace_cap = s.trace_cap;
+    d.seed = s.seed;
+    d.wid = s.wid;
+    d.sigma = s.sigma;
+    d.spin = s.spin;
+    return d;
+}
+
+template <typename T> int Bucket::upload_t() {
+    std::vector<DetDesc<T>> dd(dets.size());
+    std::vector<FlushDesc<T>> fd(dets.size());
+    for (size_t i = 0; i < dets.size(); ++i) {
+        dd[i] = to_desc<T>(dets[i]);
+        fd[i] = FlushDesc<T>{dd[i].bt, dd[i].u, dd[i].vg, dd[i].cfl, dd[i].idx, sh.kp};
+    }
+    if (!dets.empty()) {
+        HIPCHK(hipMemcpyAsync(ddesc_, dd.data(), sizeof(dd[0]) * dd.size(), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(fdesc_, fd.data(), sizeof(fd[0]) * fd.size(), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+    return DSU_OK;
+}
+
+int Bucket::set_dets(const std::vector<DetSlot> &d) {
+    HIPCHK(hipStreamSynchronize(stream));
+    dets = d;
+    CHK(ensure_capacity((int)dets.size()));
+    drop_graph();
+    return sh.prec == DSU_FP64 ? upload_t<double>() : upload_t<float>();
+}
+
+int Bucket::set_delay(int k) {
+    if (k < 1 || k > sh.kmax) return fail(DSU_EINVAL, "delay %d outside [1, %d] of this batch", k, sh.kmax);
+    K = k;
+    drop_graph();
+    return DSU_OK;
+}
+
+void Bucket::drop_graph() {
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    gexec_ = nullptr;
+    graph_ = nullptr;
+    graph_force_ = -1;
+}
+
+template <typename F> int Bucket::timed(int phase, F fn) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timing) {
+        for (hipEvent_t *e : {&e0, &e1}) {
+            if (!ev_free_.empty()) {
+                *e = ev_free_.back();
+                ev_free_.pop_back();
+            } else {
+                HIPCHK(hipEventCreate(e));
+            }
+        }
+        HIPCHK(hipEventRecord(e0, stream));
+    }
+    HIPCHK(fn());
+    if (timing) {
+        HIPCHK(hipEventRecord(e1, stream));
+        ev_used_.push_back({phase, {e0, e1}});
+    }
+    return DSU_OK;
+}
+
+int Bucket::harvest_events() {
+    if (ev_used_.empty()) return DSU_OK;
+    HIPCHK(hipStreamSynchronize(stream));
+    for (auto &e : ev_used_) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+        t_ms[e.first] += ms;
+        t_count[e.first] += 1;
+        ev_free_.push_back(e.second.first);
+        ev_free_.push_back(e.second.second);
+    }
+    ev_used_.clear();
+    return DSU_OK;
+}
+
+template <typename T> int Bucket::enqueue_sweep_t(int force) {
+    const DetDesc<T> *dd = (const DetDesc<T> *)ddesc_;
+    const FlushDesc<T> *fd = (const FlushDesc<T> *)fdesc_;
+    const int nd = (int)dets.size();
+    const int kt = kpad(K);
+    for (int e0 = 0; e0 < sh.n; e0 += K) {
+        const int kw = std::min(K, sh.n - e0);
+        const int last = e0 + kw == sh.n;
+        CHK(timed(PH_ROWS, [&] {
+            return launch_window_rows<T>(dd, nd, sh.n, sh.np, kt, e0, kw, kvec, twopi_l, stream);
+        }));
+        CHK(timed(PH_G, [&] { return launch_window_g<T>(dd, nd, sh.np, kt, sh.kp, e0, sh.nsplit, stream); }));
+        CHK(timed(PH_DECIDE, [&] {
+            return launch_window_decide<T>(dd, nd, kt, sh.kp, e0, kw, sh.nsplit, force, last, stream);
+        }));
+        CHK(timed(PH_FLUSH, [&] { return launch_flush<T>(fd, nd, sh.n, sh.np, kw, 0, stream); }));
+    }
+    return DSU_OK;
+}
+
+int Bucket::enqueue_sweep(int force) {
+    return sh.prec == DSU_FP64 ? enqueue_sweep_t<double>(force) : enqueue_sweep_t<float>(force);
+}
+
+int Bucket::build_graph(int force) {
+    drop_graph();
+    HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    const bool tm = timing;
+    timing = false;
+    int rc = enqueue_sweep(force);
+    timing = tm;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(stream, &g);
+    if (rc != DSU_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(DSU_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    graph_ = g;
+    HIPCHK(hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0));
+    graph_force_ = force;
+    return DSU_OK;
+}
+
+int Bucket::sweep(int force) {
+    if (dets.empty()) return DSU_OK;
+    if (use_graph && !timing) {
+        if (!gexec_ || graph_force_ != force) CHK(build_graph(force));
+        HIPCHK(hipGraphLaunch(gexec_, stream));
+        return DSU_OK;
+    }
+    return enqueue_sweep(force);
+}
+
+template <typename T> int Bucket::recompute_t(const std::vector<int> &which, double *drift_host) {
+    if (which.empty()) return DSU_OK;
+    const int cnt_all = (int)which.size();
+    std::vector<DetDesc<T>> sd(cnt_all);
+    std::vector<double *> sp(cnt_all);
+    std::vector<void *> sb(cnt_all);
+    for (int i = 0; i < cnt_all; ++i) {
+        const DetSlot &s = dets[which[i]];
+        sd[i] = to_desc<T>(s);
+        sp[i] = s.pos;
+        sb[i] = s.bt;
+    }
+    HIPCHK(hipMemcpyAsync(sub_ddesc_, sd.data(), sizeof(sd[0]) * cnt_all, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(sub_pos_, sp.data(), sizeof(double *) * cnt_all, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(sub_bt_, sb.data(), sizeof(void *) * cnt_all, hipMemcpyHostToDevice, stream));
+    const DetDesc<T> *dd = (const DetDesc<T> *)sub_ddesc_;
+    std::vector<int> st(gj_.g);
+    for (int g0 = 0; g0 < cnt_all; g0 += gj_.g) {
+        const int cnt = std::min(gj_.g, cnt_all - g0);
+        CHK(timed(PH_RECOMPUTE, [&] {
+            hipError_t e = launch_build_pw_transpose(sub_pos_ + g0, gj_.mptr, cnt, sh.n, sh.np, kvec, twopi_l, stream);
+            if (e != hipSuccess) return e;
+            e = launch_gj_invert(gj_.gdesc, gj_.rdesc, cnt, sh.n, sh.np, gj_.nb, stream);
+            if (e != hipSuccess) return e;
+            e = launch_cast_perm<T>(gj_.gdesc, (T *const *)(sub_bt_ + g0), cnt, sh.n, sh.np, stream);
+            if (e != hipSuccess) return e;
+            return launch_reset_state<T>(dd + g0, gj_.gdesc, drift_ + g0, cnt, stream);
+        }));
+        HIPCHK(hipMemcpyAsync(st.data(), gj_.status, sizeof(int) * cnt, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        for (int i = 0; i < cnt; ++i)
+            if (st[i] != 0) return fail(DSU_ESINGULAR, "determinant %d: Slater matrix is singular", which[g0 + i]);
+    }
+    if (drift_host) {
+        HIPCHK(hipMemcpyAsync(drift_host, drift_, sizeof(double) * cnt_all, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+    return DSU_OK;
+}
+
+int Bucket::recompute(const std::vector<int> &which, double *drift_host) {
+    return sh.prec == DSU_FP64 ? recompute_t<double>(which, drift_host) : recompute_t<float>(which, drift_host);
+}
+
+// Plane-wave table: orbitals by shells s = |n|^2 = 0, 1, 2, ...; inside a
+// shell the integer vectors whose first nonzero component is positive, in
+// ascending (nx, ny, nz); n = 0 gives the constant, every other vector cos
+// then sin.
+int build_kvectors(int n, int4 *out) {
+    if (n <= 0) return -1;
+    int j = 0;
+    out[j++] = make_int4(0, 0, 0, 0);
+    for (int s = 1; j < n; ++s) {
+        const int r = (int)std::floor(std::sqrt((double)s)) + 1;
+        for (int x = -r; x <= r && j < n; ++x)
+            for (int y = -r; y <= r && j < n; ++y) {
+                const int rest = s - x * x - y * y;
+                if (rest < 0) continue;
+                const int z0 = (int)std::lround(std::sqrt((double)rest));
+                if (z0 * z0 != rest) continue;
+                const int zs[2] = {-z0, z0};
+                for (int q = 0; q < (z0 == 0 ? 1 : 2) && j < n; ++q) {
+                    const int z = zs[q];
+                    const bool rep = x > 0 || (x == 0 && (y > 0 || (y == 0 && z > 0)));
+                    if (!rep) continue;
+                    out[j++] = make_int4(x, y, z, 1);
+                    if (j < n) out[j++] = make_int4(x, y, z, 2);
+                }
+            }
+    }
+    return 0;
+}
+
+}  // namespace dsu
+
+// ==========================================================================
+// dsu_batch: one bucket over one contiguous block of determinant storage.
+// ==========================================================================
+using namespace dsu;
+
+struct dsu_batch {
+    Bucket bk;
+    int walkers = 0, spins = 1, ndet = 0, recompute_every = 0;
+    char *store = nullptr;
+    double *trace_r = nullptr;
+    uint8_t *trace_a = nullptr;
+    long long trace_cap = 0;
+    double *inv_tmp = nullptr;
+    long long sweeps_done = 0;
+};
+
+static void batch_free(dsu_batch *b) {
+    b->bk.release();
+    dfree(b->store);
+    dfree(b->trace_r);
+    dfree(b->trace_a);
+    dfree(b->inv_tmp);
+}
+
+static std::vector<int> all_indices(int n) {
+    std::vector<int> v(n);
+    for (int i = 0; i < n; ++i) v[i] = i;
+    return v;
+}
+
+extern "C" size_t dsu_footprint_bytes(int32_t n, int32_t k_delay, int32_t precision) {
+    if (n < 1 || n > 32768 || k_delay < 1 || k_delay > DSU_MAX_K ||
+        (precision != DSU_FP64 && precision != DSU_FP32_MIXED))
+        return 0;
+    return BucketShape::make(n, k_delay, precision).det_bytes();
+}
+
+extern "C" int dsu_batch_create(int32_t walkers, int32_t n, int32_t spins, int32_t k_delay, int32_t precision,
+                                double box_L, const uint64_t *seeds, const uint64_t *walker_ids, const double *sigma,
+                                const double *positions_host, int32_t recompute_every, void *hip_stream,
+                                dsu_batch **out) {
+    if (!out) return fail(DSU_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (walkers < 1) return fail(DSU_EINVAL, "walkers = %d", walkers);
+    if (n < 1 || n > 32768) return fail(DSU_EINVAL, "n = %d out of range [1, 32768]", n);
+    if (spins != 1 && spins != 2) return fail(DSU_EINVAL, "spins must be 1 or 2");
+    if (k_delay < 1 || k_delay > DSU_MAX_K) return fail(DSU_EINVAL, "k_delay = %d out of range [1, %d]", k_delay, DSU_MAX_K);
+    if (precision != DSU_FP64 && precision != DSU_FP32_MIXED) return fail(DSU_EINVAL, "bad precision %d", precision);
+    if (!(box_L > 0)) return fail(DSU_EINVAL, "box_L must be positive");
+    if (!seeds || !walker_ids || !sigma || !positions_host) return fail(DSU_EINVAL, "NULL input array");
+    if (recompute_every < 0) return fail(DSU_EINVAL, "recompute_every < 0");
+    dsu_batch *b = new dsu_batch();
+    b->walkers = walkers;
+    b->spins = spins;
+    b->ndet = walkers * spins;
+    b->recompute_every = recompute_every;
+    const BucketShape sh = BucketShape::make(n, k_delay, precision);
+    // recompute as many determinants at once as fit in ~8 GiB of workspace
+    const size_t per = GjWork::bytes_per(sh.np, n);
+    int group = (int)std::min<size_t>((size_t)b->ndet, std::max<size_t>(1, ((size_t)8 << 30) / per));
+    int rc = b->bk.init(sh, k_delay, box_L, hip_stream, group);
+    if (rc == DSU_OK) rc = dev_alloc((void **)&b->store, sh.det_bytes() * b->ndet);
+    if (rc != DSU_OK) {
+        batch_free(b);
+        delete b;
+        return rc;
+    }
+    std::vector<DetSlot> slots(b->ndet);
+    std::vector<DetState> st(b->ndet);
+    for (int i = 0; i < b->ndet; ++i) {
+        const int w = i / spins;
+        DetSlot &s = slots[i];
+        s = sh.carve(b->store + sh.det_bytes() * i);
+        s.seed = seeds[w];
+        s.wid = walker_ids[w];
+        s.sigma = sigma[w];
+        s.spin = i % spins;
+        st[i] = DetState{0.0, 1, 0, 0, 0, 0};
+        if (hipMemcpy(s.pos, positions_host + (size_t)n * 3 * i, sizeof(double) * n * 3, hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(s.st, &st[i], sizeof(DetState), hipMemcpyHostToDevice) != hipSuccess) {
+            batch_free(b);
+            delete b;
+            return fail(DSU_EDEVICE, "upload of walker state failed");
+        }
+    }
+    rc = b->bk.set_dets(slots);
+    if (rc == DSU_OK) rc = b->bk.recompute(all_indices(b->ndet), nullptr);
+    if (rc != DSU_OK) {
+        batch_free(b);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_destroy(dsu_batch *b) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    batch_free(b);
+    delete b;
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_sweep(dsu_batch *b, int32_t sweeps, int32_t force_accept) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (sweeps < 0) return fail(DSU_EINVAL, "sweeps < 0");
+    for (int s = 0; s < sweeps; ++s) {
+        if (b->recompute_every > 0 && b->sweeps_done > 0 && b->sweeps_done % b->recompute_every == 0)
+            CHK(b->bk.recompute(all_indices(b->ndet), nullptr));
+        CHK(b->bk.sweep(force_accept ? 1 : 0));
+        ++b->sweeps_done;
+    }
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_sync(dsu_batch *b) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_recompute(dsu_batch *b, double *drift_out) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    return b->bk.recompute(all_indices(b->ndet), drift_out);
+}
+
+extern "C" int dsu_batch_set_delay(dsu_batch *b, int32_t k_delay) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    return b->bk.set_delay(k_delay);
+}
+
+extern "C" int dsu_batch_stats(dsu_batch *b, double *logdet, int32_t *sign, int64_t *accepted, int64_t *sweeps_done) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    for (int i = 0; i < b->ndet; ++i) {
+        DetState st;
+        HIPCHK(hipMemcpy(&st, b->bk.dets[i].st, sizeof(st), hipMemcpyDeviceToHost));
+        if (logdet) logdet[i] = st.logdet;
+        if (sign) sign[i] = st.sign;
+        if (accepted) accepted[i] = st.accepted;
+        if (sweeps_done) sweeps_done[i] = st.sweep;
+    }
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_get_positions(dsu_batch *b, int32_t det, double *out_host) {
+    if (!b || !out_host) return fail(DSU_EINVAL, "NULL argument");
+    if (det < 0 || det >= b->ndet) return fail(DSU_EINVAL, "det %d out of range", det);
+    HIPCHK(hipMemcpyAsync(out_host, b->bk.dets[det].pos, sizeof(double) * b->bk.sh.n * 3, hipMemcpyDeviceToHost,
+                          b->bk.stream));
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_get_inverse(dsu_batch *b, int32_t det, double *out_host) {
+    if (!b || !out_host) return fail(DSU_EINVAL, "NULL argument");
+    if (det < 0 || det >= b->ndet) return fail(DSU_EINVAL, "det %d out of range", det);
+    const int n = b->bk.sh.n, np = b->bk.sh.np;
+    if (!b->inv_tmp) CHK(dalloc(&b->inv_tmp, (size_t)n * n));
+    if (b->bk.sh.prec == DSU_FP64)
+        HIPCHK(launch_untranspose<double>((const double *)b->bk.dets[det].bt, b->inv_tmp, n, np, b->bk.stream));
+    else
+        HIPCHK(launch_untranspose<float>((const float *)b->bk.dets[det].bt, b->inv_tmp, n, np, b->bk.stream));
+    HIPCHK(hipMemcpyAsync(out_host, b->inv_tmp, sizeof(double) * n * n, hipMemcpyDeviceToHost, b->bk.stream));
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_set_trace(dsu_batch *b, int32_t sweeps) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (sweeps < 0) return fail(DSU_EINVAL, "sweeps < 0");
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    dfree(b->trace_r);
+    dfree(b->trace_a);
+    b->trace_r = nullptr;
+    b->trace_a = nullptr;
+    b->trace_cap = (long long)sweeps * b->bk.sh.n;
+    if (sweeps > 0) {
+        CHK(dalloc(&b->trace_r, (size_t)b->trace_cap * b->ndet));
+        CHK(dalloc(&b->trace_a, (size_t)b->trace_cap * b->ndet));
+    }
+    std::vector<DetSlot> slots = b->bk.dets;
+    for (int i = 0; i < b->ndet; ++i) {
+        slots[i].trace_r = b->trace_r ? b->trace_r + (size_t)b->trace_cap * i : nullptr;
+        slots[i].trace_a = b->trace_a ? b->trace_a + (size_t)b->trace_cap * i : nullptr;
+        slots[i].trace_cap = b->trace_r ? b->trace_cap : 0;
+        DetState st;
+        HIPCHK(hipMemcpy(&st, slots[i].st, sizeof(st), hipMemcpyDeviceToHost));
+        st.trace_pos = 0;
+        HIPCHK(hipMemcpy(slots[i].st, &st, sizeof(st), hipMemcpyHostToDevice));
+    }
+    return b->bk.set_dets(slots);
+}
+
+extern "C" int dsu_batch_get_trace(dsu_batch *b, int32_t det, double *ratio_host, uint8_t *accepted_host) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (det < 0 || det >= b->ndet) return fail(DSU_EINVAL, "det %d out of range", det);
+    if (!b->trace_r) return fail(DSU_ESTATE, "tracing is off");
+    if (ratio_host)
+        HIPCHK(hipMemcpyAsync(ratio_host, b->trace_r + (size_t)b->trace_cap * det, sizeof(double) * b->trace_cap,
+                              hipMemcpyDeviceToHost, b->bk.stream));
+    if (accepted_host)
+        HIPCHK(hipMemcpyAsync(accepted_host, b->trace_a + (size_t)b->trace_cap * det, b->trace_cap,
+                              hipMemcpyDeviceToHost, b->bk.stream));
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_set_timing(dsu_batch *b, int32_t enable) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    CHK(b->bk.harvest_events());
+    b->bk.timing = enable != 0;
+    for (int p = 0; p < PH_COUNT; ++p) {
+        b->bk.t_ms[p] = 0;
+        b->bk.t_count[p] = 0;
+    }
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_kernel_time(dsu_batch *b, int32_t phase, int64_t *launches, double *total_ms) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (phase < 0 || phase >= PH_COUNT) return fail(DSU_EINVAL, "bad phase %d", phase);
+    CHK(b->bk.harvest_events());
+    if (launches) *launches = b->bk.t_count[phase];
+    if (total_ms) *total_ms = b->bk.t_ms[phase];
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_use_graph(dsu_batch *b, int32_t enable) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    b->bk.use_graph = enable != 0;
+    return DSU_OK;
+}

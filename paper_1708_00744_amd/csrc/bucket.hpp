@@ -1,0 +1,90 @@
+// bucket.hpp -- a lock-step group of same-size determinants of the batched
+// form.  A bucket owns the launch machinery (descriptor arrays, stream,
+// recompute workspace, optional hipGraph of a sweep, kernel timing); the
+// determinants' storage belongs to whoever created them (one contiguous
+// block for dsu_batch, an arena for dsu_server), so members can join and
+// leave between sweeps.
+#pragma once
+#include <utility>
+#include <vector>
+
+#include "host_common.hpp"
+
+namespace dsu {
+
+// Device storage of one determinant.
+struct DetSlot {
+    void *bt = nullptr, *u = nullptr, *vg = nullptr, *gpart = nullptr;
+    double *cfl = nullptr, *cwork = nullptr, *gwork = nullptr, *prop = nullptr, *pos = nullptr;
+    int *idx = nullptr;
+    DetState *st = nullptr;
+    double *trace_r = nullptr;
+    uint8_t *trace_a = nullptr;
+    long long trace_cap = 0;
+    uint64_t seed = 0, wid = 0;
+    double sigma = 0.0;
+    int spin = 0;
+};
+
+// Sizes shared by every determinant of a bucket.
+struct BucketShape {
+    int n = 0, np = 0, kmax = 0, kp = 0, prec = 0, nsplit = 1;
+    static BucketShape make(int n, int kmax, int prec);
+    size_t det_bytes() const;            // one determinant's storage, 256-byte aligned pieces
+    DetSlot carve(char *base) const;     // split a det_bytes() block into its arrays
+};
+
+enum { PH_ROWS = 0, PH_G = 1, PH_DECIDE = 2, PH_FLUSH = 3, PH_RECOMPUTE = 4, PH_COUNT = 5 };
+
+class Bucket {
+  public:
+    BucketShape sh;
+    int K = 0;  // current delay (<= sh.kmax)
+    double L = 0.0, twopi_l = 0.0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int4 *kvec = nullptr;
+    std::vector<DetSlot> dets;
+    bool use_graph = false;
+    bool timing = false;
+
+    int init(const BucketShape &shape, int k_delay, double box_l, void *stream_or_null, int gj_group);
+    void release();
+    // Replace the member list (descriptors re-uploaded, graph invalidated).
+    int set_dets(const std::vector<DetSlot> &d);
+    int set_delay(int k);
+    // One sweep of every member, stream ordered.
+    int sweep(int force_accept);
+    // FP64 recompute of the listed members (indices into dets); waits for it
+    // and reports a singular matrix.  drift_dev (optional, per listed member)
+    // receives running-minus-fresh log|det|.
+    int recompute(const std::vector<int> &which, double *drift_host);
+    int harvest_events();
+    long long t_count[PH_COUNT] = {0};
+    double t_ms[PH_COUNT] = {0};
+
+  private:
+    int cap_ = 0;
+    void *ddesc_ = nullptr, *fdesc_ = nullptr;
+    void *sub_ddesc_ = nullptr;
+    double **sub_pos_ = nullptr;
+    void **sub_bt_ = nullptr;
+    double *drift_ = nullptr;
+    GjWork gj_;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t gexec_ = nullptr;
+    int graph_force_ = -1;
+    std::vector<hipEvent_t> ev_free_;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used_;
+
+    int ensure_capacity(int n);
+    int enqueue_sweep(int force_accept);
+    int build_graph(int force_accept);
+    void drop_graph();
+    template <typename F> int timed(int phase, F fn);
+    template <typename T> int upload_t();
+    template <typename T> int enqueue_sweep_t(int force_accept);
+    template <typename T> int recompute_t(const std::vector<int> &which, double *drift_host);
+};
+
+}  // namespace dsu

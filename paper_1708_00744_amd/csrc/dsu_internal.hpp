@@ -21,6 +21,8 @@ constexpr int kThreads = 256;    // 4 wave64 per workgroup
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // ----------------------------------------------------------------- MFMA
+// Result row of accumulator element i in lane `lane` of a 16x16 tile:
+//     Mma<T>::row0(lane) + i * Mma<T>::row_step,   column lane % 16.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -29,13 +31,18 @@ template <> struct Mma<float> {
     typedef f32x4 acc_t;
     // v_mfma_f32_16x16x4_f32: D(16x16) += A(16x4) B(4x16); lane l supplies
     // A[l%16][l/16] and B[l/16][l%16]; D[4*(l/16)+i][l%16] lands in acc[i].
+    static __device__ __forceinline__ int row0(int lane) { return 4 * (lane >> 4); }
+    static constexpr int row_step = 1;
     static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
 };
 template <> struct Mma<double> {
     typedef f64x4 acc_t;
-    // v_mfma_f64_16x16x4_f64: same operand and result layout as above.
+    // v_mfma_f64_16x16x4_f64: same A and B layout as above, but the result
+    // rows interleave: D[(l/16) + 4*i][l%16] lands in acc[i].
+    static __device__ __forceinline__ int row0(int lane) { return lane >> 4; }
+    static constexpr int row_step = 4;
     static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -156,19 +163,17 @@ hipError_t launch_walker_accept(WalkerDev *wd, int n, int np, int k, int kp, int
 // Row copy into a padded device row: mode 0 FP64->FP64, 1 FP64->float, 2 float->FP64.
 hipError_t launch_row_to(const double *src, void *dst, int mode, int n, int np, hipStream_t s);
 
-// Batched window kernels.
+// Batched window kernels.  ktile = padded delay of the launch (template tile
+// count, 16..256), kp = padded delay the buffers were allocated for (stride).
 template <typename T>
-hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int kp, int e0, int kw,
-                              const int4 *kvec, double twopi_over_l, double box_l, hipStream_t s);
+hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
+                              const int4 *kvec, double twopi_over_l, hipStream_t s);
 template <typename T>
-hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int n, int np, int kp, int e0, int kw, int nsplit,
+hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int e0, int nsplit,
                            hipStream_t s);
 template <typename T>
-hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int n, int kp, int e0, int kw, int nsplit,
+hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int nsplit,
                                 int force_accept, int last_window, hipStream_t s);
-template <typename T>
-hipError_t launch_window_flush(const DetDesc<T> *d, const FlushDesc<T> *fd, int ndesc, int n, int np, int kw,
-                               hipStream_t s);
 template <typename T>
 hipError_t launch_reset_state(const DetDesc<T> *d, const GjDesc *gj, double *drift, int ndesc, hipStream_t s);
 

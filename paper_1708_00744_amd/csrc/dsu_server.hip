@@ -1,17 +1,433 @@
-// dsu_server.hip -- serving pool (continuous batching of walkers of mixed n).
+// dsu_server.hip -- the serving pool: walkers of mixed size admitted by a
+// device-memory budget and continuously batched.
+//
+// * One device allocation of `budget` bytes is the arena every walker's
+//   state (inverses, delayed buffers, positions) is carved from (first fit,
+//   coalescing free list).  A request waits until its footprint fits.
+// * Walkers of the same n share a Bucket (lock-step windows, one launch per
+//   phase for all of them) on the bucket's own stream; buckets of different
+//   n run concurrently on the device.
+// * Membership changes only between a bucket's sweeps: arrivals join and
+//   finished walkers leave at the next sweep boundary of their bucket, while
+//   the other buckets keep running.
+// * Every walker draws from its own counter-based stream keyed by (request
+//   seed, request id), so its result does not depend on what else is resident.
 #include <hip/hip_runtime.h>
 
-#include "dsu.h"
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <memory>
+#include <thread>
+#include <vector>
 
-struct dsu_server {
-    int dummy;
+#include "bucket.hpp"
+
+using namespace dsu;
+
+namespace {
+
+// First-fit allocator over [0, size) with coalescing.
+class Arena {
+  public:
+    size_t size = 0, used = 0;
+    void reset(size_t sz) {
+        size = sz;
+        used = 0;
+        free_.clear();
+        if (sz) free_[0] = sz;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                used += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        used -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<size_t, size_t> free_;
 };
 
-extern "C" int dsu_server_create(int32_t, int32_t, double, size_t, int32_t, dsu_server **out) {
-    if (out) *out = nullptr;
-    return DSU_ESTATE;
+struct Resident {
+    uint64_t request_id = 0;
+    int n = 0, spins = 1, sweeps_target = 0, sweeps_done = 0;
+    size_t off = 0, bytes = 0;
+    std::vector<DetSlot> dets;
+    double admit_s = 0.0, last_s = 0.0;
+    int result_index = -1;
+};
+
+struct BucketState {
+    Bucket bk;
+    std::vector<int> members;  // slot ids, in descriptor order
+    bool busy = false;
+    bool dirty = false;
+    hipEvent_t done = nullptr;
+};
+
+}  // namespace
+
+struct dsu_server {
+    int K = 0, prec = 0, recompute_every = 0;
+    double L = 0.0;
+    size_t budget = 0;
+    char *arena_base = nullptr;
+    Arena arena;
+    std::map<int, std::unique_ptr<BucketState>> buckets;
+    std::map<int, Resident> resident;  // slot -> walker
+    int next_slot = 0;
+};
+
+static int bucket_for(dsu_server *s, int n, BucketState **out) {
+    auto it = s->buckets.find(n);
+    if (it != s->buckets.end()) {
+        *out = it->second.get();
+        return DSU_OK;
+    }
+    std::unique_ptr<BucketState> b(new BucketState());
+    const BucketShape sh = BucketShape::make(n, s->K, s->prec);
+    int rc = b->bk.init(sh, s->K, s->L, nullptr, 1);
+    if (rc != DSU_OK) {
+        b->bk.release();
+        return rc;
+    }
+    if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        b->bk.release();
+        return fail(DSU_EDEVICE, "hipEventCreate failed");
+    }
+    *out = b.get();
+    s->buckets[n] = std::move(b);
+    return DSU_OK;
 }
-extern "C" int dsu_server_destroy(dsu_server *) { return DSU_ESTATE; }
-extern "C" int dsu_server_run(dsu_server *, const dsu_request *, int32_t, dsu_result *, double *, int64_t, int64_t *) {
-    return DSU_ESTATE;
+
+static size_t walker_bytes(int n, int spins, int K, int prec) {
+    return BucketShape::make(n, K, prec).det_bytes() * (size_t)spins;
+}
+
+// Upload the member list of a bucket (it must be idle).
+static int refresh_bucket(dsu_server *s, BucketState *b) {
+    std::vector<DetSlot> d;
+    for (int slot : b->members)
+        for (const DetSlot &x : s->resident[slot].dets) d.push_back(x);
+    b->dirty = false;
+    return b->bk.set_dets(d);
+}
+
+// Admit one request (its bucket must be idle).  DSU_EBUDGET if it does not fit now.
+static int admit(dsu_server *s, const dsu_request &r, double now_s, int result_index, int *slot_out) {
+    if (r.n < 1 || r.n > 32768 || (r.spins != 1 && r.spins != 2) || r.sweeps < 0 || !r.positions)
+        return fail(DSU_EINVAL, "bad request %llu", (unsigned long long)r.request_id);
+    const size_t bytes = walker_bytes(r.n, r.spins, s->K, s->prec);
+    if (bytes > s->budget) return fail(DSU_EINVAL, "request %llu needs %zu bytes, budget %zu", (unsigned long long)r.request_id, bytes, s->budget);
+    size_t off = 0;
+    if (!s->arena.alloc(bytes, &off)) return fail(DSU_EBUDGET, "request does not fit the free budget now");
+    BucketState *b = nullptr;
+    int rc = bucket_for(s, r.n, &b);
+    if (rc != DSU_OK) {
+        s->arena.release(off, bytes);
+        return rc;
+    }
+    const BucketShape &sh = b->bk.sh;
+    Resident w;
+    w.request_id = r.request_id;
+    w.n = r.n;
+    w.spins = r.spins;
+    w.sweeps_target = r.sweeps;
+    w.off = off;
+    w.bytes = bytes;
+    w.admit_s = now_s;
+    w.last_s = now_s;
+    w.result_index = result_index;
+    char *base = s->arena_base + off;
+    hipStream_t st = b->bk.stream;
+    HIPCHK(hipMemsetAsync(base, 0, bytes, st));
+    const DetState init{0.0, 1, 0, 0, 0, 0};
+    for (int sp = 0; sp < r.spins; ++sp) {
+        DetSlot d = sh.carve(base + sh.det_bytes() * sp);
+        d.seed = r.seed;
+        d.wid = r.request_id;
+        d.sigma = r.sigma;
+        d.spin = sp;
+        HIPCHK(hipMemcpyAsync(d.pos, r.positions + (size_t)sp * r.n * 3, sizeof(double) * r.n * 3,
+                              hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d.st, &init, sizeof(DetState), hipMemcpyHostToDevice, st));
+        w.dets.push_back(d);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    const int slot = s->next_slot++;
+    s->resident[slot] = w;
+    b->members.push_back(slot);
+    rc = refresh_bucket(s, b);
+    if (rc == DSU_OK) {
+        // FP64 inverse of the new walker's determinants (the last members).
+        std::vector<int> which;
+        for (int i = 0; i < r.spins; ++i) which.push_back((int)b->bk.dets.size() - r.spins + i);
+        rc = b->bk.recompute(which, nullptr);
+    }
+    if (rc != DSU_OK) {
+        b->members.pop_back();
+        s->resident.erase(slot);
+        s->arena.release(off, bytes);
+        (void)refresh_bucket(s, b);
+        return rc;
+    }
+    if (slot_out) *slot_out = slot;
+    return DSU_OK;
+}
+
+static int read_result(dsu_server *s, int slot, dsu_result *out) {
+    Resident &w = s->resident[slot];
+    out->request_id = w.request_id;
+    out->status = DSU_OK;
+    out->sweeps_done = w.sweeps_done;
+    out->admit_s = w.admit_s;
+    out->finish_s = w.last_s;
+    out->accepted = 0;
+    out->logdet[0] = out->logdet[1] = 0.0;
+    out->sign[0] = out->sign[1] = 0;
+    for (int sp = 0; sp < w.spins; ++sp) {
+        DetState st;
+        HIPCHK(hipMemcpy(&st, w.dets[sp].st, sizeof(st), hipMemcpyDeviceToHost));
+        out->logdet[sp] = st.logdet;
+        out->sign[sp] = st.sign;
+        out->accepted += st.accepted;
+    }
+    return DSU_OK;
+}
+
+static void retire(dsu_server *s, int slot) {
+    Resident &w = s->resident[slot];
+    s->arena.release(w.off, w.bytes);
+    auto it = s->buckets.find(w.n);
+    if (it != s->buckets.end()) {
+        auto &m = it->second->members;
+        m.erase(std::remove(m.begin(), m.end(), slot), m.end());
+        it->second->dirty = true;
+    }
+    s->resident.erase(slot);
+}
+
+// After a completed sweep of bucket b: recompute the walkers that are due.
+static int recompute_due(dsu_server *s, BucketState *b) {
+    if (s->recompute_every <= 0) return DSU_OK;
+    std::vector<int> which;
+    int pos = 0;
+    for (int slot : b->members) {
+        const Resident &w = s->resident[slot];
+        const bool due = w.sweeps_done > 0 && w.sweeps_done < w.sweeps_target &&
+                         w.sweeps_done % s->recompute_every == 0;
+        for (int sp = 0; sp < w.spins; ++sp, ++pos)
+            if (due) which.push_back(pos);
+    }
+    return b->bk.recompute(which, nullptr);
+}
+
+extern "C" int dsu_server_create(int32_t k_delay, int32_t precision, double box_L, size_t budget_bytes,
+                                 int32_t recompute_every, dsu_server **out) {
+    if (!out) return fail(DSU_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (k_delay < 1 || k_delay > DSU_MAX_K) return fail(DSU_EINVAL, "k_delay = %d out of range", k_delay);
+    if (precision != DSU_FP64 && precision != DSU_FP32_MIXED) return fail(DSU_EINVAL, "bad precision %d", precision);
+    if (!(box_L > 0)) return fail(DSU_EINVAL, "box_L must be positive");
+    if (budget_bytes < 4096) return fail(DSU_EINVAL, "budget too small");
+    if (recompute_every < 0) return fail(DSU_EINVAL, "recompute_every < 0");
+    dsu_server *s = new dsu_server();
+    s->K = k_delay;
+    s->prec = precision;
+    s->L = box_L;
+    s->budget = budget_bytes;
+    s->recompute_every = recompute_every;
+    hipError_t e = hipMalloc((void **)&s->arena_base, budget_bytes);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(DSU_ENOMEM, "arena of %zu bytes: %s", budget_bytes, hipGetErrorString(e));
+    }
+    s->arena.reset(budget_bytes);
+    *out = s;
+    return DSU_OK;
+}
+
+extern "C" int dsu_server_destroy(dsu_server *s) {
+    if (!s) return fail(DSU_EINVAL, "server is NULL");
+    for (auto &kv : s->buckets) {
+        kv.second->bk.release();
+        if (kv.second->done) (void)hipEventDestroy(kv.second->done);
+    }
+    s->buckets.clear();
+    dfree(s->arena_base);
+    delete s;
+    return DSU_OK;
+}
+
+extern "C" int dsu_server_add(dsu_server *s, const dsu_request *req, int32_t *slot_out) {
+    if (!s || !req) return fail(DSU_EINVAL, "NULL argument");
+    auto it = s->buckets.find(req->n);
+    if (it != s->buckets.end() && it->second->busy) return fail(DSU_ESTATE, "bucket busy");
+    return admit(s, *req, 0.0, -1, slot_out);
+}
+
+extern "C" int dsu_server_step(dsu_server *s) {
+    if (!s) return fail(DSU_EINVAL, "server is NULL");
+    for (auto &kv : s->buckets) {
+        BucketState *b = kv.second.get();
+        if (b->dirty) CHK(refresh_bucket(s, b));
+        if (b->members.empty()) continue;
+        CHK(b->bk.sweep(0));
+        HIPCHK(hipEventRecord(b->done, b->bk.stream));
+        b->busy = true;
+    }
+    for (auto &kv : s->buckets) {
+        BucketState *b = kv.second.get();
+        if (!b->busy) continue;
+        HIPCHK(hipEventSynchronize(b->done));
+        b->busy = false;
+        for (int slot : b->members) s->resident[slot].sweeps_done += 1;
+        CHK(recompute_due(s, b));
+    }
+    return DSU_OK;
+}
+
+extern "C" int dsu_server_result(dsu_server *s, int32_t slot, dsu_result *out, int32_t remove) {
+    if (!s || !out) return fail(DSU_EINVAL, "NULL argument");
+    if (!s->resident.count(slot)) return fail(DSU_EINVAL, "no walker in slot %d", slot);
+    const int n = s->resident[slot].n;
+    auto it = s->buckets.find(n);
+    if (it != s->buckets.end() && it->second->busy) return fail(DSU_ESTATE, "bucket busy");
+    CHK(read_result(s, slot, out));
+    if (remove) retire(s, slot);
+    return DSU_OK;
+}
+
+extern "C" int dsu_server_usage(dsu_server *s, size_t *used_bytes, int32_t *resident_walkers) {
+    if (!s) return fail(DSU_EINVAL, "server is NULL");
+    if (used_bytes) *used_bytes = s->arena.used;
+    if (resident_walkers) *resident_walkers = (int32_t)s->resident.size();
+    return DSU_OK;
+}
+
+extern "C" int dsu_server_run(dsu_server *s, const dsu_request *reqs, int32_t count, dsu_result *results,
+                              double *sweep_latency_ms, int64_t latency_cap, int64_t *latency_count) {
+    if (!s || (count > 0 && (!reqs || !results))) return fail(DSU_EINVAL, "NULL argument");
+    if (!s->resident.empty()) return fail(DSU_ESTATE, "server already has resident walkers");
+    typedef std::chrono::steady_clock clk;
+    const auto t0 = clk::now();
+    auto now_s = [&] { return std::chrono::duration<double>(clk::now() - t0).count(); };
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+    int next = 0, completed = 0;
+    int64_t nlat = 0;
+    std::deque<int> waiting;
+    for (int i = 0; i < count; ++i) {
+        results[i] = dsu_result{};
+        results[i].request_id = reqs[i].request_id;
+        results[i].status = DSU_EBUDGET;
+    }
+    while (completed < count) {
+        const double t = now_s();
+        while (next < count && reqs[order[next]].arrival_s <= t) waiting.push_back(order[next++]);
+        // sweep completions
+        for (auto &kv : s->buckets) {
+            BucketState *b = kv.second.get();
+            if (!b->busy) continue;
+            const hipError_t q = hipEventQuery(b->done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return fail(DSU_EDEVICE, "hipEventQuery: %s", hipGetErrorString(q));
+            b->busy = false;
+            const double td = now_s();
+            std::vector<int> finished;
+            for (int slot : b->members) {
+                Resident &w = s->resident[slot];
+                w.sweeps_done += 1;
+                if (sweep_latency_ms && nlat < latency_cap) sweep_latency_ms[nlat] = 1e3 * (td - w.last_s);
+                ++nlat;
+                w.last_s = td;
+                if (w.sweeps_done >= w.sweeps_target) finished.push_back(slot);
+            }
+            for (int slot : finished) {
+                dsu_result &res = results[s->resident[slot].result_index];
+                CHK(read_result(s, slot, &res));
+                retire(s, slot);
+                ++completed;
+            }
+            CHK(recompute_due(s, b));
+        }
+        // admission, first fit in arrival order, into idle buckets
+        for (auto it = waiting.begin(); it != waiting.end();) {
+            const dsu_request &r = reqs[*it];
+            auto bit = s->buckets.find(r.n);
+            if (bit != s->buckets.end() && bit->second->busy) {
+                ++it;
+                continue;
+            }
+            if (walker_bytes(r.n, r.spins, s->K, s->prec) > s->budget || r.sweeps == 0) {
+                results[*it].status = r.sweeps == 0 ? DSU_OK : DSU_EBUDGET;
+                results[*it].admit_s = results[*it].finish_s = now_s();
+                ++completed;
+                it = waiting.erase(it);
+                continue;
+            }
+            int slot = -1;
+            const int rc = admit(s, r, now_s(), *it, &slot);
+            if (rc == DSU_EBUDGET) {
+                ++it;
+                continue;
+            }
+            if (rc != DSU_OK) return rc;
+            it = waiting.erase(it);
+        }
+        // launch the next sweep of every idle, non-empty bucket
+        bool any_busy = false;
+        for (auto &kv : s->buckets) {
+            BucketState *b = kv.second.get();
+            if (!b->busy) {
+                if (b->dirty) CHK(refresh_bucket(s, b));
+                if (!b->members.empty()) {
+                    CHK(b->bk.sweep(0));
+                    HIPCHK(hipEventRecord(b->done, b->bk.stream));
+                    b->busy = true;
+                }
+            }
+            any_busy = any_busy || b->busy;
+        }
+        if (!any_busy) {
+            if (next < count) {
+                const double wait = reqs[order[next]].arrival_s - now_s();
+                if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+            } else if (!waiting.empty() && s->resident.empty()) {
+                return fail(DSU_EBUDGET, "waiting requests cannot be admitted into an empty pool");
+            }
+        } else {
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+    }
+    if (latency_count) *latency_count = std::min(nlat, latency_cap);
+    return DSU_OK;
 }

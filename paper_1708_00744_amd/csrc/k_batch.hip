@@ -75,8 +75,8 @@ __device__ __forceinline__ double pw_orbital(int4 kv, double twopi_l, double x, 
 // Vg (the stale BT rows e0..e0+kw-1, zero past kw).  Block 0 of a determinant
 // also stores the proposals for the decision kernel.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__restrict__ descs, int n, int np, int kp,
-                                                          int e0, int kw, const int4 *__restrict__ kvec,
+__global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__restrict__ descs, int n, int np,
+                                                          int ktile, int e0, int kw, const int4 *__restrict__ kvec,
                                                           double twopi_l) {
 #pragma clang fp contract(off)
     __shared__ double s_r[DSU_KMAX_LDS][3];
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__re
     __syncthreads();
     const int cols = np / gridDim.y;
     const int c_begin = blockIdx.y * cols;
-    for (int v = tid; v < kp * cols; v += kThreads) {
+    for (int v = tid; v < ktile * cols; v += kThreads) {
         const int a = v / cols, c = c_begin + v % cols;
         T val = T(0), vgv = T(0);
         if (a < kw) {
@@ -111,24 +111,24 @@ __global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__re
 }
 
 template <typename T>
-hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int kp, int e0, int kw,
-                              const int4 *kvec, double twopi_over_l, double box_l, hipStream_t s) {
-    (void)box_l;
+hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
+                              const int4 *kvec, double twopi_over_l, hipStream_t s) {
     int nsplit = np / 256;
     if (nsplit < 1) nsplit = 1;
     while (np % nsplit) --nsplit;
-    hipLaunchKernelGGL((k_window_rows<T>), dim3(ndesc, nsplit), dim3(kThreads), 0, s, d, n, np, kp, e0, kw, kvec,
+    hipLaunchKernelGGL((k_window_rows<T>), dim3(ndesc, nsplit), dim3(kThreads), 0, s, d, n, np, ktile, e0, kw, kvec,
                        twopi_over_l);
     return hipGetLastError();
 }
 template hipError_t launch_window_rows<float>(const DetDesc<float> *, int, int, int, int, int, int, const int4 *,
-                                              double, double, hipStream_t);
+                                              double, hipStream_t);
 template hipError_t launch_window_rows<double>(const DetDesc<double> *, int, int, int, int, int, int, const int4 *,
-                                               double, double, hipStream_t);
+                                               double, hipStream_t);
 
 // ---------------------------------------------- window look-ahead products
-// gpart[s][b][a] = sum over the s-th column range of BT[e0+b, c] * U[a, c].
-// grid: ndesc * nsplit * nrb, nrb = 64-row blocks covering kp rows.  Same
+// gpart[s][b][a] = sum over the s-th column range of BT[e0+b, c] * U[a, c]
+// (a, b < KP; row stride kp of the allocation).
+// grid: ndesc * nsplit * nrb, nrb = 64-row blocks covering KP rows.  Same
 // matrix-core tiling as the flush's first product (64 rows x KP columns).
 template <typename T, int KP>
 __global__ __launch_bounds__(kThreads) void k_window_g(const DetDesc<T> *__restrict__ descs, int np, int kp, int e0,
@@ -152,21 +152,19 @@ __global__ __launch_bounds__(kThreads) void k_window_g(const DetDesc<T> *__restr
     for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int br = rb * 64 + 16 * wave + 4 * (lane >> 4) + i;
+            const int br = rb * 64 + 16 * wave + Mma<T>::row0(lane) + i * Mma<T>::row_step;
             const int ac = 16 * t + (lane & 15);
-            if (br < kp) out[(size_t)br * kp + ac] = acc[t][i];
+            if (br < KP) out[(size_t)br * kp + ac] = acc[t][i];
         }
 }
 
 template <typename T>
-hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int n, int np, int kp, int e0, int kw, int nsplit,
+hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int e0, int nsplit,
                            hipStream_t s) {
-    (void)n;
-    (void)kw;
-    const int nrb = kp > 64 ? kp / 64 : 1;
+    const int nrb = ktile > 64 ? ktile / 64 : 1;
     const dim3 grid(ndesc * nsplit * nrb);
 #define DSU_G(KPV)                                                                                          \
-    if (kp == KPV) {                                                                                        \
+    if (ktile == KPV) {                                                                                     \
         hipLaunchKernelGGL((k_window_g<T, KPV>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);    \
         return hipGetLastError();                                                                           \
     }
@@ -174,8 +172,8 @@ hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int n, int np, int kp
 #undef DSU_G
     return hipErrorInvalidValue;
 }
-template hipError_t launch_window_g<float>(const DetDesc<float> *, int, int, int, int, int, int, int, hipStream_t);
-template hipError_t launch_window_g<double>(const DetDesc<double> *, int, int, int, int, int, int, int, hipStream_t);
+template hipError_t launch_window_g<float>(const DetDesc<float> *, int, int, int, int, int, int, hipStream_t);
+template hipError_t launch_window_g<double>(const DetDesc<double> *, int, int, int, int, int, int, hipStream_t);
 
 // ------------------------------------------------------ window decisions
 // One workgroup (max(64, KP) threads) per determinant.  Thread i owns row i
@@ -191,7 +189,7 @@ template <int KP> struct DecideCfg {
 
 template <typename T, int KP>
 __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const DetDesc<T> *__restrict__ descs,
-                                                                          int n, int kp, int e0, int kw, int nsplit,
+                                                                          int kp, int e0, int kw, int nsplit,
                                                                           int force_accept, int last_window) {
     typedef DecideCfg<KP> C;
     constexpr int LD = C::ld, NT = C::threads;
@@ -278,12 +276,12 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
     }
 
     // zero-embedded C^{-1} for the flush, electrons, positions, state, trace
-    for (int v = tid; v < kp * kp; v += NT) {
-        const int i = v / kp, j = v % kp;
-        const int pi = i < KP ? s_pos[i] : -1, pj = j < KP ? s_pos[j] : -1;
-        d.cfl[v] = (pi >= 0 && pj >= 0) ? Cm[pi * LD + pj] : 0.0;
+    for (int v = tid; v < KP * KP; v += NT) {
+        const int i = v / KP, j = v % KP;
+        const int pi = s_pos[i], pj = s_pos[j];
+        d.cfl[(size_t)i * kp + j] = (pi >= 0 && pj >= 0) ? Cm[pi * LD + pj] : 0.0;
     }
-    for (int a = tid; a < kp; a += NT) d.idx[a] = a < kw ? e0 + a : -1;
+    for (int a = tid; a < KP; a += NT) d.idx[a] = a < kw ? e0 + a : -1;
     for (int v = tid; v < kw * 3; v += NT) {
         const int a = v / 3, c = v % 3;
         if (s_ok[a]) d.pos[3 * (e0 + a) + c] = d.prop[4 * a + c];
@@ -308,11 +306,11 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
 }
 
 template <typename T>
-hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int n, int kp, int e0, int kw, int nsplit,
+hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int nsplit,
                                 int force_accept, int last_window, hipStream_t s) {
 #define DSU_D(KPV)                                                                                                \
-    if (kp == KPV) {                                                                                              \
-        hipLaunchKernelGGL((k_window_decide<T, KPV>), dim3(ndesc), dim3(DecideCfg<KPV>::threads), 0, s, d, n, kp, \
+    if (ktile == KPV) {                                                                                           \
+        hipLaunchKernelGGL((k_window_decide<T, KPV>), dim3(ndesc), dim3(DecideCfg<KPV>::threads), 0, s, d, kp,    \
                            e0, kw, nsplit, force_accept, last_window);                                            \
         return hipGetLastError();                                                                                 \
     }
@@ -324,17 +322,6 @@ template hipError_t launch_window_decide<float>(const DetDesc<float> *, int, int
                                                 hipStream_t);
 template hipError_t launch_window_decide<double>(const DetDesc<double> *, int, int, int, int, int, int, int, int,
                                                  hipStream_t);
-
-template <typename T>
-hipError_t launch_window_flush(const DetDesc<T> *d, const FlushDesc<T> *fd, int ndesc, int n, int np, int kw,
-                               hipStream_t s) {
-    (void)d;
-    return launch_flush<T>(fd, ndesc, n, np, kw, 0, s);
-}
-template hipError_t launch_window_flush<float>(const DetDesc<float> *, const FlushDesc<float> *, int, int, int, int,
-                                               hipStream_t);
-template hipError_t launch_window_flush<double>(const DetDesc<double> *, const FlushDesc<double> *, int, int, int,
-                                                int, hipStream_t);
 
 // ------------------------------------------------- Slater matrix, FP64
 // M[j][i] = phi_j(r_i) for i, j < n (the transpose of A), identity padding.

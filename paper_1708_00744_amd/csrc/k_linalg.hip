@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kThreads) void k_flush_mfma(const FlushDesc<T> *__r
 #pragma unroll
     for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) lds[(16 * wave + 4 * (lane >> 4) + i) * LDY + 16 * t + (lane & 15)] = acc[t][i];
+        for (int i = 0; i < 4; ++i) lds[(16 * wave + Mma<T>::row0(lane) + i * Mma<T>::row_step) * LDY + 16 * t + (lane & 15)] = acc[t][i];
     __syncthreads();
     for (int j = tid; j < kslots; j += kThreads) {
         const int e = fd.idx[j];
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void k_flush_mfma(const FlushDesc<T> *__r
 #pragma unroll
     for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) lds[(16 * wave + 4 * (lane >> 4) + i) * LDY + 16 * t + (lane & 15)] = wacc[t][i];
+        for (int i = 0; i < 4; ++i) lds[(16 * wave + Mma<T>::row0(lane) + i * Mma<T>::row_step) * LDY + 16 * t + (lane & 15)] = wacc[t][i];
     __syncthreads();
     T wa[KP / 4];
 #pragma unroll

@@ -90,7 +90,8 @@ __device__ __forceinline__ void rowblock_plus_wv(T *__restrict__ rows, int ld, i
     typedef Phase3Cfg<T, KP> C;
     constexpr int CW = C::CW, LDV = C::LDV, VEC = 16 / sizeof(T);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    T *rp = rows + (size_t)(wave * 16 + 4 * (lane >> 4)) * ld + (lane & 15);
+    constexpr int RS = Mma<T>::row_step;
+    T *rp = rows + (size_t)(wave * 16 + Mma<T>::row0(lane)) * ld + (lane & 15);
     for (int c0 = 0; c0 < ncols; c0 += CW) {
         for (int v = tid; v < KP * (CW / VEC); v += kThreads) {
             const int r = v / (CW / VEC), cc = (v % (CW / VEC)) * VEC;
@@ -101,7 +102,7 @@ __device__ __forceinline__ void rowblock_plus_wv(T *__restrict__ rows, int ld, i
 #pragma unroll
         for (int t = 0; t < CW / 16; ++t)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[t][i] = rp[(size_t)i * ld + c0 + 16 * t];
+            for (int i = 0; i < 4; ++i) acc[t][i] = rp[(size_t)(i * RS) * ld + c0 + 16 * t];
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < KP / 4; ++s) {
@@ -112,7 +113,7 @@ __device__ __forceinline__ void rowblock_plus_wv(T *__restrict__ rows, int ld, i
 #pragma unroll
         for (int t = 0; t < CW / 16; ++t)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) rp[(size_t)i * ld + c0 + 16 * t] = acc[t][i];
+            for (int i = 0; i < 4; ++i) rp[(size_t)(i * RS) * ld + c0 + 16 * t] = acc[t][i];
         __syncthreads();
     }
 }

@@ -78,9 +78,14 @@ SIGNATURES = {
     "dsu_batch_set_timing": (C.c_int, [_vp, _i32]),
     "dsu_batch_kernel_time": (C.c_int, [_vp, _i32, _pi64, _pd]),
     "dsu_batch_use_graph": (C.c_int, [_vp, _i32]),
+    "dsu_batch_set_delay": (C.c_int, [_vp, _i32]),
     "dsu_server_create": (C.c_int, [_i32, _i32, _dbl, _sz, _i32, _pvp]),
     "dsu_server_destroy": (C.c_int, [_vp]),
     "dsu_server_run": (C.c_int, [_vp, C.POINTER(Request), _i32, C.POINTER(Result), _pd, _i64, _pi64]),
+    "dsu_server_add": (C.c_int, [_vp, C.POINTER(Request), _pi32]),
+    "dsu_server_step": (C.c_int, [_vp]),
+    "dsu_server_result": (C.c_int, [_vp, _i32, C.POINTER(Result), _i32]),
+    "dsu_server_usage": (C.c_int, [_vp, C.POINTER(_sz), _pi32]),
 }
 
 
@@ -142,9 +147,9 @@ class Walker:
         self._h = h
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().dsu_walker_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dsu_walker_destroy(self._h)
+        self._h = None
 
     __del__ = close
 
@@ -218,9 +223,9 @@ class Batch:
         self._trace_sweeps = 0
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().dsu_batch_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dsu_batch_destroy(self._h)
+        self._h = None
 
     __del__ = close
 
@@ -281,3 +286,82 @@ class Batch:
 
     def use_graph(self, enable):
         _check(lib().dsu_batch_use_graph(self._h, int(bool(enable))))
+
+    def set_delay(self, k_delay):
+        _check(lib().dsu_batch_set_delay(self._h, int(k_delay)))
+        self.k_delay = int(k_delay)
+
+
+def _request(rid, n, spins, seed, sigma, sweeps, arrival_s, positions):
+    pos = _f64(positions, (spins * n * 3,))
+    r = Request(int(rid), int(n), int(spins), int(seed), float(sigma), int(sweeps), float(arrival_s),
+                pos.ctypes.data_as(_pd))
+    return r, pos
+
+
+def _result_dict(r):
+    return {"request_id": r.request_id, "status": r.status, "sweeps_done": r.sweeps_done, "admit_s": r.admit_s,
+            "finish_s": r.finish_s, "logdet": [r.logdet[0], r.logdet[1]], "sign": [r.sign[0], r.sign[1]],
+            "accepted": r.accepted}
+
+
+class Server:
+    """Serving pool (dsu_server_*): mixed-n walkers admitted by a device-memory
+    budget and continuously batched."""
+
+    def __init__(self, k_delay, precision=FP32_MIXED, box_l=10.0, budget_bytes=8 << 30, recompute_every=0):
+        h = C.c_void_p()
+        _check(lib().dsu_server_create(int(k_delay), int(precision), float(box_l), int(budget_bytes),
+                                       int(recompute_every), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dsu_server_destroy(self._h)
+        self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def add(self, rid, n, spins, seed, sigma, sweeps, positions):
+        r, keep = _request(rid, n, spins, seed, sigma, sweeps, 0.0, positions)
+        slot = C.c_int32()
+        _check(lib().dsu_server_add(self._h, C.byref(r), C.byref(slot)))
+        del keep
+        return slot.value
+
+    def step(self):
+        _check(lib().dsu_server_step(self._h))
+
+    def result(self, slot, remove=False):
+        out = Result()
+        _check(lib().dsu_server_result(self._h, int(slot), C.byref(out), int(bool(remove))))
+        return _result_dict(out)
+
+    def usage(self):
+        used, res = C.c_size_t(), C.c_int32()
+        _check(lib().dsu_server_usage(self._h, C.byref(used), C.byref(res)))
+        return used.value, res.value
+
+    def run(self, requests, latency_cap=1 << 20):
+        """requests: iterable of dicts with request_id, n, spins, seed, sigma,
+        sweeps, arrival_s, positions.  Returns (results, sweep latencies in ms)."""
+        reqs = list(requests)
+        arr = (Request * len(reqs))()
+        keep = []
+        for i, q in enumerate(reqs):
+            r, pos = _request(q["request_id"], q["n"], q["spins"], q["seed"], q["sigma"], q["sweeps"],
+                              q["arrival_s"], q["positions"])
+            arr[i] = r
+            keep.append(pos)
+        res = (Result * len(reqs))()
+        lat = np.zeros(latency_cap)
+        cnt = C.c_int64()
+        _check(lib().dsu_server_run(self._h, arr, len(reqs), res, _dp(lat), int(latency_cap), C.byref(cnt)))
+        del keep
+        return [_result_dict(r) for r in res], lat[:cnt.value]
