@@ -1,0 +1,291 @@
+#!/usr/bin/env python
+"""Benchmark of the delayed Slater-determinant update on one MI355X.
+
+Headline (`value`): electron moves per second of the FP32-batched delayed
+update on 32 walkers of N = 4096 (plane-wave orbitals, periodic box L = 10,
+acceptance ~0.99, K from the autotuner, FP64 recompute every 20 sweeps; a step
+is one sweep of every walker: N proposals each, their look-ahead ratios,
+Metropolis decisions and en-bloc Woodbury updates).  Beside it: moves/s vs K
+at N = 4096, the FP32 batch at N = 1024 and 2048, the plain FP64 single
+walker (host-driven through the C ABI, and device-driven), a short serving
+run (p50/p99 sweep latency), the flush kernel against the matrix-core
+roofline, and the CPU oracle timed on a bounded sample.
+
+All inputs are seeded and synthetic.  Usage:
+    python bench.py [--steps K] [--warmup W] [--quick] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BOX_L = 10.0
+PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
+PEAK_FP64_MFMA = 78.6    # TFLOP/s
+PEAK_HBM = 8000.0        # GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def batch_positions(n, walkers, spins=1, seed0=1000):
+    from paper_1708_00744_amd import inputs
+    return np.stack([inputs.positions(seed0 + w, w, spins * n, BOX_L).reshape(spins, n, 3) for w in range(walkers)])
+
+
+def sigma_or_default(n, target, cache):
+    from paper_1708_00744_amd import tune
+    s = tune.sigma_for(n, target, cache)
+    if s is None:
+        log(f"no tuned sigma for n={n} acc={target}: tuning now (not timed)")
+        s, _ = tune.tune_sigma(n, target)
+    return s
+
+
+def time_sweeps(b, steps, warmup, force=False):
+    import torch
+    b.sweep(warmup, force)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.sweep(steps, force)
+    b.sync()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def headline(args, cache):
+    from paper_1708_00744_amd import dsu, tune
+    n, walkers = 4096, 32
+    sigma = sigma_or_default(n, 0.99, cache)
+    dkey = tune.delay_key(n, walkers, dsu.FP32_MIXED)
+    K = int(cache["delay"].get(dkey, {}).get("best", 64))
+    pos = batch_positions(n, walkers)
+    t0 = time.perf_counter()
+    b = dsu.Batch(n, pos, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, 256,
+                  precision=dsu.FP32_MIXED, box_l=BOX_L, recompute_every=20)
+    setup_s = time.perf_counter() - t0
+    b.set_delay(K)
+    b.sweep(args.warmup)
+    b.sync()
+    b.set_timing(True)
+    dt = time_sweeps(b, args.steps, 0)
+    st = b.stats()
+    cnt, ms = b.kernel_time(dsu.PHASE_FLUSH)
+    phases = {name: b.kernel_time(p) for name, p in (("rows", dsu.PHASE_ROWS), ("lookahead_G", dsu.PHASE_G),
+                                                      ("decide", dsu.PHASE_DECIDE), ("flush", dsu.PHASE_FLUSH),
+                                                      ("recompute", dsu.PHASE_RECOMPUTE))}
+    b.set_timing(False)
+    moves = walkers * n * args.steps
+    acc = float(st["accepted"].sum()) / (walkers * n * (args.steps + args.warmup))
+    # flush roofline: algorithmic work of one launch = every walker's rank-K update
+    avg_s = ms / cnt / 1e3
+    flops = walkers * (4.0 * n * n * K + 2.0 * n * K * K)
+    bytes_ = walkers * 2.0 * n * n * 4
+    intensity = flops / bytes_
+    if intensity > PEAK_FP32_MFMA * 1e12 / (PEAK_HBM * 1e9):
+        roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = "k_flush_mfma<float,%d>" % (16 if K <= 16 else 1 << math.ceil(math.log2(K)))
+    roof["avg_launch_ms"] = ms / cnt
+    roof["launches"] = cnt
+    roof["flops_per_launch"] = flops
+    roof["bytes_per_launch"] = bytes_
+    out = {
+        "moves_per_s": moves / dt, "ms_per_step": 1e3 * dt / args.steps, "K": K, "sigma": sigma,
+        "acceptance": acc, "setup_s": setup_s,
+        "phase_ms_per_sweep": {k: v[1] / args.steps for k, v in phases.items()},
+        "roofline": roof, "batch": b,
+    }
+    return out
+
+
+def k_curve(b, steps=1):
+    from paper_1708_00744_amd import dsu
+    res = {}
+    for k in (32, 64, 128, 256):
+        b.set_delay(k)
+        dt = time_sweeps(b, steps, 1)
+        res[str(k)] = b.walkers * b.n * steps / dt
+    return res
+
+
+def batched_at(n, walkers, cache, steps=2):
+    from paper_1708_00744_amd import dsu, tune
+    sigma = sigma_or_default(n, 0.99, cache)
+    K = int(cache["delay"].get(tune.delay_key(n, walkers, dsu.FP32_MIXED), {}).get("best", 64))
+    pos = batch_positions(n, walkers)
+    with dsu.Batch(n, pos, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, K,
+                   precision=dsu.FP32_MIXED, box_l=BOX_L) as b:
+        dt = time_sweeps(b, steps, 1)
+    return {"walkers": walkers, "K": K, "moves_per_s": walkers * n * steps / dt}
+
+
+def fp64_single_walker(cache, n=1024, sweeps=1):
+    """The plain FP64 single-walker form: host-driven through the C ABI (one
+    propose/accept call per move, host decisions), plane-wave rows from the
+    library, and the same walker driven on the device (a batch of one)."""
+    from paper_1708_00744_amd import dsu, inputs
+    sigma = sigma_or_default(n, 0.99, cache)
+    pos0 = inputs.positions(2, 0, n, BOX_L)
+    res = {"n": n, "sigma": sigma}
+    a0 = dsu.plane_wave_rows(n, BOX_L, pos0)
+    for K in (1, 16, 64):
+        pos = pos0.copy()
+        g = inputs.normals(3, (sweeps, n, 3))
+        us = inputs.uniforms(4, sweeps * n)
+        with dsu.Walker(a0, K, precision=dsu.FP64, policy=dsu.FLUSH_K_ACCEPTED) as w:
+            t0 = time.perf_counter()
+            for s in range(sweeps):
+                prop = pos + sigma * g[s]
+                rows = dsu.plane_wave_rows(n, BOX_L, prop)
+                for e in range(n):
+                    r = w.propose(e, rows[e])
+                    if us[s * n + e] < r * r:
+                        w.accept()
+                        pos[e] = prop[e]
+                    else:
+                        w.reject()
+            w.flush()
+            dt = time.perf_counter() - t0
+        res[f"host_driven_K{K}"] = n * sweeps / dt
+    for K in (1, 64):
+        with dsu.Batch(n, pos0[None], [2], [0], sigma, K, precision=dsu.FP64, box_l=BOX_L) as b:
+            dt = time_sweeps(b, 2, 1)
+        res[f"device_driven_K{K}"] = n * 2 / dt
+    return res
+
+
+def serving(cache, count=40, seed=7):
+    from paper_1708_00744_amd import dsu, inputs
+    sizes, accs, seeds = inputs.serving_mix(seed, count)
+    reqs = []
+    for i in range(count):
+        n = int(sizes[i])
+        s = sigma_or_default(n, float(accs[i]), cache) if n <= 2048 else 0.01
+        reqs.append({"request_id": i, "n": n, "spins": 2, "seed": int(seeds[i]), "sigma": s, "sweeps": 20,
+                     "arrival_s": 0.0, "positions": inputs.positions(int(seeds[i]), i, 2 * n, BOX_L)})
+    # arrivals: Poisson at the rate that keeps the pool busy (about one
+    # request per mean service time of a small walker)
+    arr = inputs.poisson_arrivals(seed, count, rate_per_s=40.0)
+    for q, t in zip(reqs, arr):
+        q["arrival_s"] = float(t)
+    with dsu.Server(64, precision=dsu.FP32_MIXED, box_l=BOX_L, budget_bytes=8 << 30, recompute_every=10) as srv:
+        t0 = time.perf_counter()
+        results, lat = srv.run(reqs)
+        wall = time.perf_counter() - t0
+    moves = sum(2 * q["n"] * q["sweeps"] for q, r in zip(reqs, results) if r["status"] == 0)
+    e2e = [r["finish_s"] - q["arrival_s"] for q, r in zip(reqs, results) if r["status"] == 0]
+    wait = [r["admit_s"] - q["arrival_s"] for q, r in zip(reqs, results) if r["status"] == 0]
+    return {"requests": count, "wall_s": wall, "moves_per_s": moves / wall,
+            "sweep_latency_ms_p50": float(np.percentile(lat, 50)), "sweep_latency_ms_p99": float(np.percentile(lat, 99)),
+            "queue_wait_s_p50": float(np.percentile(wait, 50)), "end_to_end_s_p99": float(np.percentile(e2e, 99))}
+
+
+def cpu_baseline(n=4096, sigma=0.002, target_s=15.0):
+    """The oracle (plain FP64 Sherman-Morrison in C) on the host cores: a
+    bounded sample of the headline workload -- one thread per walker, each
+    running the first moves of sweep 0 from a fresh inverse (set-up not timed)."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, 16))
+    walkers = threads
+    kv = oracle.pw_kvectors(n)
+    pos = batch_positions(n, walkers)[:, 0]
+    pos = np.ascontiguousarray(pos)
+    a = np.stack([oracle.pw_matrix(kv, BOX_L, pos[w]) for w in range(walkers)])
+    ainv = np.ascontiguousarray(np.stack([np.linalg.inv(a[w]) for w in range(walkers)]))
+    # calibrate the sample size with 4 moves
+    t0 = time.perf_counter()
+    oracle.walkers_moves(n, BOX_L, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, 0, 0, 4,
+                         pos, a, ainv)
+    per = (time.perf_counter() - t0) / 4
+    m = max(8, int(target_s / max(per, 1e-6)))
+    t0 = time.perf_counter()
+    _, used = oracle.walkers_moves(n, BOX_L, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, 0, 4, m,
+                                   pos, a, ainv)
+    dt = time.perf_counter() - t0
+    return {"value": walkers * m / dt, "unit": "moves/s", "cores": int(used), "kind": "oracle",
+            "sample": f"{walkers} walkers x {m} moves of sweep 0 at N={n} (FP64 Sherman-Morrison, one OpenMP thread "
+                      f"per walker, set-up by LAPACK inverse not timed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--quick", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "bench.py measures one GPU: walkers shard across GPUs with no communication, "
+                                   "so only --gpus 1 is supported"}))
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        return 1
+    torch.cuda.set_device(0)
+    from paper_1708_00744_amd import dsu, tune
+    dsu.lib()
+    cache = tune.load_cache()
+    log("headline: 32 walkers, N=4096, FP32 batched")
+    h = headline(args, cache)
+    b = h.pop("batch")
+    extras = {}
+    if not args.quick:
+        log("K curve")
+        extras["k_curve_n4096_moves_per_s"] = k_curve(b)
+    b.close()
+    if not args.quick:
+        log("batched N=1024 / 2048")
+        extras["fp32_batched_n1024"] = batched_at(1024, 256, cache)
+        extras["fp32_batched_n2048"] = batched_at(2048, 64, cache)
+        log("FP64 single walker N=1024")
+        extras["fp64_single_walker_n1024"] = fp64_single_walker(cache)
+        log("serving")
+        extras["serving"] = serving(cache)
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(sigma=h["sigma"])
+    roof = h.pop("roofline")
+    line = {
+        "metric": "electron moves/sec/GPU (FP32-batched delayed update, N=4096)",
+        "value": h["moves_per_s"],
+        "unit": "moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (FP64 recompute and log-det)",
+        "data": "synthetic: seeded uniform positions, plane-wave orbitals, device Philox4x64-10 moves",
+        "config": {"workload": "32 walkers x N=4096 Slater matrices, K=%d, acceptance %.3f, FP64 recompute every 20 "
+                               "sweeps; step = one sweep of every walker" % (h["K"], h["acceptance"]),
+                   "walkers": 32, "n": 4096, "K": h["K"], "sigma": h["sigma"], "precision": "fp32_mixed"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "detail": {k: v for k, v in h.items() if k not in ("moves_per_s", "ms_per_step")},
+        "extras": extras,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -79,6 +79,18 @@ int dsu_version(void);
  * recompute workspace.  0 on a bad argument. */
 size_t dsu_footprint_bytes(int32_t n, int32_t k_delay, int32_t precision);
 
+/* Plane-wave orbitals phi_j(r) = 1, cos(k.r), sin(k.r), k = (2 pi / L) n
+ * (n integer; shells of |n|^2 in ascending order, inside a shell the vectors
+ * whose first nonzero component is positive in ascending (nx, ny, nz); n = 0
+ * gives the constant, every other vector cos then sin).  The batched form
+ * uses these as the N single-particle functions of the Slater matrix
+ * (Sec. I).  dsu_plane_wave_table writes {nx, ny, nz, kind} per orbital
+ * (kind 0 = 1, 1 = cos, 2 = sin; host only, no device needed).
+ * dsu_plane_wave_rows evaluates rows_host[c][j] = phi_j(positions_host[c])
+ * for `count` positions (count*3 FP64 in, count*n FP64 out) on the device. */
+int dsu_plane_wave_table(int32_t n, int32_t *out4);
+int dsu_plane_wave_rows(int32_t n, double box_L, int32_t count, const double *positions_host, double *rows_host);
+
 /* ======================================================================
  * Single walker, host-driven: the paper's procedure one call per step.
  * ====================================================================== */
@@ -184,6 +196,12 @@ int dsu_batch_use_graph(dsu_batch *b, int32_t enable);
  * with; Sec. II: K is the tunable of the method).  Takes effect at the next
  * sweep. */
 int dsu_batch_set_delay(dsu_batch *b, int32_t k_delay);
+/* Window schedule.  streaming = 1 (default): three launches per window
+ * (proposals, one-pass flush that also forms the next window's look-ahead
+ * products while each chunk of the inverse is on chip, decisions).
+ * streaming = 0: four launches (proposals, look-ahead products, decisions,
+ * flush that reads the inverse twice).  Both compute the same ratios. */
+int dsu_batch_set_flush_path(dsu_batch *b, int32_t streaming);
 
 /* ======================================================================
  * Serving: a pool of walkers of mixed n admitted by a device-memory budget,

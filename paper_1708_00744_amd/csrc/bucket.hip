@@ -38,7 +38,8 @@ BucketShape BucketShape::make(int n, int kmax, int prec) {
 }
 
 // Piece sizes in carve order.
-static void pieces(const BucketShape &s, size_t out[11]) {
+static constexpr int kPieces = 14;
+static void pieces(const BucketShape &s, size_t out[kPieces]) {
     const size_t e = elem_size(s.prec), np = s.np, kp = s.kp;
     out[0] = np * np * e;                           // bt
     out[1] = kp * np * e;                           // u
@@ -51,21 +52,24 @@ static void pieces(const BucketShape &s, size_t out[11]) {
     out[8] = (size_t)s.n * 3 * 8;                   // pos
     out[9] = kp * 4;                                // idx
     out[10] = sizeof(DetState);                     // st
+    out[11] = kp * np * e;                          // u2
+    out[12] = kp * np * e;                          // vg2
+    out[13] = np * kp * e;                          // y
 }
 
 size_t BucketShape::det_bytes() const {
-    size_t p[11], b = 0;
+    size_t p[kPieces], b = 0;
     pieces(*this, p);
     for (size_t x : p) b += align256(x);
     return b;
 }
 
 DetSlot BucketShape::carve(char *base) const {
-    size_t p[11];
+    size_t p[kPieces];
     pieces(*this, p);
     char *c = base;
-    void *ptr[11];
-    for (int i = 0; i < 11; ++i) {
+    void *ptr[kPieces];
+    for (int i = 0; i < kPieces; ++i) {
         ptr[i] = p[i] ? (void *)c : nullptr;
         c += align256(p[i]);
     }
@@ -81,6 +85,9 @@ DetSlot BucketShape::carve(char *base) const {
     d.pos = (double *)ptr[8];
     d.idx = (int *)ptr[9];
     d.st = (DetState *)ptr[10];
+    d.u2 = ptr[11];
+    d.vg2 = ptr[12];
+    d.y = ptr[13];
     return d;
 }
 
@@ -157,6 +164,9 @@ template <typename T> static DetDesc<T> to_desc(const DetSlot &s) {
     d.wid = s.wid;
     d.sigma = s.sigma;
     d.spin = s.spin;
+    d.u2 = (T *)s.u2;
+    d.vg2 = (T *)s.vg2;
+    d.y = (T *)s.y;
     return d;
 }
 
@@ -254,7 +264,44 @@ template <typename T> int Bucket::enqueue_sweep_t(int force) {
     return DSU_OK;
 }
 
+// Streaming sweep: prime (proposals of window 0, y = BT U^T for all rows,
+// decisions of window 0), then per window w: proposals of w+1, one-pass flush
+// of w producing y for w+1, decisions of w+1.
+template <typename T> int Bucket::enqueue_sweep_stream_t(int force) {
+    const DetDesc<T> *dd = (const DetDesc<T> *)ddesc_;
+    const int nd = (int)dets.size();
+    const int kt = kpad(K);
+    const int nwin = (sh.n + K - 1) / K;
+    auto kw_of = [&](int w) { return std::min(K, sh.n - w * K); };
+    CHK(timed(PH_ROWS, [&] {
+        return launch_window_props<T>(dd, nd, sh.n, sh.np, kt, 0, kw_of(0), kvec, twopi_l, 0, 1, stream);
+    }));
+    CHK(timed(PH_G, [&] { return launch_window_prime<T>(dd, nd, sh.np, kt, sh.kp, 0, stream); }));
+    CHK(timed(PH_DECIDE, [&] {
+        return launch_window_decide<T>(dd, nd, kt, sh.kp, 0, kw_of(0), 1, force, nwin == 1, stream, 1);
+    }));
+    for (int w = 0; w < nwin; ++w) {
+        const int cur = w & 1, nxt = cur ^ 1;
+        const bool has_next = w + 1 < nwin;
+        const int e0n = (w + 1) * K, kwn = has_next ? kw_of(w + 1) : 0;
+        if (has_next)
+            CHK(timed(PH_ROWS, [&] {
+                return launch_window_props<T>(dd, nd, sh.n, sh.np, kt, e0n, kwn, kvec, twopi_l, nxt, 0, stream);
+            }));
+        CHK(timed(PH_FLUSH, [&] {
+            return launch_flush_stream<T>(dd, nd, sh.np, kt, sh.kp, kw_of(w), cur, has_next ? 1 : 0, e0n, kwn, stream);
+        }));
+        if (has_next)
+            CHK(timed(PH_DECIDE, [&] {
+                return launch_window_decide<T>(dd, nd, kt, sh.kp, e0n, kwn, 1, force, w + 2 == nwin, stream, 1);
+            }));
+    }
+    return DSU_OK;
+}
+
 int Bucket::enqueue_sweep(int force) {
+    if (streaming)
+        return sh.prec == DSU_FP64 ? enqueue_sweep_stream_t<double>(force) : enqueue_sweep_stream_t<float>(force);
     return sh.prec == DSU_FP64 ? enqueue_sweep_t<double>(force) : enqueue_sweep_t<float>(force);
 }
 
@@ -362,6 +409,54 @@ int build_kvectors(int n, int4 *out) {
 }
 
 }  // namespace dsu
+
+// ==========================================================================
+// Plane-wave utilities
+// ==========================================================================
+extern "C" int dsu_plane_wave_table(int32_t n, int32_t *out4) {
+    if (n < 1 || n > 32768 || !out4) return dsu::fail(DSU_EINVAL, "bad arguments");
+    std::vector<int4> kv(n);
+    dsu::build_kvectors(n, kv.data());
+    for (int j = 0; j < n; ++j) {
+        out4[4 * j + 0] = kv[j].x;
+        out4[4 * j + 1] = kv[j].y;
+        out4[4 * j + 2] = kv[j].z;
+        out4[4 * j + 3] = kv[j].w;
+    }
+    return DSU_OK;
+}
+
+extern "C" int dsu_plane_wave_rows(int32_t n, double box_L, int32_t count, const double *positions_host,
+                                   double *rows_host) {
+    using namespace dsu;
+    if (n < 1 || n > 32768 || count < 0 || !(box_L > 0)) return fail(DSU_EINVAL, "bad arguments");
+    if (count == 0) return DSU_OK;
+    if (!positions_host || !rows_host) return fail(DSU_EINVAL, "NULL array");
+    std::vector<int4> kv(n);
+    build_kvectors(n, kv.data());
+    int4 *dk = nullptr;
+    double *dp = nullptr, *dr = nullptr;
+    hipStream_t s = nullptr;
+    bool own = false;
+    int rc = make_stream(nullptr, &s, &own);
+    if (rc == DSU_OK) rc = dalloc(&dk, (size_t)n);
+    if (rc == DSU_OK) rc = dalloc(&dp, (size_t)count * 3);
+    if (rc == DSU_OK) rc = dalloc(&dr, (size_t)count * n);
+    hipError_t e = hipSuccess;
+    if (rc == DSU_OK) e = hipMemcpyAsync(dk, kv.data(), sizeof(int4) * n, hipMemcpyHostToDevice, s);
+    if (rc == DSU_OK && e == hipSuccess)
+        e = hipMemcpyAsync(dp, positions_host, sizeof(double) * count * 3, hipMemcpyHostToDevice, s);
+    if (rc == DSU_OK && e == hipSuccess) e = launch_pw_rows(dp, dr, n, count, dk, 2.0 * M_PI / box_L, s);
+    if (rc == DSU_OK && e == hipSuccess)
+        e = hipMemcpyAsync(rows_host, dr, sizeof(double) * count * n, hipMemcpyDeviceToHost, s);
+    if (rc == DSU_OK && e == hipSuccess) e = hipStreamSynchronize(s);
+    if (rc == DSU_OK && e != hipSuccess) rc = fail(DSU_EDEVICE, "plane-wave rows: %s", hipGetErrorString(e));
+    dfree(dk);
+    dfree(dp);
+    dfree(dr);
+    if (own && s) (void)hipStreamDestroy(s);
+    return rc;
+}
 
 // ==========================================================================
 // dsu_batch: one bucket over one contiguous block of determinant storage.
@@ -597,4 +692,11 @@ extern "C" int dsu_batch_use_graph(dsu_batch *b, int32_t enable) {
     if (!b) return fail(DSU_EINVAL, "batch is NULL");
     b->bk.use_graph = enable != 0;
     return DSU_OK;
+}
+
+extern "C" int dsu_batch_set_flush_path(dsu_batch *b, int32_t streaming) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    b->bk.streaming = streaming != 0;
+    return b->bk.set_dets(b->bk.dets);  // drops any captured graph
 }

@@ -14,7 +14,7 @@ namespace dsu {
 
 // Device storage of one determinant.
 struct DetSlot {
-    void *bt = nullptr, *u = nullptr, *vg = nullptr, *gpart = nullptr;
+    void *bt = nullptr, *u = nullptr, *vg = nullptr, *gpart = nullptr, *u2 = nullptr, *vg2 = nullptr, *y = nullptr;
     double *cfl = nullptr, *cwork = nullptr, *gwork = nullptr, *prop = nullptr, *pos = nullptr;
     int *idx = nullptr;
     DetState *st = nullptr;
@@ -47,6 +47,7 @@ class Bucket {
     std::vector<DetSlot> dets;
     bool use_graph = false;
     bool timing = false;
+    bool streaming = true;  // one-pass flush with the next window's products (else 4-launch windows)
 
     int init(const BucketShape &shape, int k_delay, double box_l, void *stream_or_null, int gj_group);
     void release();
@@ -84,6 +85,7 @@ class Bucket {
     template <typename F> int timed(int phase, F fn);
     template <typename T> int upload_t();
     template <typename T> int enqueue_sweep_t(int force_accept);
+    template <typename T> int enqueue_sweep_stream_t(int force_accept);
     template <typename T> int recompute_t(const std::vector<int> &which, double *drift_host);
 };
 

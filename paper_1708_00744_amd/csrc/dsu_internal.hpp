@@ -96,6 +96,11 @@ template <typename T> struct DetDesc {
     uint64_t seed, wid;
     double sigma;
     int spin;
+    // streaming path: second U/Vg buffers (windows alternate) and the
+    // look-ahead products of the next window for every row, y[i][a] = BT[i].U[a]
+    T *u2;           // kp x np
+    T *vg2;          // kp x np
+    T *y;            // np x kp
 };
 
 // ------------------------------------------------------- launchers (host)
@@ -173,9 +178,29 @@ hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int np, int ktile, in
                            hipStream_t s);
 template <typename T>
 hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int nsplit,
-                                int force_accept, int last_window, hipStream_t s);
+                                int force_accept, int last_window, hipStream_t s, int g_from_y = 0);
+
+// Streaming path (one pass over BT per window):
+//   props : proposals and orbital rows of a window into U buffer `buf`
+//           (and, with copy_vg, the window's current BT rows into Vg `buf`)
+//   prime : y = BT U[buf]^T for every row (start of a sweep)
+//   flush : BT -= W Vg[cur] with W = (y - E) C^{-T}; while each chunk of BT is
+//           on chip, y = BT_new U[nxt]^T for the next window and the next
+//           window's BT rows into Vg[nxt]
+template <typename T>
+hipError_t launch_window_props(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
+                               const int4 *kvec, double twopi_over_l, int buf, int copy_vg, hipStream_t s);
+template <typename T>
+hipError_t launch_window_prime(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int buf, hipStream_t s);
+template <typename T>
+hipError_t launch_flush_stream(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int kslots, int cur,
+                               int has_next, int e0n, int kwn, hipStream_t s);
 template <typename T>
 hipError_t launch_reset_state(const DetDesc<T> *d, const GjDesc *gj, double *drift, int ndesc, hipStream_t s);
+
+// rows[c][j] = phi_j(pos_c): plane-wave orbital rows at `count` positions.
+hipError_t launch_pw_rows(const double *pos_dev, double *rows_dev, int n, int count, const int4 *kvec,
+                          double twopi_over_l, hipStream_t s);
 
 // Host-side plane-wave table: orbitals by shells of |n|^2 (see kvec.cpp).
 int build_kvectors(int n, int4 *out /* n entries: nx, ny, nz, kind */);

@@ -77,7 +77,7 @@ __device__ __forceinline__ double pw_orbital(int4 kv, double twopi_l, double x, 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__restrict__ descs, int n, int np,
                                                           int ktile, int e0, int kw, const int4 *__restrict__ kvec,
-                                                          double twopi_l) {
+                                                          double twopi_l, int buf, int copy_vg) {
 #pragma clang fp contract(off)
     __shared__ double s_r[DSU_KMAX_LDS][3];
     const DetDesc<T> d = descs[blockIdx.x];
@@ -105,8 +105,8 @@ __global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__re
             if (c < n) val = T(pw_orbital(kvec[c], twopi_l, s_r[a][0], s_r[a][1], s_r[a][2]));
             vgv = d.bt[(size_t)(e0 + a) * np + c];
         }
-        d.u[(size_t)a * np + c] = val;
-        d.vg[(size_t)a * np + c] = vgv;
+        (buf ? d.u2 : d.u)[(size_t)a * np + c] = val;
+        if (copy_vg) (buf ? d.vg2 : d.vg)[(size_t)a * np + c] = vgv;
     }
 }
 
@@ -117,9 +117,24 @@ hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int
     if (nsplit < 1) nsplit = 1;
     while (np % nsplit) --nsplit;
     hipLaunchKernelGGL((k_window_rows<T>), dim3(ndesc, nsplit), dim3(kThreads), 0, s, d, n, np, ktile, e0, kw, kvec,
-                       twopi_over_l);
+                       twopi_over_l, 0, 1);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_window_props(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
+                               const int4 *kvec, double twopi_over_l, int buf, int copy_vg, hipStream_t s) {
+    int nsplit = np / 256;
+    if (nsplit < 1) nsplit = 1;
+    while (np % nsplit) --nsplit;
+    hipLaunchKernelGGL((k_window_rows<T>), dim3(ndesc, nsplit), dim3(kThreads), 0, s, d, n, np, ktile, e0, kw, kvec,
+                       twopi_over_l, buf, copy_vg);
+    return hipGetLastError();
+}
+template hipError_t launch_window_props<float>(const DetDesc<float> *, int, int, int, int, int, int, const int4 *,
+                                               double, int, int, hipStream_t);
+template hipError_t launch_window_props<double>(const DetDesc<double> *, int, int, int, int, int, int, const int4 *,
+                                                double, int, int, hipStream_t);
 template hipError_t launch_window_rows<float>(const DetDesc<float> *, int, int, int, int, int, int, const int4 *,
                                               double, hipStream_t);
 template hipError_t launch_window_rows<double>(const DetDesc<double> *, int, int, int, int, int, int, const int4 *,
@@ -190,7 +205,8 @@ template <int KP> struct DecideCfg {
 template <typename T, int KP>
 __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const DetDesc<T> *__restrict__ descs,
                                                                           int kp, int e0, int kw, int nsplit,
-                                                                          int force_accept, int last_window) {
+                                                                          int force_accept, int last_window,
+                                                                          int g_from_y) {
     typedef DecideCfg<KP> C;
     constexpr int LD = C::ld, NT = C::threads;
     __shared__ double s_g[C::lds_g];
@@ -208,7 +224,9 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
     for (int v = tid; v < kw * kw; v += NT) {
         const int a = v / kw, b = v % kw;
         double acc = 0.0;
-        for (int s = 0; s < nsplit; ++s) acc += (double)d.gpart[((size_t)s * kp + b) * kp + a];
+        if (g_from_y) acc = (double)d.y[(size_t)(e0 + b) * kp + a];
+        else
+            for (int s = 0; s < nsplit; ++s) acc += (double)d.gpart[((size_t)s * kp + b) * kp + a];
         G[a * LD + b] = acc;
     }
     for (int a = tid; a < KP; a += NT) {
@@ -307,11 +325,11 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
 
 template <typename T>
 hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int nsplit,
-                                int force_accept, int last_window, hipStream_t s) {
+                                int force_accept, int last_window, hipStream_t s, int g_from_y) {
 #define DSU_D(KPV)                                                                                                \
     if (ktile == KPV) {                                                                                           \
         hipLaunchKernelGGL((k_window_decide<T, KPV>), dim3(ndesc), dim3(DecideCfg<KPV>::threads), 0, s, d, kp,    \
-                           e0, kw, nsplit, force_accept, last_window);                                            \
+                           e0, kw, nsplit, force_accept, last_window, g_from_y);                                  \
         return hipGetLastError();                                                                                 \
     }
     DSU_D(16) DSU_D(32) DSU_D(64) DSU_D(128) DSU_D(256)
@@ -319,9 +337,198 @@ hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int k
     return hipErrorInvalidValue;
 }
 template hipError_t launch_window_decide<float>(const DetDesc<float> *, int, int, int, int, int, int, int, int,
-                                                hipStream_t);
+                                                hipStream_t, int);
 template hipError_t launch_window_decide<double>(const DetDesc<double> *, int, int, int, int, int, int, int, int,
-                                                 hipStream_t);
+                                                 hipStream_t, int);
+
+// ------------------------------------------------------- streaming path
+// y[i][a] = BT[i,:] . U[buf][a,:] for every row i (the look-ahead products of
+// the first window of a sweep, for all rows at once).
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_window_prime(const DetDesc<T> *__restrict__ descs, int np, int nblk,
+                                                           int kp, int buf) {
+    constexpr int LDU = 128 / (int)sizeof(T) + 16 / (int)sizeof(T);
+    __shared__ __attribute__((aligned(16))) T lds[KP * LDU];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int d = b / nblk, r0 = (b % nblk) * kRowBlock;
+    const DetDesc<T> dd = descs[d];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    typename Mma<T>::acc_t acc[KP / 16];
+    rowblock_times_ut<T, KP>(dd.bt + (size_t)r0 * np, np, kRowBlock, buf ? dd.u2 : dd.u, np, 0, np, lds, acc);
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = r0 + 16 * wave + Mma<T>::row0(lane) + i * Mma<T>::row_step;
+            dd.y[(size_t)row * kp + 16 * t + (lane & 15)] = acc[t][i];
+        }
+}
+
+template <typename T>
+hipError_t launch_window_prime(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int buf, hipStream_t s) {
+    const int nblk = np / kRowBlock;
+    const dim3 grid(ndesc * nblk);
+#define DSU_P(KPV)                                                                                          \
+    if (ktile == KPV) {                                                                                     \
+        hipLaunchKernelGGL((k_window_prime<T, KPV>), grid, dim3(kThreads), 0, s, d, np, nblk, kp, buf);     \
+        return hipGetLastError();                                                                           \
+    }
+    DSU_P(16) DSU_P(32) DSU_P(64) DSU_P(128) DSU_P(256)
+#undef DSU_P
+    return hipErrorInvalidValue;
+}
+template hipError_t launch_window_prime<float>(const DetDesc<float> *, int, int, int, int, int, hipStream_t);
+template hipError_t launch_window_prime<double>(const DetDesc<double> *, int, int, int, int, int, hipStream_t);
+
+// One pass over BT per window.  Per 64-row block:
+//   W    = (y - E) C^{-T}          (from this block's rows of y, on matrix cores)
+//   for each column chunk of BT (on chip once):
+//     BT  -= W Vg[cur]              (eq. (4), row-local)
+//     y   += BT_new U[nxt]^T        (look-ahead products of the next window)
+//     rows of the next window -> Vg[nxt]
+template <typename T, int KP> struct StreamCfg {
+    static constexpr int CW = Phase3Cfg<T, KP>::CW;
+    static constexpr int LDV = Phase3Cfg<T, KP>::LDV;
+    static constexpr int LDU = CW + 1;
+    static constexpr int LDT = CW + 1;
+    static constexpr int LDY = KP + 16 / (int)sizeof(T);
+    static constexpr int chunk = KP * LDV + KP * LDU + 64 * LDT;
+    static constexpr int elems = chunk > 64 * LDY ? chunk : 64 * LDY;
+};
+
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_flush_stream(const DetDesc<T> *__restrict__ descs, int np, int nblk,
+                                                           int kp, int kslots, int cur, int has_next, int e0n,
+                                                           int kwn) {
+    typedef StreamCfg<T, KP> C;
+    constexpr int CW = C::CW, LDV = C::LDV, LDU = C::LDU, LDT = C::LDT, LDY = C::LDY, VEC = 16 / sizeof(T);
+    constexpr int RS = Mma<T>::row_step;
+    __shared__ __attribute__((aligned(16))) T lds[C::elems];
+    T *Vs = lds, *Us = lds + KP * LDV, *Ts = Us + KP * LDU;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int d = b / nblk, r0 = (b % nblk) * kRowBlock;
+    const DetDesc<T> dd = descs[d];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const T *vcur = cur ? dd.vg2 : dd.vg;
+    const T *unext = cur ? dd.u : dd.u2;
+    T *vnext = cur ? dd.vg : dd.vg2;
+
+    // W = (y - E) C^{-T} for this block's 64 rows
+    for (int v = tid; v < 64 * KP; v += kThreads) {
+        const int i = v / KP, j = v % KP;
+        lds[i * LDY + j] = dd.y[(size_t)(r0 + i) * kp + j];
+    }
+    __syncthreads();
+    for (int j = tid; j < kslots; j += kThreads) {
+        const int e = dd.idx[j];
+        if (e >= r0 && e < r0 + kRowBlock) lds[(e - r0) * LDY + j] -= T(1);
+    }
+    __syncthreads();
+    typename Mma<T>::acc_t wacc[KP / 16];
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t) wacc[t] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    for (int s = 0; s < KP / 4; ++s) {
+        const int jc = 4 * s + (lane >> 4);
+        const T a = lds[(16 * wave + (lane & 15)) * LDY + jc];
+#pragma unroll
+        for (int t = 0; t < KP / 16; ++t) {
+            const int lr = 16 * t + (lane & 15);
+            const T bb = (lr < kslots && jc < kslots) ? T(dd.cfl[(size_t)lr * kp + jc]) : T(0);
+            wacc[t] = Mma<T>::mma(a, bb, wacc[t]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            lds[(16 * wave + Mma<T>::row0(lane) + i * RS) * LDY + 16 * t + (lane & 15)] = wacc[t][i];
+    __syncthreads();
+    T wa[KP / 4];
+#pragma unroll
+    for (int s = 0; s < KP / 4; ++s) wa[s] = -lds[(16 * wave + (lane & 15)) * LDY + 4 * s + (lane >> 4)];
+    __syncthreads();
+
+    typename Mma<T>::acc_t accy[KP / 16];
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t) accy[t] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    const int drow = 16 * wave + Mma<T>::row0(lane);  // this lane's first result row in the block
+    T *rp = dd.bt + (size_t)(r0 + drow) * np + (lane & 15);
+    for (int c0 = 0; c0 < np; c0 += CW) {
+        for (int v = tid; v < KP * (CW / VEC); v += kThreads) {
+            const int r = v / (CW / VEC), cc = (v % (CW / VEC)) * VEC;
+            *reinterpret_cast<V16<T> *>(Vs + r * LDV + cc) =
+                *reinterpret_cast<const V16<T> *>(vcur + (size_t)r * np + c0 + cc);
+        }
+        if (has_next)
+            for (int v = tid; v < KP * CW; v += kThreads) {
+                const int r = v / CW, cc = v % CW;
+                Us[r * LDU + cc] = unext[(size_t)r * np + c0 + cc];
+            }
+        typename Mma<T>::acc_t acc[CW / 16];
+#pragma unroll
+        for (int t = 0; t < CW / 16; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[t][i] = rp[(size_t)(i * RS) * np + c0 + 16 * t];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < KP / 4; ++s) {
+            const T *bp = Vs + (4 * s + (lane >> 4)) * LDV + (lane & 15);
+#pragma unroll
+            for (int t = 0; t < CW / 16; ++t) acc[t] = Mma<T>::mma(wa[s], bp[16 * t], acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < CW / 16; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const T x = acc[t][i];
+                const int row = drow + i * RS;
+                const int col = c0 + 16 * t + (lane & 15);
+                rp[(size_t)(i * RS) * np + c0 + 16 * t] = x;
+                Ts[row * LDT + 16 * t + (lane & 15)] = x;
+                const int g = r0 + row - e0n;
+                if (has_next && g >= 0 && g < kwn) vnext[(size_t)g * np + col] = x;
+            }
+        // Ts rows 16w..16w+15 were written by this wave only: the A operands below
+        // read them back through LDS in program order.
+        if (has_next) {
+#pragma unroll
+            for (int s = 0; s < CW / 4; ++s) {
+                const T a = Ts[(16 * wave + (lane & 15)) * LDT + 4 * s + (lane >> 4)];
+#pragma unroll
+                for (int t = 0; t < KP / 16; ++t)
+                    accy[t] = Mma<T>::mma(a, Us[(16 * t + (lane & 15)) * LDU + 4 * s + (lane >> 4)], accy[t]);
+            }
+        }
+        __syncthreads();
+    }
+    if (has_next) {
+#pragma unroll
+        for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dd.y[(size_t)(r0 + drow + i * RS) * kp + 16 * t + (lane & 15)] = accy[t][i];
+    }
+}
+
+template <typename T>
+hipError_t launch_flush_stream(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int kslots, int cur,
+                               int has_next, int e0n, int kwn, hipStream_t s) {
+    const int nblk = np / kRowBlock;
+    const dim3 grid(ndesc * nblk);
+#define DSU_S(KPV)                                                                                           \
+    if (ktile == KPV) {                                                                                      \
+        hipLaunchKernelGGL((k_flush_stream<T, KPV>), grid, dim3(kThreads), 0, s, d, np, nblk, kp, kslots, cur, \
+                           has_next, e0n, kwn);                                                              \
+        return hipGetLastError();                                                                            \
+    }
+    DSU_S(16) DSU_S(32) DSU_S(64) DSU_S(128) DSU_S(256)
+#undef DSU_S
+    return hipErrorInvalidValue;
+}
+template hipError_t launch_flush_stream<float>(const DetDesc<float> *, int, int, int, int, int, int, int, int, int,
+                                               hipStream_t);
+template hipError_t launch_flush_stream<double>(const DetDesc<double> *, int, int, int, int, int, int, int, int, int,
+                                                hipStream_t);
 
 // ------------------------------------------------- Slater matrix, FP64
 // M[j][i] = phi_j(r_i) for i, j < n (the transpose of A), identity padding.
@@ -343,6 +550,22 @@ hipError_t launch_build_pw_transpose(const double *const *pos_dev, double *const
                                      const int4 *kvec, double twopi_over_l, hipStream_t s) {
     hipLaunchKernelGGL(k_build_pw_transpose, dim3((np + kThreads - 1) / kThreads, np, ndesc), dim3(kThreads), 0, s,
                        pos_dev, m_dev, n, np, kvec, twopi_over_l);
+    return hipGetLastError();
+}
+
+// rows[c][j] = phi_j(pos_c) for c < count, j < n (FP64).
+__global__ __launch_bounds__(kThreads) void k_pw_rows(const double *__restrict__ pos, double *__restrict__ rows, int n,
+                                                      const int4 *__restrict__ kvec, double twopi_l) {
+    const int c = blockIdx.y;
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= n) return;
+    rows[(size_t)c * n + j] = pw_orbital(kvec[j], twopi_l, pos[3 * c], pos[3 * c + 1], pos[3 * c + 2]);
+}
+
+hipError_t launch_pw_rows(const double *pos_dev, double *rows_dev, int n, int count, const int4 *kvec,
+                          double twopi_over_l, hipStream_t s) {
+    hipLaunchKernelGGL(k_pw_rows, dim3((n + kThreads - 1) / kThreads, count), dim3(kThreads), 0, s, pos_dev, rows_dev,
+                       n, kvec, twopi_over_l);
     return hipGetLastError();
 }
 

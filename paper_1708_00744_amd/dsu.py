@@ -53,6 +53,8 @@ SIGNATURES = {
     "dsu_last_error": (C.c_char_p, []),
     "dsu_version": (C.c_int, []),
     "dsu_footprint_bytes": (_sz, [_i32, _i32, _i32]),
+    "dsu_plane_wave_table": (C.c_int, [_i32, _pi32]),
+    "dsu_plane_wave_rows": (C.c_int, [_i32, _dbl, _i32, _pd, _pd]),
     "dsu_walker_create": (C.c_int, [_i32, _i32, _i32, _i32, _pd, _vp, _pvp]),
     "dsu_walker_destroy": (C.c_int, [_vp]),
     "dsu_propose_ratio": (C.c_int, [_vp, _i32, _pd, _pd]),
@@ -79,6 +81,7 @@ SIGNATURES = {
     "dsu_batch_kernel_time": (C.c_int, [_vp, _i32, _pi64, _pd]),
     "dsu_batch_use_graph": (C.c_int, [_vp, _i32]),
     "dsu_batch_set_delay": (C.c_int, [_vp, _i32]),
+    "dsu_batch_set_flush_path": (C.c_int, [_vp, _i32]),
     "dsu_server_create": (C.c_int, [_i32, _i32, _dbl, _sz, _i32, _pvp]),
     "dsu_server_destroy": (C.c_int, [_vp]),
     "dsu_server_run": (C.c_int, [_vp, C.POINTER(Request), _i32, C.POINTER(Result), _pd, _i64, _pi64]),
@@ -131,6 +134,20 @@ def _stream_ptr(stream):
 
 def footprint_bytes(n, k_delay, precision=FP32_MIXED):
     return int(lib().dsu_footprint_bytes(n, k_delay, precision))
+
+
+def plane_wave_table(n):
+    out = np.zeros((n, 4), np.int32)
+    _check(lib().dsu_plane_wave_table(int(n), out.ctypes.data_as(_pi32)))
+    return out
+
+
+def plane_wave_rows(n, box_l, positions):
+    """Orbital rows phi_j(r_c) for positions (count, 3), evaluated on the device."""
+    pos = _f64(positions).reshape(-1, 3)
+    rows = np.zeros((pos.shape[0], n))
+    _check(lib().dsu_plane_wave_rows(int(n), float(box_l), pos.shape[0], _dp(pos), _dp(rows)))
+    return rows
 
 
 class Walker:
@@ -286,6 +303,9 @@ class Batch:
 
     def use_graph(self, enable):
         _check(lib().dsu_batch_use_graph(self._h, int(bool(enable))))
+
+    def set_flush_path(self, streaming):
+        _check(lib().dsu_batch_set_flush_path(self._h, int(bool(streaming))))
 
     def set_delay(self, k_delay):
         _check(lib().dsu_batch_set_delay(self._h, int(k_delay)))

@@ -53,3 +53,14 @@ def test_host_only_calls():
     assert L.dsu_walker_create(8, 0, 0, 0, None, None, ctypes.byref(h)) == dsu.EINVAL
     assert L.dsu_accept(None) == dsu.EINVAL
     assert L.dsu_batch_sweep(None, 1, 0) == dsu.EINVAL
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 1000, 4096])
+def test_plane_wave_table_matches_oracle(n):
+    """The library's orbital table and the oracle's are written independently;
+    they must list the same orbitals in the same order."""
+    if not os.path.exists(dsu.LIB_PATH):
+        pytest.skip("libdsu.so not built")
+    import numpy as np
+    import oracle
+    np.testing.assert_array_equal(dsu.plane_wave_table(n), oracle.pw_kvectors(n))

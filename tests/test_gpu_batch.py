@@ -213,3 +213,24 @@ def test_c4_shape_sampled():
         print(f"walker {w}: residual {res:.2e}, logdet diff {st['logdet'][w] - l_np:.2e}", flush=True)
         assert res < 1e-2
     b.close()
+
+
+@pytest.mark.parametrize("prec,n,K", [(dsu.FP64, 100, 16), (dsu.FP64, 200, 64), (dsu.FP32_MIXED, 256, 64),
+                                      (dsu.FP32_MIXED, 192, 128)])
+def test_two_window_schedules_agree(prec, n, K):
+    """The one-pass streaming flush and the four-launch window schedule compute
+    the same ratios and decisions (to rounding)."""
+    require_gpu()
+    out = []
+    for streaming in (True, False):
+        b, pos = make_batch(n, 2, 1, K, prec, 0.2, seed=51)
+        b.set_flush_path(streaming)
+        b.set_trace(2)
+        b.sweep(2)
+        out.append((b.trace(0), b.trace(1), b.stats()))
+        b.close()
+    tol = 1e-11 if prec == dsu.FP64 else 1e-4
+    for (r0, a0), (r1, a1) in zip(out[0][:2], out[1][:2]):
+        m = len(a0) if np.array_equal(a0, a1) else int(np.nonzero(a0 != a1)[0][0])
+        assert m > n
+        assert rel_err(r0[:m], r1[:m]).max() < tol
