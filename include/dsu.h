@@ -100,7 +100,8 @@ typedef struct dsu_walker dsu_walker;
  * electron i).  Computes A^{-1} and log|det A| in FP64 on the device
  * (blocked Gauss-Jordan with partial pivoting: the explicit route of
  * Sec. I).  k_delay in [1, DSU_MAX_K]; k_delay = 1 is plain Sherman-Morrison,
- * eq. (2).  DSU_ESINGULAR if A is singular. */
+ * eq. (2).  DSU_ESINGULAR if A is singular to working precision (a pivot at
+ * or below n * 2^-52 times the largest pivot). */
 int dsu_walker_create(int32_t n, int32_t k_delay, int32_t precision, int32_t policy,
                       const double *slater_host, void *hip_stream, dsu_walker **out);
 int dsu_walker_destroy(dsu_walker *w);
@@ -120,7 +121,10 @@ int dsu_propose_ratio_dev(dsu_walker *w, int32_t electron, const void *phi_dev, 
  * border the K x K inverse, update A's row and the running log-determinant.
  * When the delay limit is reached the queued moves are applied en bloc by
  * the Woodbury formula, eq. (4).  DSU_ESTATE without a pending proposal;
- * DSU_ESINGULAR (walker unchanged) if the proposal's ratio is 0 or not finite. */
+ * DSU_ESINGULAR (walker unchanged) if the ratio is not finite or |R| <= 1e-12
+ * (1e-6 in DSU_FP32_MIXED): the updated matrix would be numerically singular,
+ * and a Metropolis test accepts such a move with probability R^2 below 1e-24
+ * (1e-12).  The batched form rejects such proposals the same way. */
 int dsu_accept(dsu_walker *w);
 /* Drop the pending proposal.  Under DSU_FLUSH_K_PROPOSED it still takes a
  * slot toward K. */

@@ -248,7 +248,8 @@ extern "C" int dsu_accept(dsu_walker *w) {
     if (!w) return fail(DSU_EINVAL, "walker is NULL");
     if (!w->has_prop) return fail(DSU_ESTATE, "no pending proposal");
     const double r = w->prop_r;
-    if (!(std::isfinite(r)) || r == 0.0) return fail(DSU_ESINGULAR, "ratio %g cannot be accepted", r);
+    const double floor = w->prec == DSU_FP64 ? RatioFloor<double>::value : RatioFloor<float>::value;
+    if (!(std::fabs(r) > floor) || !std::isfinite(r)) return fail(DSU_ESINGULAR, "ratio %g cannot be accepted", r);
     if (w->prec == DSU_FP64) HIPCHK(launch_walker_accept<double>(&w->wd, w->n, w->np, w->k, w->kp, w->prop_e, w->stream));
     else HIPCHK(launch_walker_accept<float>(&w->wd, w->n, w->np, w->k, w->kp, w->prop_e, w->stream));
     w->idx[w->k] = w->prop_e;

@@ -125,7 +125,15 @@ struct GjDesc {
     double *logdet;   // out
     int *sign;        // out
     int *status;      // out: 0 or -3 singular
+    double *pmax;     // largest pivot magnitude so far (singularity threshold)
 };
+
+// A ratio whose magnitude is at or below this cannot be accepted: the
+// updated matrix would be numerically singular (and Metropolis would accept
+// it with probability R^2 <= 1e-24 resp. 1e-12).
+template <typename T> struct RatioFloor;
+template <> struct RatioFloor<double> { static constexpr double value = 1e-12; };
+template <> struct RatioFloor<float> { static constexpr double value = 1e-6; };
 hipError_t launch_gj_invert(const GjDesc *descs_dev, const RankDesc *rank_dev, int ndesc, int n, int np,
                             int nb, hipStream_t s);
 // BT[i][j] = T(M[i][perm[j]]) for i, j < n, zero padding elsewhere.

@@ -62,7 +62,7 @@ static int gj_panel_width(int n) { return n >= 512 ? 64 : (n >= 64 ? 32 : 16); }
 
 size_t GjWork::bytes_per(int np_, int n) {
     const size_t nb_ = gj_panel_width(n);
-    return (size_t)np_ * np_ * 8 + (size_t)np_ * nb_ * 8 * 3 + (size_t)np_ * 8 + 64;
+    return (size_t)np_ * np_ * 8 + (size_t)np_ * nb_ * 8 * 3 + (size_t)np_ * 8 + 128;
 }
 
 int GjWork::alloc(int groups, int np_, int n) {
@@ -79,6 +79,7 @@ int GjWork::alloc(int groups, int np_, int n) {
     CHK(dalloc(&perm, (size_t)np * g));
     CHK(dalloc(&sign, g));
     CHK(dalloc(&status, g));
+    CHK(dalloc(&pmax, g));
     CHK(dalloc(&gdesc, g));
     CHK(dalloc(&rdesc, g));
     CHK(dalloc(&mptr, g));
@@ -87,7 +88,7 @@ int GjWork::alloc(int groups, int np_, int n) {
     std::vector<double *> mp(g);
     for (int i = 0; i < g; ++i) {
         gd[i] = GjDesc{m + np2 * i, panel + (size_t)np * nb * i, w + (size_t)np * nb * i, q + (size_t)np * nb * i,
-                       piv + (size_t)np * i, perm + (size_t)np * i, logdet + i, sign + i, status + i};
+                       piv + (size_t)np * i, perm + (size_t)np * i, logdet + i, sign + i, status + i, pmax + i};
         rd[i] = RankDesc{gd[i].m, gd[i].w, gd[i].q};
         mp[i] = gd[i].m;
     }
@@ -99,9 +100,9 @@ int GjWork::alloc(int groups, int np_, int n) {
 
 void GjWork::release() {
     for (void *p : {(void *)m, (void *)panel, (void *)w, (void *)q, (void *)logdet, (void *)piv, (void *)perm,
-                    (void *)sign, (void *)status, (void *)gdesc, (void *)rdesc, (void *)mptr})
+                    (void *)sign, (void *)status, (void *)gdesc, (void *)rdesc, (void *)mptr, (void *)pmax})
         dfree(p);
-    m = panel = w = q = logdet = nullptr;
+    m = panel = w = q = logdet = pmax = nullptr;
     piv = perm = sign = status = nullptr;
     gdesc = nullptr;
     rdesc = nullptr;

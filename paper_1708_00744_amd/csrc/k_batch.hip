@@ -268,7 +268,7 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
             __syncthreads();
         }
         const double r = G[a * LD + a] - part;
-        const bool finite_nz = (r == r) && (r != 0.0) && (fabs(r) <= 1.7976931348623157e308);
+        const bool finite_nz = fabs(r) > RatioFloor<T>::value && fabs(r) <= 1.7976931348623157e308;
         const bool ok = finite_nz && (force_accept || s_u[a] < r * r);
         if (!finite_nz) ++bad;
         if (tid == 0) { s_ratio[a] = r; s_ok[a] = ok; }
@@ -393,7 +393,8 @@ template <typename T, int KP> struct StreamCfg {
     static constexpr int LDT = CW + 1;
     static constexpr int LDY = KP + 16 / (int)sizeof(T);
     static constexpr int chunk = KP * LDV + KP * LDU + 64 * LDT;
-    static constexpr int elems = chunk > 64 * LDY ? chunk : 64 * LDY;
+    static constexpr int wpart = 64 * LDY + WCfg<T, KP>::elems;
+    static constexpr int elems = chunk > wpart ? chunk : wpart;
 };
 
 template <typename T, int KP>
@@ -425,19 +426,7 @@ __global__ __launch_bounds__(kThreads) void k_flush_stream(const DetDesc<T> *__r
     }
     __syncthreads();
     typename Mma<T>::acc_t wacc[KP / 16];
-#pragma unroll
-    for (int t = 0; t < KP / 16; ++t) wacc[t] = typename Mma<T>::acc_t{0, 0, 0, 0};
-    for (int s = 0; s < KP / 4; ++s) {
-        const int jc = 4 * s + (lane >> 4);
-        const T a = lds[(16 * wave + (lane & 15)) * LDY + jc];
-#pragma unroll
-        for (int t = 0; t < KP / 16; ++t) {
-            const int lr = 16 * t + (lane & 15);
-            const T bb = (lr < kslots && jc < kslots) ? T(dd.cfl[(size_t)lr * kp + jc]) : T(0);
-            wacc[t] = Mma<T>::mma(a, bb, wacc[t]);
-        }
-    }
-    __syncthreads();
+    w_from_y<T, KP>(lds, LDY, dd.cfl, kp, kslots, lds + 64 * LDY, wacc);
 #pragma unroll
     for (int t = 0; t < KP / 16; ++t)
 #pragma unroll

@@ -22,7 +22,7 @@ namespace dsu {
 template <typename T, int KP> struct FlushLds {
     static constexpr int LDY = KP + 16 / (int)sizeof(T);
     static constexpr int p1 = KP * (128 / (int)sizeof(T) + 16 / (int)sizeof(T));
-    static constexpr int p2 = 64 * LDY;
+    static constexpr int p2 = 64 * LDY + WCfg<T, KP>::elems;  // Y' block + staged C chunk
     static constexpr int p3 = KP * Phase3Cfg<T, KP>::LDV;
     static constexpr int m12 = p1 > p2 ? p1 : p2;
     static constexpr int elems = m12 > p3 ? m12 : p3;
@@ -56,19 +56,7 @@ __global__ __launch_bounds__(kThreads) void k_flush_mfma(const FlushDesc<T> *__r
     }
     __syncthreads();
     typename Mma<T>::acc_t wacc[KP / 16];
-#pragma unroll
-    for (int t = 0; t < KP / 16; ++t) wacc[t] = typename Mma<T>::acc_t{0, 0, 0, 0};
-    for (int s = 0; s < KP / 4; ++s) {
-        const int jc = 4 * s + (lane >> 4);
-        const T a = lds[(16 * wave + (lane & 15)) * LDY + jc];
-#pragma unroll
-        for (int t = 0; t < KP / 16; ++t) {
-            const int lr = 16 * t + (lane & 15);
-            const T bb = (lr < kslots && jc < kslots) ? T(fd.cinv[(size_t)lr * fd.ldc + jc]) : T(0);
-            wacc[t] = Mma<T>::mma(a, bb, wacc[t]);
-        }
-    }
-    __syncthreads();
+    w_from_y<T, KP>(lds, LDY, fd.cinv, fd.ldc, kslots, lds + 64 * LDY, wacc);
 #pragma unroll
     for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
@@ -217,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void k_gj_panel(const GjDesc *__restrict_
         const int j = v / np, i = v % np;
         P[(size_t)j * np + i] = g.m[(size_t)i * np + k0 + j];
     }
-    if (k0 == 0 && tid == 0) { *g.logdet = 0.0; *g.sign = 1; *g.status = 0; }
+    if (k0 == 0 && tid == 0) { *g.logdet = 0.0; *g.sign = 1; *g.status = 0; *g.pmax = 0.0; }
     __syncthreads();
     for (int kk = 0; kk < w; ++kk) {
         const int k = k0 + kk;
@@ -236,7 +224,10 @@ __global__ __launch_bounds__(kThreads) void k_gj_panel(const GjDesc *__restrict_
             double bv = s_v[0];
             int bidx = s_i[0];
             for (int q = 1; q < kThreads / 64; ++q) argmax_combine(bv, bidx, s_v[q], s_i[q]);
-            if (!(bv > 0.0)) { *g.status = -3; bidx = k; }
+            // singular when the best pivot is at rounding level of the largest one
+            const double pm = fmax(*g.pmax, bv);
+            *g.pmax = pm;
+            if (!(bv > (double)n * 2.220446049250313e-16 * pm)) { *g.status = -3; bidx = k; }
             s_p = bidx;
             g.piv[k] = bidx;
         }

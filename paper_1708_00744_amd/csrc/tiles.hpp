@@ -118,4 +118,44 @@ __device__ __forceinline__ void rowblock_plus_wv(T *__restrict__ rows, int ld, i
     }
 }
 
+
+// W = Y' C^T for the block's 64 rows: Y' (64 x KP) in LDS with pitch ldy,
+// C = inverse of eq. (3)'s C matrix, FP64 in global memory (pitch ldc), taken
+// as zero beyond kslots.  C is staged in LDS chunk by chunk (converted to T
+// and zero padded), so the product is a branch-free loop over LDS operands.
+template <typename T, int KP> struct WCfg {
+    // chunk budget: 32 KB, or 16 KB when the Y' block itself is large (FP64, K = 256)
+    static constexpr int budget = KP * (int)sizeof(T) >= 2048 ? 16384 : 32768;
+    static constexpr int JC = (KP * 64 * (int)sizeof(T) <= budget) ? 64
+                              : (KP * 32 * (int)sizeof(T) <= budget ? 32 : (KP * 16 * (int)sizeof(T) <= budget ? 16 : 8));
+    static constexpr int JCE = JC < KP ? JC : KP;
+    static constexpr int LDC = JCE + 16 / (int)sizeof(T);
+    static constexpr int elems = KP * LDC;
+};
+
+template <typename T, int KP>
+__device__ __forceinline__ void w_from_y(const T *ylds, int ldy, const double *__restrict__ cinv, int ldc, int kslots,
+                                         T *cbuf, typename Mma<T>::acc_t (&wacc)[KP / 16]) {
+    typedef WCfg<T, KP> C;
+    constexpr int JC = C::JCE, LDC = C::LDC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t) wacc[t] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    for (int j0 = 0; j0 < KP; j0 += JC) {
+        for (int v = tid; v < KP * JC; v += kThreads) {
+            const int l = v / JC, jj = v % JC, j = j0 + jj;
+            cbuf[l * LDC + jj] = (l < kslots && j < kslots) ? T(cinv[(size_t)l * ldc + j]) : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < JC / 4; ++s) {
+            const T a = ylds[(16 * wave + (lane & 15)) * ldy + j0 + 4 * s + (lane >> 4)];
+#pragma unroll
+            for (int t = 0; t < KP / 16; ++t)
+                wacc[t] = Mma<T>::mma(a, cbuf[(16 * t + (lane & 15)) * LDC + 4 * s + (lane >> 4)], wacc[t]);
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace dsu
