@@ -97,7 +97,8 @@ def headline(args, cache):
         roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    roof["kernel"] = "k_flush_mfma<float,%d>" % (16 if K <= 16 else 1 << math.ceil(math.log2(K)))
+    roof["kernel"] = "k_flush_stream<float,%d>" % (16 if K <= 16 else 1 << math.ceil(math.log2(K)))
+    roof["mfma_frac"] = flops / avg_s / 1e12 / PEAK_FP32_MFMA
     roof["avg_launch_ms"] = ms / cnt
     roof["launches"] = cnt
     roof["flops_per_launch"] = flops

@@ -386,15 +386,28 @@ template hipError_t launch_window_prime<double>(const DetDesc<double> *, int, in
 //     BT  -= W Vg[cur]              (eq. (4), row-local)
 //     y   += BT_new U[nxt]^T        (look-ahead products of the next window)
 //     rows of the next window -> Vg[nxt]
+// In the streaming pass the BT tile is kept transposed in the matrix cores:
+// D' = V^T (-W)^T, so that a lane's four results are one BT row's four
+// consecutive columns 16t + 4*(lane/16) + i (one vector load and store), and
+// the same registers are directly the A operand of the next window's product
+// BT_new U_next^T (its contraction order is free).  For the FP64 result layout
+// (rows lane/16 + 4i) the V operand of tile row m is taken from column
+// tcol(m) to give the same column set.
+template <typename T> __device__ __forceinline__ int tcol(int m) {
+    return Mma<T>::row_step == 1 ? m : 4 * (m & 3) + (m >> 2);
+}
+
 template <typename T, int KP> struct StreamCfg {
     static constexpr int CW = Phase3Cfg<T, KP>::CW;
-    static constexpr int LDV = Phase3Cfg<T, KP>::LDV;
-    static constexpr int LDU = CW + 1;
-    static constexpr int LDT = CW + 1;
-    static constexpr int LDY = KP + 16 / (int)sizeof(T);
-    static constexpr int chunk = KP * LDV + KP * LDU + 64 * LDT;
+    static constexpr int VEC = 16 / (int)sizeof(T);
+    static constexpr int LDVT = KP + VEC;  // V chunk stored transposed: [column][slot]
+    static constexpr int LDU = CW + VEC;
+    static constexpr int LDY = KP + VEC;
+    static constexpr int NV = KP * (CW / VEC) / kThreads;  // staged vectors per thread and operand
+    static constexpr int chunk = CW * LDVT + KP * LDU;
     static constexpr int wpart = 64 * LDY + WCfg<T, KP>::elems;
     static constexpr int elems = chunk > wpart ? chunk : wpart;
+    static_assert(NV >= 1 && NV * kThreads == KP * (CW / VEC), "staging split");
 };
 
 template <typename T, int KP>
@@ -402,22 +415,25 @@ __global__ __launch_bounds__(kThreads) void k_flush_stream(const DetDesc<T> *__r
                                                            int kp, int kslots, int cur, int has_next, int e0n,
                                                            int kwn) {
     typedef StreamCfg<T, KP> C;
-    constexpr int CW = C::CW, LDV = C::LDV, LDU = C::LDU, LDT = C::LDT, LDY = C::LDY, VEC = 16 / sizeof(T);
-    constexpr int RS = Mma<T>::row_step;
+    typedef typename Mma<T>::acc_t acc_t;
+    typedef typename Vec16<T>::type vec_t;
+    constexpr int CW = C::CW, LDVT = C::LDVT, LDU = C::LDU, LDY = C::LDY, VEC = C::VEC, NV = C::NV, NT = CW / 16;
+    constexpr int RS = Mma<T>::row_step, HV = 4 / VEC;  // 16-byte vectors per 4-element tile column group
+    constexpr int KQ = KP / 4;                          // slots per lane group in the V^T W^T product
     __shared__ __attribute__((aligned(16))) T lds[C::elems];
-    T *Vs = lds, *Us = lds + KP * LDV, *Ts = Us + KP * LDU;
+    T *Vt = lds, *Us = lds + CW * LDVT;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int d = b / nblk, r0 = (b % nblk) * kRowBlock;
     const DetDesc<T> dd = descs[d];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const T *vcur = cur ? dd.vg2 : dd.vg;
-    const T *unext = cur ? dd.u : dd.u2;
-    T *vnext = cur ? dd.vg : dd.vg2;
+    DSU_GLOBAL const T *vcur = gmem<const T>(cur ? dd.vg2 : dd.vg);
+    DSU_GLOBAL const T *unext = gmem<const T>(cur ? dd.u : dd.u2);
+    DSU_GLOBAL T *y = gmem(dd.y);
 
     // W = (y - E) C^{-T} for this block's 64 rows
     for (int v = tid; v < 64 * KP; v += kThreads) {
         const int i = v / KP, j = v % KP;
-        lds[i * LDY + j] = dd.y[(size_t)(r0 + i) * kp + j];
+        lds[i * LDY + j] = y[(size_t)(r0 + i) * kp + j];
     }
     __syncthreads();
     for (int j = tid; j < kslots; j += kThreads) {
@@ -425,77 +441,120 @@ __global__ __launch_bounds__(kThreads) void k_flush_stream(const DetDesc<T> *__r
         if (e >= r0 && e < r0 + kRowBlock) lds[(e - r0) * LDY + j] -= T(1);
     }
     __syncthreads();
-    typename Mma<T>::acc_t wacc[KP / 16];
-    w_from_y<T, KP>(lds, LDY, dd.cfl, kp, kslots, lds + 64 * LDY, wacc);
-#pragma unroll
-    for (int t = 0; t < KP / 16; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            lds[(16 * wave + Mma<T>::row0(lane) + i * RS) * LDY + 16 * t + (lane & 15)] = wacc[t][i];
-    __syncthreads();
     T wa[KP / 4];
+    {
+        acc_t wacc[KP / 16];
+        w_from_y<T, KP>(lds, LDY, dd.cfl, kp, kslots, lds + 64 * LDY, wacc);
 #pragma unroll
-    for (int s = 0; s < KP / 4; ++s) wa[s] = -lds[(16 * wave + (lane & 15)) * LDY + 4 * s + (lane >> 4)];
-    __syncthreads();
-
-    typename Mma<T>::acc_t accy[KP / 16];
+        for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
-    for (int t = 0; t < KP / 16; ++t) accy[t] = typename Mma<T>::acc_t{0, 0, 0, 0};
-    const int drow = 16 * wave + Mma<T>::row0(lane);  // this lane's first result row in the block
-    T *rp = dd.bt + (size_t)(r0 + drow) * np + (lane & 15);
-    for (int c0 = 0; c0 < np; c0 += CW) {
-        for (int v = tid; v < KP * (CW / VEC); v += kThreads) {
-            const int r = v / (CW / VEC), cc = (v % (CW / VEC)) * VEC;
-            *reinterpret_cast<V16<T> *>(Vs + r * LDV + cc) =
-                *reinterpret_cast<const V16<T> *>(vcur + (size_t)r * np + c0 + cc);
-        }
-        if (has_next)
-            for (int v = tid; v < KP * CW; v += kThreads) {
-                const int r = v / CW, cc = v % CW;
-                Us[r * LDU + cc] = unext[(size_t)r * np + c0 + cc];
-            }
-        typename Mma<T>::acc_t acc[CW / 16];
-#pragma unroll
-        for (int t = 0; t < CW / 16; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[t][i] = rp[(size_t)(i * RS) * np + c0 + 16 * t];
+            for (int i = 0; i < 4; ++i)
+                lds[(16 * wave + Mma<T>::row0(lane) + i * RS) * LDY + 16 * t + (lane & 15)] = wacc[t][i];
         __syncthreads();
+        // B operand of the V^T W^T product; its contraction runs over slot
+        // (lane/16)*KQ + s so that a lane's V operands are contiguous in Vt
 #pragma unroll
-        for (int s = 0; s < KP / 4; ++s) {
-            const T *bp = Vs + (4 * s + (lane >> 4)) * LDV + (lane & 15);
+        for (int s = 0; s < KQ; ++s) wa[s] = -lds[(16 * wave + (lane & 15)) * LDY + (lane >> 4) * KQ + s];
+        __syncthreads();
+    }
+
+    // this lane's BT row, and its first column in each 16-column tile
+    const int lrow = 16 * wave + (lane & 15);
+    DSU_GLOBAL T *rp = gmem(dd.bt) + (size_t)(r0 + lrow) * np + 4 * (lane >> 4);
+    const int g = r0 + lrow - e0n;
+    const bool wv = has_next && g >= 0 && g < kwn;
+    DSU_GLOBAL T *vp = gmem(cur ? dd.vg : dd.vg2) + (size_t)(wv ? g : 0) * np + 4 * (lane >> 4);
+    // staging of V and U: this thread's 16-byte pieces (row r, column cc of a chunk)
+    int goff[NV], voff[NV], uoff[NV];
 #pragma unroll
-            for (int t = 0; t < CW / 16; ++t) acc[t] = Mma<T>::mma(wa[s], bp[16 * t], acc[t]);
+    for (int q = 0; q < NV; ++q) {
+        const int v = tid + q * kThreads, r = v / (CW / VEC), cc = (v % (CW / VEC)) * VEC;
+        goff[q] = r * np + cc;
+        voff[q] = cc * LDVT + r;
+        uoff[q] = r * LDU + cc;
+    }
+    vec_t sv[NV], su[NV], nx[NT * HV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        sv[q] = *(DSU_GLOBAL const vec_t *)(vcur + goff[q]);
+        if (has_next) su[q] = *(DSU_GLOBAL const vec_t *)(unext + goff[q]);
+    }
+#pragma unroll
+    for (int h = 0; h < NT * HV; ++h) nx[h] = *(DSU_GLOBAL const vec_t *)(rp + (h / HV) * 16 + (h % HV) * VEC);
+
+    acc_t accy[KP / 16];
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t) accy[t] = acc_t{0, 0, 0, 0};
+    for (int c0 = 0; c0 < np; c0 += CW) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) Vt[voff[q] + e * LDVT] = sv[q][e];
+            if (has_next) *reinterpret_cast<vec_t *>(Us + uoff[q]) = su[q];
+        }
+        acc_t acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[t][i] = nx[t * HV + i / VEC][i % VEC];
+        __syncthreads();
+        const int c1 = c0 + CW;
+        if (c1 < np) {  // next chunk's loads stay in flight during this chunk's products
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                sv[q] = *(DSU_GLOBAL const vec_t *)(vcur + goff[q] + c1);
+                if (has_next) su[q] = *(DSU_GLOBAL const vec_t *)(unext + goff[q] + c1);
+            }
+#pragma unroll
+            for (int h = 0; h < NT * HV; ++h)
+                nx[h] = *(DSU_GLOBAL const vec_t *)(rp + c1 + (h / HV) * 16 + (h % HV) * VEC);
+        }
+        const T *ap = Vt + tcol<T>(lane & 15) * LDVT + (lane >> 4) * KQ;
+#pragma unroll
+        for (int j = 0; j < KQ / VEC; ++j) {
+            vec_t a[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) a[t] = *reinterpret_cast<const vec_t *>(ap + 16 * t * LDVT + j * VEC);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = Mma<T>::mma(a[t][e], wa[j * VEC + e], acc[t]);
         }
 #pragma unroll
-        for (int t = 0; t < CW / 16; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const T x = acc[t][i];
-                const int row = drow + i * RS;
-                const int col = c0 + 16 * t + (lane & 15);
-                rp[(size_t)(i * RS) * np + c0 + 16 * t] = x;
-                Ts[row * LDT + 16 * t + (lane & 15)] = x;
-                const int g = r0 + row - e0n;
-                if (has_next && g >= 0 && g < kwn) vnext[(size_t)g * np + col] = x;
+            for (int h = 0; h < HV; ++h) {
+                vec_t o;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) o[e] = acc[t][h * VEC + e];
+                *(DSU_GLOBAL vec_t *)(rp + c0 + 16 * t + h * VEC) = o;
+                if (wv) *(DSU_GLOBAL vec_t *)(vp + c0 + 16 * t + h * VEC) = o;
             }
-        // Ts rows 16w..16w+15 were written by this wave only: the A operands below
-        // read them back through LDS in program order.
         if (has_next) {
 #pragma unroll
-            for (int s = 0; s < CW / 4; ++s) {
-                const T a = Ts[(16 * wave + (lane & 15)) * LDT + 4 * s + (lane >> 4)];
+            for (int t = 0; t < NT; ++t) {
+                vec_t ub[KP / 16][HV];
 #pragma unroll
-                for (int t = 0; t < KP / 16; ++t)
-                    accy[t] = Mma<T>::mma(a, Us[(16 * t + (lane & 15)) * LDU + 4 * s + (lane >> 4)], accy[t]);
+                for (int jt = 0; jt < KP / 16; ++jt)
+#pragma unroll
+                    for (int h = 0; h < HV; ++h)
+                        ub[jt][h] = *reinterpret_cast<const vec_t *>(Us + (16 * jt + (lane & 15)) * LDU + 16 * t +
+                                                                     4 * (lane >> 4) + h * VEC);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int jt = 0; jt < KP / 16; ++jt)
+                        accy[jt] = Mma<T>::mma(acc[t][i], ub[jt][i / VEC][i % VEC], accy[jt]);
             }
         }
         __syncthreads();
     }
     if (has_next) {
+        const int drow = 16 * wave + Mma<T>::row0(lane);
 #pragma unroll
         for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) dd.y[(size_t)(r0 + drow + i * RS) * kp + 16 * t + (lane & 15)] = accy[t][i];
+            for (int i = 0; i < 4; ++i) y[(size_t)(r0 + drow + i * RS) * kp + 16 * t + (lane & 15)] = accy[t][i];
     }
 }
 

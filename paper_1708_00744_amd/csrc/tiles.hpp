@@ -8,6 +8,15 @@ namespace dsu {
 
 template <typename T> struct alignas(16) V16 { T v[16 / sizeof(T)]; };
 
+// 16-byte vector registers, and global-memory pointers: pointers read from a
+// descriptor are generic (flat) to the compiler; flat accesses also count
+// against the LDS wait counter, which would serialise prefetches with LDS use.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+#define DSU_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ DSU_GLOBAL T *gmem(T *p) { return (DSU_GLOBAL T *)p; }
+
 // The hardware hands consecutive workgroups to the 8 XCDs in turn; renumber
 // them so that each XCD (own L2) works on a contiguous range of logical blocks,
 // i.e. on the same determinant's U and Vg.

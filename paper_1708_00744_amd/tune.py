@@ -106,10 +106,11 @@ def main(argv):
     torch.cuda.set_device(0)
     c = load_cache()
     out_path = CACHE
+    delay_only = "--delay-only" in argv
     for a in argv:
         if a.startswith("--out="):
             out_path = a.split("=", 1)[1]
-    for n in (64, 128, 256, 512, 1024, 2048, 4096):
+    for n in () if delay_only else (64, 128, 256, 512, 1024, 2048, 4096):
         targets = (0.5, 0.75, 0.9, 0.99) if n <= 2048 else (0.99,)
         for t in targets:
             s, acc = tune_sigma(n, t, walkers=2 if n >= 2048 else 4)
