@@ -32,6 +32,33 @@ PEAK_FP64_MFMA = 78.6    # TFLOP/s
 PEAK_HBM = 8000.0        # GB/s
 
 
+# HBM bytes per launch of the flush kernel at this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
+# counter reads for a plain 1 GiB device copy (fetch x 2.000, write x 1.000).
+# Valid only for the kernel sources it was taken on; null once they change.
+FLUSH_TRAFFIC = {
+    "kernel": "k_flush_stream<float,64>",
+    "bytes_per_launch": 4587698995.0,
+    "sources_sha256": {
+        "k_batch.hip": "5a27fdb789e1c8cd8da6b4bca821413088045c89675d48f8490a323e5e30eaa3",
+        "tiles.hpp": "922215d624556b60ccf0f15ae683635301cd30a16be6b554702694307bfa1413",
+        "dsu_internal.hpp": "34ca2e42b2241767dbc593b8ae865def4ab30181d7161cc98ca43a3d1d06579f",
+    },
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    if kernel != FLUSH_TRAFFIC["kernel"]:
+        return None
+    csrc = os.path.join(ROOT, "paper_1708_00744_amd", "csrc")
+    for f, h in FLUSH_TRAFFIC["sources_sha256"].items():
+        with open(os.path.join(csrc, f), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != h:
+                return None
+    return FLUSH_TRAFFIC["bytes_per_launch"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -96,8 +123,8 @@ def headline(args, cache):
     else:
         roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
     roof["kernel"] = "k_flush_stream<float,%d>" % (16 if K <= 16 else 1 << math.ceil(math.log2(K)))
+    roof["traffic"] = measured_traffic(roof["kernel"])
     roof["mfma_frac"] = flops / avg_s / 1e12 / PEAK_FP32_MFMA
     roof["avg_launch_ms"] = ms / cnt
     roof["launches"] = cnt
@@ -229,7 +256,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (scale for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        torch.cuda.set_device(0)
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 3}))
+        return 0
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU: walkers shard across GPUs with no communication, "
                                    "so only --gpus 1 is supported"}))

@@ -297,6 +297,162 @@ __global__ __launch_bounds__(kThreads) void k_gj_swap(const GjDesc *__restrict__
     for (int kk = 0; kk < nb; ++kk) g.q[(size_t)kk * np + c] = kk < w ? g.m[(size_t)(k0 + kk) * np + c] : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Two-level panel factorisation (same algebra one level down).  One panel
+// pass of the single-workgroup step above moves the whole N x nb panel for
+// every column; here the panel's columns are factored WS at a time inside LDS
+// by one workgroup per determinant (k_gj_sub), and each group's row swaps and
+// rank-WS update  P_c <- P_c - (E - S) P_c[pivot rows]  reach the panel's
+// other columns through k_gj_sub_apply, spread over many workgroups.
+// ---------------------------------------------------------------------------
+constexpr int kGjThreads = 1024;
+
+// P[j][i] = M[i][k0 + j] for the panel's w columns (64-row tiles through LDS).
+__global__ __launch_bounds__(kThreads) void k_gj_gather(const GjDesc *__restrict__ descs, int np, int k0, int w) {
+    __shared__ double t[64][65];
+    const GjDesc g = descs[blockIdx.y];
+    const int r0 = blockIdx.x * 64, tid = threadIdx.x;
+    for (int v = tid; v < 64 * w; v += kThreads) {
+        const int i = v / w, j = v % w;
+        t[i][j] = g.m[(size_t)(r0 + i) * np + k0 + j];
+    }
+    __syncthreads();
+    for (int v = tid; v < 64 * w; v += kThreads) {
+        const int j = v / 64, i = v % 64;
+        g.panel[(size_t)j * np + r0 + i] = t[i][j];
+    }
+}
+
+template <int WS, int NPMAX>
+__global__ __launch_bounds__(kGjThreads) void k_gj_sub(const GjDesc *__restrict__ descs, int n, int np, int k0, int j0,
+                                                       int ws) {
+    __shared__ double S[WS * NPMAX];  // the group's columns, S[j * np + i]
+    __shared__ double s_v[kGjThreads / 64];
+    __shared__ int s_i[kGjThreads / 64];
+    __shared__ double s_row[WS];
+    __shared__ int s_p;
+    const GjDesc g = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *P = g.panel + (size_t)j0 * np;
+    for (int v = tid; v < ws * np; v += kGjThreads) S[v] = P[v];
+    if (k0 == 0 && j0 == 0 && tid == 0) { *g.logdet = 0.0; *g.sign = 1; *g.status = 0; *g.pmax = 0.0; }
+    __syncthreads();
+    for (int kk = 0; kk < ws; ++kk) {
+        const int k = k0 + j0 + kk;
+        const double *sc = S + kk * np;
+        double best = -1.0;
+        int bi = n;
+        for (int i = k + tid; i < n; i += kGjThreads) argmax_combine(best, bi, fabs(sc[i]), i);
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v2 = __shfl_xor(best, o, 64);
+            const int i2 = __shfl_xor(bi, o, 64);
+            argmax_combine(best, bi, v2, i2);
+        }
+        if (lane == 0) { s_v[wave] = best; s_i[wave] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double bv = s_v[0];
+            int bidx = s_i[0];
+            for (int q = 1; q < kGjThreads / 64; ++q) argmax_combine(bv, bidx, s_v[q], s_i[q]);
+            const double pm = fmax(*g.pmax, bv);
+            *g.pmax = pm;
+            if (!(bv > (double)n * 2.220446049250313e-16 * pm)) { *g.status = -3; bidx = k; }
+            s_p = bidx;
+            g.piv[k] = bidx;
+        }
+        __syncthreads();
+        const int p = s_p;
+        if (p != k && tid < ws) {
+            const double t = S[tid * np + k];
+            S[tid * np + k] = S[tid * np + p];
+            S[tid * np + p] = t;
+        }
+        __syncthreads();
+        const double d = S[kk * np + k];
+        if (tid == 0) {
+            if (d != 0.0) *g.logdet += log(fabs(d));
+            int sg = *g.sign;
+            if (p != k) sg = -sg;
+            if (d < 0.0) sg = -sg;
+            *g.sign = sg;
+        }
+        const double dinv = d != 0.0 ? 1.0 / d : 0.0;
+        if (tid < ws) s_row[tid] = tid == kk ? dinv : S[tid * np + k] * dinv;
+        __syncthreads();
+        for (int i = tid; i < np; i += kGjThreads) {
+            if (i == k) {
+                for (int j = 0; j < ws; ++j) S[j * np + i] = s_row[j];
+                continue;
+            }
+            const double f = S[kk * np + i];
+            for (int j = 0; j < ws; ++j) S[j * np + i] = j == kk ? -f * dinv : S[j * np + i] - f * s_row[j];
+        }
+        __syncthreads();
+    }
+    // the factored columns, and the group's update (E - S) column-major in w
+    for (int v = tid; v < ws * np; v += kGjThreads) {
+        const int j = v / np, i = v % np;
+        P[v] = S[v];
+        g.w[v] = (i == k0 + j0 + j ? 1.0 : 0.0) - S[v];
+    }
+}
+
+// The group's swaps, then P_c -= (E - S) Q_c, for every other panel column c.
+__global__ __launch_bounds__(kThreads) void k_gj_sub_apply(const GjDesc *__restrict__ descs, int np, int k0, int j0,
+                                                           int ws) {
+    const int c = blockIdx.x;
+    if (c >= j0 && c < j0 + ws) return;
+    __shared__ double q[64];
+    const GjDesc g = descs[blockIdx.y];
+    double *col = g.panel + (size_t)c * np;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        for (int kk = 0; kk < ws; ++kk) {
+            const int k = k0 + j0 + kk, p = g.piv[k];
+            if (p != k) {
+                const double t = col[k];
+                col[k] = col[p];
+                col[p] = t;
+            }
+        }
+        for (int kk = 0; kk < ws; ++kk) q[kk] = col[k0 + j0 + kk];
+    }
+    __syncthreads();
+    for (int i = tid; i < np; i += kThreads) {
+        double a = col[i];
+        for (int kk = 0; kk < ws; ++kk) a -= g.w[(size_t)kk * np + i] * q[kk];
+        col[i] = a;
+    }
+}
+
+// W = E_R - P, np x nb row-major, zero beyond the panel width (64-row tiles).
+__global__ __launch_bounds__(kThreads) void k_gj_wout(const GjDesc *__restrict__ descs, int np, int nb, int k0, int w) {
+    __shared__ double t[64][65];
+    const GjDesc g = descs[blockIdx.y];
+    const int r0 = blockIdx.x * 64, tid = threadIdx.x;
+    for (int v = tid; v < 64 * w; v += kThreads) {
+        const int j = v / 64, i = v % 64;
+        t[i][j] = g.panel[(size_t)j * np + r0 + i];
+    }
+    __syncthreads();
+    for (int v = tid; v < 64 * nb; v += kThreads) {
+        const int i = v / nb, j = v % nb, r = r0 + i;
+        g.w[(size_t)r * nb + j] = j < w ? ((r == k0 + j ? 1.0 : 0.0) - t[i][j]) : 0.0;
+    }
+}
+
+template <int WS, int NPMAX>
+static void launch_gj_panel2(const GjDesc *descs_dev, int ndesc, int n, int np, int nb, int k0, int w, hipStream_t s) {
+    hipLaunchKernelGGL(k_gj_gather, dim3(np / 64, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, w);
+    for (int j0 = 0; j0 < w; j0 += WS) {
+        const int ws = j0 + WS <= w ? WS : w - j0;
+        hipLaunchKernelGGL((k_gj_sub<WS, NPMAX>), dim3(ndesc), dim3(kGjThreads), 0, s, descs_dev, n, np, k0, j0, ws);
+        if (w > ws)
+            hipLaunchKernelGGL(k_gj_sub_apply, dim3(w, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, j0, ws);
+    }
+    hipLaunchKernelGGL(k_gj_wout, dim3(np / 64, ndesc), dim3(kThreads), 0, s, descs_dev, np, nb, k0, w);
+}
+
 // Final column permutation: idx = identity, then for k = n-1..0 swap idx[k], idx[piv[k]].
 __global__ void k_gj_perm(const GjDesc *__restrict__ descs, int n, int np) {
     const GjDesc g = descs[blockIdx.x];
@@ -315,7 +471,13 @@ hipError_t launch_gj_invert(const GjDesc *descs_dev, const RankDesc *rank_dev, i
     if (nb != 16 && nb != 32 && nb != 64) return hipErrorInvalidValue;
     for (int k0 = 0; k0 < n; k0 += nb) {
         const int k1 = k0 + nb < n ? k0 + nb : n;
-        hipLaunchKernelGGL(k_gj_panel, dim3(ndesc), dim3(kThreads), 0, s, descs_dev, n, np, nb, k0, k1);
+        // group width: the group's np x WS columns fill at most 128 KB of LDS
+        if (np <= 512) launch_gj_panel2<16, 512>(descs_dev, ndesc, n, np, nb, k0, k1 - k0, s);
+        else if (np <= 1024) launch_gj_panel2<16, 1024>(descs_dev, ndesc, n, np, nb, k0, k1 - k0, s);
+        else if (np <= 2048) launch_gj_panel2<8, 2048>(descs_dev, ndesc, n, np, nb, k0, k1 - k0, s);
+        else if (np <= 4096) launch_gj_panel2<4, 4096>(descs_dev, ndesc, n, np, nb, k0, k1 - k0, s);
+        else if (np <= 8192) launch_gj_panel2<2, 8192>(descs_dev, ndesc, n, np, nb, k0, k1 - k0, s);
+        else hipLaunchKernelGGL(k_gj_panel, dim3(ndesc), dim3(kThreads), 0, s, descs_dev, n, np, nb, k0, k1);
         hipLaunchKernelGGL(k_gj_swap, dim3((np + kThreads - 1) / kThreads, ndesc), dim3(kThreads), 0, s, descs_dev, np,
                            nb, k0, k1);
         hipError_t e = launch_rank_update(rank_dev, ndesc, np, nb, s);
@@ -338,10 +500,28 @@ __global__ __launch_bounds__(kThreads) void k_cast_perm(const GjDesc *__restrict
     out[(size_t)i * np + j] = (i < n && j < n) ? T(g.m[(size_t)i * np + g.perm[j]]) : T(0);
 }
 
+// The same with the row staged in LDS first (one row per workgroup): the
+// permuted gather then reads LDS instead of scattered global lines.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cast_perm_row(const GjDesc *__restrict__ gj, T *const *__restrict__ bt,
+                                                            int n, int np) {
+    __shared__ double row[8192];
+    const GjDesc g = gj[blockIdx.y];
+    T *out = bt[blockIdx.y] + (size_t)blockIdx.x * np;
+    const int i = blockIdx.x;
+    const double *src = g.m + (size_t)i * np;
+    for (int j = threadIdx.x; j < np; j += kThreads) row[j] = src[j];
+    __syncthreads();
+    for (int j = threadIdx.x; j < np; j += kThreads) out[j] = (i < n && j < n) ? T(row[g.perm[j]]) : T(0);
+}
+
 template <typename T>
 hipError_t launch_cast_perm(const GjDesc *gj_dev, T *const *bt_dev, int ndesc, int n, int np, hipStream_t s) {
-    hipLaunchKernelGGL((k_cast_perm<T>), dim3((np + kThreads - 1) / kThreads, np, ndesc), dim3(kThreads), 0, s, gj_dev,
-                       bt_dev, n, np);
+    if (np <= 8192)
+        hipLaunchKernelGGL((k_cast_perm_row<T>), dim3(np, ndesc), dim3(kThreads), 0, s, gj_dev, bt_dev, n, np);
+    else
+        hipLaunchKernelGGL((k_cast_perm<T>), dim3((np + kThreads - 1) / kThreads, np, ndesc), dim3(kThreads), 0, s,
+                           gj_dev, bt_dev, n, np);
     return hipGetLastError();
 }
 template hipError_t launch_cast_perm<float>(const GjDesc *, float *const *, int, int, int, hipStream_t);
