@@ -243,18 +243,24 @@ int dsu_server_create(int32_t k_delay, int32_t precision, double box_L, size_t b
                       int32_t recompute_every, dsu_server **out);
 int dsu_server_destroy(dsu_server *s);
 /* Manual control.  dsu_server_add admits one walker now (its arrival_s is
- * ignored): DSU_EBUDGET if it does not fit the free budget, DSU_EINVAL if it
- * never can.  dsu_server_step runs one sweep of every resident walker (the
- * sizes concurrently) and waits.  dsu_server_result reads a walker's result;
- * with remove = 1 it also retires the walker and frees its memory.
- * dsu_server_usage reports arena bytes in use and resident walkers. */
+ * ignored) and waits for its FP64 inverses: DSU_EBUDGET if it does not fit
+ * the free budget, DSU_EINVAL if it never can, DSU_ESINGULAR (not admitted)
+ * if a determinant is singular.  dsu_server_step runs one sweep of every
+ * resident walker (the sizes concurrently) and waits.  dsu_server_result
+ * reads a walker's result (status DSU_ESINGULAR if a periodic recompute found
+ * its matrix singular); with remove = 1 it also retires the walker and frees
+ * its memory.  dsu_server_usage reports arena bytes in use and resident
+ * walkers. */
 int dsu_server_add(dsu_server *s, const dsu_request *req, int32_t *slot_out);
 int dsu_server_step(dsu_server *s);
 int dsu_server_result(dsu_server *s, int32_t slot, dsu_result *out, int32_t remove);
 int dsu_server_usage(dsu_server *s, size_t *used_bytes, int32_t *resident_walkers);
 /* Serve `count` requests in arrival order (wall clock): admit by budget,
  * sweep all resident walkers (one batch per n, concurrently), retire
- * finished ones.  Fills results[count].  sweep_latency_ms (optional,
+ * finished ones.  Fills results[count]; a walker whose matrix is singular
+ * at admission or at a recompute ends early with status DSU_ESINGULAR (the
+ * inverses are computed on the device ahead of the walker's next sweep, so
+ * admission never waits for them).  sweep_latency_ms (optional,
  * capacity latency_cap) receives every per-walker sweep latency: the time
  * between consecutive sweep completions of a walker (the first measured from
  * its admission); *latency_count is the number written. */

@@ -110,6 +110,11 @@ void Bucket::release() {
     drop_graph();
     for (void *p : {(void *)kvec, ddesc_, fdesc_, sub_ddesc_, (void *)sub_pos_, (void *)sub_bt_, (void *)drift_})
         dfree(p);
+    if (status_h_) (void)hipHostFree(status_h_);
+    if (stage_h_) (void)hipHostFree(stage_h_);
+    status_h_ = nullptr;
+    stage_h_ = nullptr;
+    pending_.clear();
     kvec = nullptr;
     ddesc_ = fdesc_ = sub_ddesc_ = nullptr;
     sub_pos_ = nullptr;
@@ -128,10 +133,22 @@ void Bucket::release() {
     stream = nullptr;
 }
 
+static size_t stage_bytes_per() {
+    return std::max(sizeof(DetDesc<double>), sizeof(DetDesc<float>)) + sizeof(double *) + sizeof(void *);
+}
+
 int Bucket::ensure_capacity(int n) {
     if (n <= cap_) return DSU_OK;
     int c = std::max(n, cap_ * 2);
+    // pending recompute statuses survive the move (the stream has passed them:
+    // callers grow the arrays only between sweeps, after a synchronisation)
+    HIPCHK(hipStreamSynchronize(stream));
+    std::vector<int> keep(status_h_ ? status_h_ : nullptr, status_h_ ? status_h_ + pending_.size() : nullptr);
     for (void *p : {ddesc_, fdesc_, sub_ddesc_, (void *)sub_pos_, (void *)sub_bt_, (void *)drift_}) dfree(p);
+    if (status_h_) (void)hipHostFree(status_h_);
+    if (stage_h_) (void)hipHostFree(stage_h_);
+    status_h_ = nullptr;
+    stage_h_ = nullptr;
     const size_t dsz = std::max(sizeof(DetDesc<double>), sizeof(DetDesc<float>));
     const size_t fsz = std::max(sizeof(FlushDesc<double>), sizeof(FlushDesc<float>));
     CHK(dev_alloc(&ddesc_, dsz * c));
@@ -140,6 +157,9 @@ int Bucket::ensure_capacity(int n) {
     CHK(dalloc(&sub_pos_, c));
     CHK(dalloc(&sub_bt_, c));
     CHK(dalloc(&drift_, c));
+    HIPCHK(hipHostMalloc((void **)&status_h_, sizeof(int) * c));
+    HIPCHK(hipHostMalloc((void **)&stage_h_, stage_bytes_per() * c));
+    std::copy(keep.begin(), keep.end(), status_h_);
     cap_ = c;
     return DSU_OK;
 }
@@ -335,48 +355,67 @@ int Bucket::sweep(int force) {
     return enqueue_sweep(force);
 }
 
-template <typename T> int Bucket::recompute_t(const std::vector<int> &which, double *drift_host) {
+template <typename T> int Bucket::recompute_async_t(const std::vector<int> &which) {
     if (which.empty()) return DSU_OK;
-    const int cnt_all = (int)which.size();
-    std::vector<DetDesc<T>> sd(cnt_all);
-    std::vector<double *> sp(cnt_all);
-    std::vector<void *> sb(cnt_all);
+    const int base = (int)pending_.size(), cnt_all = (int)which.size();
+    if (base + cnt_all > cap_) return fail(DSU_ESTATE, "more pending recomputes than members");
+    // descriptors staged in pinned memory at this call's own offset, so that
+    // calls pending together do not overwrite each other's uploads
+    DetDesc<T> *hd = (DetDesc<T> *)stage_h_;
+    double **hp = (double **)(stage_h_ + std::max(sizeof(DetDesc<double>), sizeof(DetDesc<float>)) * cap_);
+    void **hb = (void **)((char *)hp + sizeof(double *) * cap_);
     for (int i = 0; i < cnt_all; ++i) {
         const DetSlot &s = dets[which[i]];
-        sd[i] = to_desc<T>(s);
-        sp[i] = s.pos;
-        sb[i] = s.bt;
+        hd[base + i] = to_desc<T>(s);
+        hp[base + i] = s.pos;
+        hb[base + i] = s.bt;
     }
-    HIPCHK(hipMemcpyAsync(sub_ddesc_, sd.data(), sizeof(sd[0]) * cnt_all, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(sub_pos_, sp.data(), sizeof(double *) * cnt_all, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(sub_bt_, sb.data(), sizeof(void *) * cnt_all, hipMemcpyHostToDevice, stream));
-    const DetDesc<T> *dd = (const DetDesc<T> *)sub_ddesc_;
-    std::vector<int> st(gj_.g);
+    DetDesc<T> *dd = (DetDesc<T> *)sub_ddesc_ + base;
+    HIPCHK(hipMemcpyAsync(dd, hd + base, sizeof(DetDesc<T>) * cnt_all, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(sub_pos_ + base, hp + base, sizeof(double *) * cnt_all, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(sub_bt_ + base, hb + base, sizeof(void *) * cnt_all, hipMemcpyHostToDevice, stream));
     for (int g0 = 0; g0 < cnt_all; g0 += gj_.g) {
         const int cnt = std::min(gj_.g, cnt_all - g0);
         CHK(timed(PH_RECOMPUTE, [&] {
-            hipError_t e = launch_build_pw_transpose(sub_pos_ + g0, gj_.mptr, cnt, sh.n, sh.np, kvec, twopi_l, stream);
+            hipError_t e =
+                launch_build_pw_transpose(sub_pos_ + base + g0, gj_.mptr, cnt, sh.n, sh.np, kvec, twopi_l, stream);
             if (e != hipSuccess) return e;
             e = launch_gj_invert(gj_.gdesc, gj_.rdesc, cnt, sh.n, sh.np, gj_.nb, stream);
             if (e != hipSuccess) return e;
-            e = launch_cast_perm<T>(gj_.gdesc, (T *const *)(sub_bt_ + g0), cnt, sh.n, sh.np, stream);
+            e = launch_cast_perm<T>(gj_.gdesc, (T *const *)(sub_bt_ + base + g0), cnt, sh.n, sh.np, stream);
             if (e != hipSuccess) return e;
-            return launch_reset_state<T>(dd + g0, gj_.gdesc, drift_ + g0, cnt, stream);
+            return launch_reset_state<T>(dd + g0, gj_.gdesc, drift_ + base + g0, cnt, stream);
         }));
-        HIPCHK(hipMemcpyAsync(st.data(), gj_.status, sizeof(int) * cnt, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
-        for (int i = 0; i < cnt; ++i)
-            if (st[i] != 0) return fail(DSU_ESINGULAR, "determinant %d: Slater matrix is singular", which[g0 + i]);
+        HIPCHK(hipMemcpyAsync(status_h_ + base + g0, gj_.status, sizeof(int) * cnt, hipMemcpyDeviceToHost, stream));
     }
-    if (drift_host) {
-        HIPCHK(hipMemcpyAsync(drift_host, drift_, sizeof(double) * cnt_all, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
-    }
+    pending_.insert(pending_.end(), which.begin(), which.end());
     return DSU_OK;
 }
 
+int Bucket::recompute_async(const std::vector<int> &which) {
+    return sh.prec == DSU_FP64 ? recompute_async_t<double>(which) : recompute_async_t<float>(which);
+}
+
+void Bucket::check_recompute(std::vector<int> *singular) {
+    for (size_t i = 0; i < pending_.size(); ++i)
+        if (status_h_[i] != 0 && singular) singular->push_back(pending_[i]);
+    pending_.clear();
+}
+
 int Bucket::recompute(const std::vector<int> &which, double *drift_host) {
-    return sh.prec == DSU_FP64 ? recompute_t<double>(which, drift_host) : recompute_t<float>(which, drift_host);
+    if (which.empty()) return DSU_OK;
+    HIPCHK(hipStreamSynchronize(stream));
+    check_recompute(nullptr);
+    CHK(recompute_async(which));
+    HIPCHK(hipStreamSynchronize(stream));
+    std::vector<int> bad;
+    check_recompute(&bad);
+    if (!bad.empty()) return fail(DSU_ESINGULAR, "determinant %d: Slater matrix is singular", bad[0]);
+    if (drift_host) {
+        HIPCHK(hipMemcpyAsync(drift_host, drift_, sizeof(double) * which.size(), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+    return DSU_OK;
 }
 
 // Plane-wave table: orbitals by shells s = |n|^2 = 0, 1, 2, ...; inside a

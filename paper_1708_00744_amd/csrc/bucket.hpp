@@ -60,6 +60,15 @@ class Bucket {
     // and reports a singular matrix.  drift_dev (optional, per listed member)
     // receives running-minus-fresh log|det|.
     int recompute(const std::vector<int> &which, double *drift_host);
+    // The same, only enqueued on the bucket's stream: nothing waits.  Status
+    // words land in pinned host memory; once the stream has passed this point,
+    // check_recompute() lists the members (indices into dets) found singular.
+    // Several calls may be pending at once; members must not be reordered
+    // until they are checked.
+    int recompute_async(const std::vector<int> &which);
+    void check_recompute(std::vector<int> *singular);
+    // Pre-size the descriptor arrays for n members.
+    int reserve(int n) { return ensure_capacity(n); }
     int harvest_events();
     long long t_count[PH_COUNT] = {0};
     double t_ms[PH_COUNT] = {0};
@@ -71,6 +80,9 @@ class Bucket {
     double **sub_pos_ = nullptr;
     void **sub_bt_ = nullptr;
     double *drift_ = nullptr;
+    int *status_h_ = nullptr;      // pinned: one status word per pending recompute
+    char *stage_h_ = nullptr;      // pinned: descriptor staging of pending recomputes
+    std::vector<int> pending_;
     GjWork gj_;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t gexec_ = nullptr;
@@ -86,7 +98,7 @@ class Bucket {
     template <typename T> int upload_t();
     template <typename T> int enqueue_sweep_t(int force_accept);
     template <typename T> int enqueue_sweep_stream_t(int force_accept);
-    template <typename T> int recompute_t(const std::vector<int> &which, double *drift_host);
+    template <typename T> int recompute_async_t(const std::vector<int> &which);
 };
 
 }  // namespace dsu

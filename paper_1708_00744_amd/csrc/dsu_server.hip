@@ -82,6 +82,7 @@ struct Resident {
     std::vector<DetSlot> dets;
     double admit_s = 0.0, last_s = 0.0;
     int result_index = -1;
+    int status = DSU_OK;  // DSU_ESINGULAR once an inverse of the walker came out singular
 };
 
 struct BucketState {
@@ -113,7 +114,9 @@ static int bucket_for(dsu_server *s, int n, BucketState **out) {
     }
     std::unique_ptr<BucketState> b(new BucketState());
     const BucketShape sh = BucketShape::make(n, s->K, s->prec);
-    int rc = b->bk.init(sh, s->K, s->L, nullptr, 1);
+    // recomputes run four determinants per pass; descriptor room for 64
+    int rc = b->bk.init(sh, s->K, s->L, nullptr, 4);
+    if (rc == DSU_OK) rc = b->bk.reserve(64);
     if (rc != DSU_OK) {
         b->bk.release();
         return rc;
@@ -186,10 +189,12 @@ static int admit(dsu_server *s, const dsu_request &r, double now_s, int result_i
     b->members.push_back(slot);
     rc = refresh_bucket(s, b);
     if (rc == DSU_OK) {
-        // FP64 inverse of the new walker's determinants (the last members).
+        // FP64 inverse of the new walker's determinants (the last members),
+        // enqueued ahead of the bucket's next sweep; a singular start is
+        // reported when that sweep completes.
         std::vector<int> which;
         for (int i = 0; i < r.spins; ++i) which.push_back((int)b->bk.dets.size() - r.spins + i);
-        rc = b->bk.recompute(which, nullptr);
+        rc = b->bk.recompute_async(which);
     }
     if (rc != DSU_OK) {
         b->members.pop_back();
@@ -205,7 +210,7 @@ static int admit(dsu_server *s, const dsu_request &r, double now_s, int result_i
 static int read_result(dsu_server *s, int slot, dsu_result *out) {
     Resident &w = s->resident[slot];
     out->request_id = w.request_id;
-    out->status = DSU_OK;
+    out->status = w.status;
     out->sweeps_done = w.sweeps_done;
     out->admit_s = w.admit_s;
     out->finish_s = w.last_s;
@@ -246,7 +251,34 @@ static int recompute_due(dsu_server *s, BucketState *b) {
         for (int sp = 0; sp < w.spins; ++sp, ++pos)
             if (due) which.push_back(pos);
     }
-    return b->bk.recompute(which, nullptr);
+    return b->bk.recompute_async(which);
+}
+
+static int slot_of_det(dsu_server *s, BucketState *b, int pos);
+
+// After bucket b's stream has passed its pending recomputes: flag the walkers
+// whose inverse came out singular; returns their slots.
+static std::vector<int> flag_singular(dsu_server *s, BucketState *b) {
+    std::vector<int> bad, slots;
+    b->bk.check_recompute(&bad);
+    for (int pos : bad) {
+        const int slot = slot_of_det(s, b, pos);
+        if (slot >= 0 && std::find(slots.begin(), slots.end(), slot) == slots.end()) {
+            slots.push_back(slot);
+            s->resident[slot].status = DSU_ESINGULAR;
+        }
+    }
+    return slots;
+}
+
+// Slot of the walker that owns determinant `pos` of bucket b (descriptor order).
+static int slot_of_det(dsu_server *s, BucketState *b, int pos) {
+    for (int slot : b->members) {
+        const int sp = s->resident[slot].spins;
+        if (pos < sp) return slot;
+        pos -= sp;
+    }
+    return -1;
 }
 
 extern "C" int dsu_server_create(int32_t k_delay, int32_t precision, double box_L, size_t budget_bytes,
@@ -290,7 +322,17 @@ extern "C" int dsu_server_add(dsu_server *s, const dsu_request *req, int32_t *sl
     if (!s || !req) return fail(DSU_EINVAL, "NULL argument");
     auto it = s->buckets.find(req->n);
     if (it != s->buckets.end() && it->second->busy) return fail(DSU_ESTATE, "bucket busy");
-    return admit(s, *req, 0.0, -1, slot_out);
+    int slot = -1;
+    CHK(admit(s, *req, 0.0, -1, &slot));
+    BucketState *b = s->buckets[req->n].get();
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    const std::vector<int> bad = flag_singular(s, b);
+    if (std::find(bad.begin(), bad.end(), slot) != bad.end()) {
+        retire(s, slot);
+        return fail(DSU_ESINGULAR, "request %llu: Slater matrix is singular", (unsigned long long)req->request_id);
+    }
+    if (slot_out) *slot_out = slot;
+    return DSU_OK;
 }
 
 extern "C" int dsu_server_step(dsu_server *s) {
@@ -308,6 +350,7 @@ extern "C" int dsu_server_step(dsu_server *s) {
         if (!b->busy) continue;
         HIPCHK(hipEventSynchronize(b->done));
         b->busy = false;
+        (void)flag_singular(s, b);
         for (int slot : b->members) s->resident[slot].sweeps_done += 1;
         CHK(recompute_due(s, b));
     }
@@ -362,6 +405,12 @@ extern "C" int dsu_server_run(dsu_server *s, const dsu_request *reqs, int32_t co
             if (q != hipSuccess) return fail(DSU_EDEVICE, "hipEventQuery: %s", hipGetErrorString(q));
             b->busy = false;
             const double td = now_s();
+            // walkers whose (re)computed inverse came out singular leave with that status
+            for (int slot : flag_singular(s, b)) {
+                CHK(read_result(s, slot, &results[s->resident[slot].result_index]));
+                retire(s, slot);
+                ++completed;
+            }
             std::vector<int> finished;
             for (int slot : b->members) {
                 Resident &w = s->resident[slot];
