@@ -323,17 +323,137 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
     }
 }
 
+// The same decisions for windows of up to 64 slots as an in-place
+// Gauss-Jordan sweep over G in slot order, pivoting only on accepted slots:
+// before slot a is decided, G[a][a] has had every earlier accepted slot
+// eliminated, so it is the Schur complement r0 - p^T C^{-1} q of the
+// look-ahead; after the window, G restricted to the accepted slots is C^{-1}.
+// Four waves; wave w holds rows w*KP/4 .. of G, lane y column y, in registers
+// (the loop over slots is unrolled, so every register index is fixed).  A
+// step is one LDS exchange of the pivot row and one barrier; the pivot
+// column comes from lane j of each wave.
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__restrict__ descs, int kp, int e0,
+                                                          int kw, int nsplit, int force_accept, int last_window,
+                                                          int g_from_y) {
+    constexpr int RW = KP / 4;
+    __shared__ double s_row[2][64];
+    __shared__ double s_u[KP], s_ratio[KP];
+    __shared__ int s_ok[KP];
+    const DetDesc<T> d = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double g[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int a = wave * RW + r, b = lane;
+        double v = a == b ? 1.0 : 0.0;
+        if (a < kw && b < kw) {
+            if (g_from_y) v = (double)d.y[(size_t)(e0 + b) * kp + a];
+            else {
+                v = 0.0;
+                for (int q = 0; q < nsplit; ++q) v += (double)d.gpart[((size_t)q * kp + b) * kp + a];
+            }
+        }
+        g[r] = v;
+    }
+    for (int a = tid; a < KP; a += 256) {
+        s_u[a] = a < kw ? d.prop[4 * a + 3] : 0.0;
+        s_ok[a] = 0;
+    }
+    // |prod R| kept as mantissa * 2^exponent; one log at the end
+    int m = 0, sgn = 1, bad = 0, pexp = 0;
+    double pman = 1.0;
+#pragma unroll 1
+    for (int jb = 0; jb < 4; ++jb) {
+#pragma unroll
+        for (int jj = 0; jj < RW; ++jj) {
+            const int j = jb * RW + jj;
+            if (j < kw) {
+                double *row = s_row[j & 1];
+                if (wave == jb) row[lane] = g[jj];
+                __syncthreads();
+                const double r = row[j];
+                const bool finite_nz = fabs(r) > RatioFloor<T>::value && fabs(r) <= 1.7976931348623157e308;
+                const bool ok = finite_nz && (force_accept || s_u[j] < r * r);
+                if (!finite_nz) ++bad;
+                if (tid == 0) {
+                    s_ratio[j] = r;
+                    s_ok[j] = ok;
+                }
+                if (ok) {
+                    const double dinv = 1.0 / r;
+                    const double rj = lane == j ? dinv : row[lane] * dinv;
+#pragma unroll
+                    for (int q = 0; q < RW; ++q) {
+                        // column j of this wave's rows, from lane j (a uniform lane index)
+                        const double gq = g[q];
+                        const int lo = __builtin_amdgcn_readlane(__double2loint(gq), j);
+                        const int hi = __builtin_amdgcn_readlane(__double2hiint(gq), j);
+                        const double f = __hiloint2double(hi, lo);
+                        if (wave * RW + q == j) g[q] = rj;
+                        else g[q] = lane == j ? -f * dinv : gq - f * rj;
+                    }
+                    int e;
+                    pman *= frexp(fabs(r), &e);
+                    pexp += e;
+                    pman = frexp(pman, &e);
+                    pexp += e;
+                    if (r < 0.0) sgn = -sgn;
+                    ++m;
+                }
+            }
+        }
+    }
+    const double logdet = log(pman) + (double)pexp * 0.69314718055994530942;
+    __syncthreads();
+    // zero-embedded C^{-1} for the flush, electrons, positions, state, trace
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int a = wave * RW + r;
+        if (lane < KP) d.cfl[(size_t)a * kp + lane] = (s_ok[a] && s_ok[lane]) ? g[r] : 0.0;
+    }
+    for (int a = tid; a < KP; a += 256) d.idx[a] = a < kw ? e0 + a : -1;
+    for (int v = tid; v < kw * 3; v += 256) {
+        const int a = v / 3, c = v % 3;
+        if (s_ok[a]) d.pos[3 * (e0 + a) + c] = d.prop[4 * a + c];
+    }
+    if (tid == 0) {
+        DetState *st = d.st;
+        if (d.trace_r) {
+            const long long p0 = st->trace_pos;
+            for (int a = 0; a < kw; ++a)
+                if (p0 + a < d.trace_cap) {
+                    d.trace_r[p0 + a] = s_ratio[a];
+                    d.trace_a[p0 + a] = (uint8_t)s_ok[a];
+                }
+            st->trace_pos = p0 + kw;
+        }
+        st->logdet += logdet;
+        st->sign *= sgn;
+        st->accepted += m;
+        st->bad += bad;
+        if (last_window) st->sweep += 1;
+    }
+}
+
 template <typename T>
 hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int nsplit,
                                 int force_accept, int last_window, hipStream_t s, int g_from_y) {
+#define DSU_G(KPV)                                                                                                \
+    if (ktile == KPV) {                                                                                           \
+        hipLaunchKernelGGL((k_window_decide_gj<T, KPV>), dim3(ndesc), dim3(256), 0, s, d, kp, e0, kw, nsplit,     \
+                           force_accept, last_window, g_from_y);                                                  \
+        return hipGetLastError();                                                                                 \
+    }
 #define DSU_D(KPV)                                                                                                \
     if (ktile == KPV) {                                                                                           \
         hipLaunchKernelGGL((k_window_decide<T, KPV>), dim3(ndesc), dim3(DecideCfg<KPV>::threads), 0, s, d, kp,    \
                            e0, kw, nsplit, force_accept, last_window, g_from_y);                                  \
         return hipGetLastError();                                                                                 \
     }
-    DSU_D(16) DSU_D(32) DSU_D(64) DSU_D(128) DSU_D(256)
+    DSU_G(16) DSU_G(32) DSU_G(64) DSU_D(128) DSU_D(256)
 #undef DSU_D
+#undef DSU_G
     return hipErrorInvalidValue;
 }
 template hipError_t launch_window_decide<float>(const DetDesc<float> *, int, int, int, int, int, int, int, int,
