@@ -524,7 +524,8 @@ template <typename T, int KP> struct StreamCfg {
     static constexpr int LDU = CW + VEC;
     static constexpr int LDY = KP + VEC;
     static constexpr int NV = KP * (CW / VEC) / kThreads;  // staged vectors per thread and operand
-    static constexpr int chunk = CW * LDVT + KP * LDU;
+    static constexpr int buf = CW * LDVT + KP * LDU;  // one chunk's V^T and U
+    static constexpr int chunk = 2 * buf;                // double-buffered
     static constexpr int wpart = 64 * LDY + WCfg<T, KP>::elems;
     static constexpr int elems = chunk > wpart ? chunk : wpart;
     static_assert(NV >= 1 && NV * kThreads == KP * (CW / VEC), "staging split");
@@ -541,7 +542,6 @@ __global__ __launch_bounds__(kThreads) void k_flush_stream(const DetDesc<T> *__r
     constexpr int RS = Mma<T>::row_step, HV = 4 / VEC;  // 16-byte vectors per 4-element tile column group
     constexpr int KQ = KP / 4;                          // slots per lane group in the V^T W^T product
     __shared__ __attribute__((aligned(16))) T lds[C::elems];
-    T *Vt = lds, *Us = lds + CW * LDVT;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int d = b / nblk, r0 = (b % nblk) * kRowBlock;
     const DetDesc<T> dd = descs[d];
@@ -593,6 +593,9 @@ __global__ __launch_bounds__(kThreads) void k_flush_stream(const DetDesc<T> *__r
         voff[q] = cc * LDVT + r;
         uoff[q] = r * LDU + cc;
     }
+    // chunk c's V^T and U sit in LDS buffer c & 1; chunk c+1's are loaded into
+    // registers while chunk c's products run, then written to the other buffer:
+    // one barrier per chunk
     vec_t sv[NV], su[NV], nx[NT * HV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -601,23 +604,26 @@ __global__ __launch_bounds__(kThreads) void k_flush_stream(const DetDesc<T> *__r
     }
 #pragma unroll
     for (int h = 0; h < NT * HV; ++h) nx[h] = *(DSU_GLOBAL const vec_t *)(rp + (h / HV) * 16 + (h % HV) * VEC);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) lds[voff[q] + e * LDVT] = sv[q][e];
+        if (has_next) *reinterpret_cast<vec_t *>(lds + CW * LDVT + uoff[q]) = su[q];
+    }
+    __syncthreads();
 
     acc_t accy[KP / 16];
 #pragma unroll
     for (int t = 0; t < KP / 16; ++t) accy[t] = acc_t{0, 0, 0, 0};
-    for (int c0 = 0; c0 < np; c0 += CW) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) Vt[voff[q] + e * LDVT] = sv[q][e];
-            if (has_next) *reinterpret_cast<vec_t *>(Us + uoff[q]) = su[q];
-        }
+    int cb = 0;  // current buffer
+    for (int c0 = 0; c0 < np; c0 += CW, cb ^= 1) {
+        const T *Vt = lds + cb * C::buf;
+        const T *Us = Vt + CW * LDVT;
         acc_t acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) acc[t][i] = nx[t * HV + i / VEC][i % VEC];
-        __syncthreads();
         const int c1 = c0 + CW;
         if (c1 < np) {  // next chunk's loads stay in flight during this chunk's products
 #pragma unroll
@@ -665,6 +671,16 @@ __global__ __launch_bounds__(kThreads) void k_flush_stream(const DetDesc<T> *__r
 #pragma unroll
                     for (int jt = 0; jt < KP / 16; ++jt)
                         accy[jt] = Mma<T>::mma(acc[t][i], ub[jt][i / VEC][i % VEC], accy[jt]);
+            }
+        }
+        if (c1 < np) {
+            // the other buffer was last read before the previous barrier
+            T *nb = lds + (cb ^ 1) * C::buf;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) nb[voff[q] + e * LDVT] = sv[q][e];
+                if (has_next) *reinterpret_cast<vec_t *>(nb + CW * LDVT + uoff[q]) = su[q];
             }
         }
         __syncthreads();
