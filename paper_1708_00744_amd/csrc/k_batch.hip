@@ -820,17 +820,24 @@ __global__ __launch_bounds__(kThreads, 2) void k_flush_stream32(const DetDesc<fl
                 for (int h = 0; h < NT * 4; ++h)
                     nx[h] = *(DSU_GLOBAL const vec_t *)(rp + c1 + (h / 4) * 32 + (h % 4) * 8);
         }
+        // operands of the next group of products are read from LDS while the
+        // current group runs
         const float *ap = Vt + (lane & 31) * LDVT + (lane >> 5) * KH;
+        vec_t a[2][NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) a[0][t] = *reinterpret_cast<const vec_t *>(ap + 32 * t * LDVT);
 #pragma unroll
         for (int j = 0; j < KH / 4; ++j) {
-            vec_t a[NT];
+            if (j + 1 < KH / 4)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) a[t] = *reinterpret_cast<const vec_t *>(ap + 32 * t * LDVT + 4 * j);
+                for (int t = 0; t < NT; ++t)
+                    a[(j + 1) & 1][t] = *reinterpret_cast<const vec_t *>(ap + 32 * t * LDVT + 4 * (j + 1));
+            __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this group's products
 #pragma unroll
             for (int e = 0; e < 4; ++e)
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t][e], wa[4 * j + e], acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j & 1][t][e], wa[4 * j + e], acc[t], 0, 0, 0);
         }
         if (wvalid)
 #pragma unroll
@@ -842,22 +849,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_flush_stream32(const DetDesc<fl
                     if (wv) *(DSU_GLOBAL vec_t *)(vp + c0 + 32 * t + 8 * gq) = o;
                 }
         if (has_next) {
+            const float *up = Us + (lane & 31) * LDU + 4 * (lane >> 5);
+            vec_t ub[2][JT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int jt = 0; jt < JT; ++jt) ub[0][jt] = *reinterpret_cast<const vec_t *>(up + 32 * jt * LDU);
 #pragma unroll
-                for (int gq = 0; gq < 4; ++gq) {
-                    vec_t ub[JT];
+            for (int q = 0; q < NT * 4; ++q) {  // q = 4t + gq
+                if (q + 1 < NT * 4)
 #pragma unroll
                     for (int jt = 0; jt < JT; ++jt)
-                        ub[jt] = *reinterpret_cast<const vec_t *>(Us + (32 * jt + (lane & 31)) * LDU + 32 * t + 8 * gq +
-                                                                  4 * (lane >> 5));
+                        ub[(q + 1) & 1][jt] = *reinterpret_cast<const vec_t *>(
+                            up + 32 * jt * LDU + 32 * ((q + 1) / 4) + 8 * ((q + 1) % 4));
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
+                for (int e = 0; e < 4; ++e)
 #pragma unroll
-                        for (int jt = 0; jt < JT; ++jt)
-                            accy[jt] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[t][4 * gq + e], ub[jt][e], accy[jt],
-                                                                            0, 0, 0);
-                }
+                    for (int jt = 0; jt < JT; ++jt)
+                        accy[jt] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[q / 4][4 * (q % 4) + e], ub[q & 1][jt][e],
+                                                                        accy[jt], 0, 0, 0);
+            }
         }
         if (c1 < np) {
             float *nb = lds + (cb ^ 1) * C::buf;
