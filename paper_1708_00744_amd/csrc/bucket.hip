@@ -101,6 +101,8 @@ int Bucket::init(const BucketShape &shape, int k_delay, double box_l, void *stre
     std::vector<int4> kv(sh.n);
     build_kvectors(sh.n, kv.data());
     HIPCHK(hipMemcpy(kvec, kv.data(), sizeof(int4) * sh.n, hipMemcpyHostToDevice));
+    kmax_comp = 0;
+    for (const int4 &k : kv) kmax_comp = std::max({kmax_comp, std::abs(k.x), std::abs(k.y), std::abs(k.z)});
     CHK(gj_.alloc(std::max(1, gj_group), sh.np, sh.n));
     return DSU_OK;
 }
@@ -273,7 +275,7 @@ template <typename T> int Bucket::enqueue_sweep_t(int force) {
         const int kw = std::min(K, sh.n - e0);
         const int last = e0 + kw == sh.n;
         CHK(timed(PH_ROWS, [&] {
-            return launch_window_rows<T>(dd, nd, sh.n, sh.np, kt, e0, kw, kvec, twopi_l, stream);
+            return launch_window_rows<T>(dd, nd, sh.n, sh.np, kt, e0, kw, kvec, twopi_l, kmax_comp, stream);
         }));
         CHK(timed(PH_G, [&] { return launch_window_g<T>(dd, nd, sh.np, kt, sh.kp, e0, sh.nsplit, stream); }));
         CHK(timed(PH_DECIDE, [&] {
@@ -294,7 +296,7 @@ template <typename T> int Bucket::enqueue_sweep_stream_t(int force) {
     const int nwin = (sh.n + K - 1) / K;
     auto kw_of = [&](int w) { return std::min(K, sh.n - w * K); };
     CHK(timed(PH_ROWS, [&] {
-        return launch_window_props<T>(dd, nd, sh.n, sh.np, kt, 0, kw_of(0), kvec, twopi_l, 0, 1, stream);
+        return launch_window_props<T>(dd, nd, sh.n, sh.np, kt, 0, kw_of(0), kvec, twopi_l, 0, 1, kmax_comp, stream);
     }));
     CHK(timed(PH_G, [&] { return launch_window_prime<T>(dd, nd, sh.np, kt, sh.kp, 0, stream); }));
     CHK(timed(PH_DECIDE, [&] {
@@ -306,7 +308,8 @@ template <typename T> int Bucket::enqueue_sweep_stream_t(int force) {
         const int e0n = (w + 1) * K, kwn = has_next ? kw_of(w + 1) : 0;
         if (has_next)
             CHK(timed(PH_ROWS, [&] {
-                return launch_window_props<T>(dd, nd, sh.n, sh.np, kt, e0n, kwn, kvec, twopi_l, nxt, 0, stream);
+                return launch_window_props<T>(dd, nd, sh.n, sh.np, kt, e0n, kwn, kvec, twopi_l, nxt, 0, kmax_comp,
+                                              stream);
             }));
         CHK(timed(PH_FLUSH, [&] {
             return launch_flush_stream<T>(dd, nd, sh.np, kt, sh.kp, kw_of(w), cur, has_next ? 1 : 0, e0n, kwn, stream);

@@ -44,6 +44,7 @@ class Bucket {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int4 *kvec = nullptr;
+    int kmax_comp = 0;  // largest |component| of the plane-wave integer vectors
     std::vector<DetSlot> dets;
     bool use_graph = false;
     bool timing = false;

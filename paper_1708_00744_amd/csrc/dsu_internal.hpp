@@ -177,10 +177,11 @@ hipError_t launch_walker_accept(WalkerDev *wd, int n, int np, int k, int kp, int
 hipError_t launch_row_to(const double *src, void *dst, int mode, int n, int np, hipStream_t s);
 
 // Batched window kernels.  ktile = padded delay of the launch (template tile
-// count, 16..256), kp = padded delay the buffers were allocated for (stride).
+// count, 16..256), kp = padded delay the buffers were allocated for (stride),
+// nmax = largest |component| of the plane-wave integer vectors.
 template <typename T>
 hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
-                              const int4 *kvec, double twopi_over_l, hipStream_t s);
+                              const int4 *kvec, double twopi_over_l, int nmax, hipStream_t s);
 template <typename T>
 hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int e0, int nsplit,
                            hipStream_t s);
@@ -197,7 +198,7 @@ hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int k
 //           window's BT rows into Vg[nxt]
 template <typename T>
 hipError_t launch_window_props(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
-                               const int4 *kvec, double twopi_over_l, int buf, int copy_vg, hipStream_t s);
+                               const int4 *kvec, double twopi_over_l, int buf, int copy_vg, int nmax, hipStream_t s);
 template <typename T>
 hipError_t launch_window_prime(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int buf, hipStream_t s);
 template <typename T>

@@ -74,12 +74,23 @@ __device__ __forceinline__ double pw_orbital(int4 kv, double twopi_l, double x, 
 // fills its column range of U (proposed orbital rows, zero past kw and n) and
 // Vg (the stale BT rows e0..e0+kw-1, zero past kw).  Block 0 of a determinant
 // also stores the proposals for the decision kernel.
+//
+// Orbitals from per-axis phase factors: with q = 2 pi / L,
+// exp(i q (nx x + ny y + nz z)) = Ex^nx Ey^ny Ez^nz and E^-n = conj(E^n), so a
+// group of proposals needs only cos/sin(q n r_axis) for 0 <= n <= nmax (one
+// sincos each), and every orbital is two complex products (cos = real part,
+// sin = imaginary part).  Used when nmax <= kPwTab; otherwise cos/sin per
+// orbital.
+constexpr int kPwTab = 24;
+constexpr int kPwGroup = 32;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__restrict__ descs, int n, int np,
                                                           int ktile, int e0, int kw, const int4 *__restrict__ kvec,
-                                                          double twopi_l, int buf, int copy_vg) {
+                                                          double twopi_l, int buf, int copy_vg, int nmax) {
 #pragma clang fp contract(off)
     __shared__ double s_r[DSU_KMAX_LDS][3];
+    __shared__ double s_c[kPwGroup][3][kPwTab + 1], s_s[kPwGroup][3][kPwTab + 1];
     const DetDesc<T> d = descs[blockIdx.x];
     const int tid = threadIdx.x;
     const long long sweep = d.st->sweep;
@@ -98,47 +109,92 @@ __global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__re
     __syncthreads();
     const int cols = np / gridDim.y;
     const int c_begin = blockIdx.y * cols;
-    for (int v = tid; v < ktile * cols; v += kThreads) {
-        const int a = v / cols, c = c_begin + v % cols;
-        T val = T(0), vgv = T(0);
-        if (a < kw) {
-            if (c < n) val = T(pw_orbital(kvec[c], twopi_l, s_r[a][0], s_r[a][1], s_r[a][2]));
-            vgv = d.bt[(size_t)(e0 + a) * np + c];
+    T *uo = buf ? d.u2 : d.u;
+    T *vo = buf ? d.vg2 : d.vg;
+    if (nmax > kPwTab) {
+        for (int v = tid; v < ktile * cols; v += kThreads) {
+            const int a = v / cols, c = c_begin + v % cols;
+            T val = T(0), vgv = T(0);
+            if (a < kw) {
+                if (c < n) val = T(pw_orbital(kvec[c], twopi_l, s_r[a][0], s_r[a][1], s_r[a][2]));
+                if (copy_vg) vgv = d.bt[(size_t)(e0 + a) * np + c];
+            }
+            uo[(size_t)a * np + c] = val;
+            if (copy_vg) vo[(size_t)a * np + c] = vgv;
         }
-        (buf ? d.u2 : d.u)[(size_t)a * np + c] = val;
-        if (copy_vg) (buf ? d.vg2 : d.vg)[(size_t)a * np + c] = vgv;
+        return;
+    }
+    for (int a0 = 0; a0 < ktile; a0 += kPwGroup) {
+        const int ga = min(kPwGroup, ktile - a0);
+        __syncthreads();
+        for (int v = tid; v < ga * 3 * (nmax + 1); v += kThreads) {
+            const int a = v / (3 * (nmax + 1)), r = v % (3 * (nmax + 1)), ax = r / (nmax + 1), m = r % (nmax + 1);
+            double sn = 0.0, cs = 1.0;
+            if (a0 + a < kw) sincos(twopi_l * ((double)m * s_r[a0 + a][ax]), &sn, &cs);
+            s_c[a][ax][m] = cs;
+            s_s[a][ax][m] = sn;
+        }
+        __syncthreads();
+        for (int v = tid; v < ga * cols; v += kThreads) {
+            const int a = v / cols, c = c_begin + v % cols, ag = a0 + a;
+            T val = T(0), vgv = T(0);
+            if (ag < kw) {
+                if (c < n) {
+                    const int4 kv = kvec[c];
+                    double o = 1.0;
+                    if (kv.w != 0) {
+                        const int ax_n[3] = {kv.x, kv.y, kv.z};
+                        double re = 1.0, im = 0.0;
+#pragma unroll
+                        for (int ax = 0; ax < 3; ++ax) {
+                            const int m = ax_n[ax] < 0 ? -ax_n[ax] : ax_n[ax];
+                            const double fc = s_c[a][ax][m];
+                            const double fs = ax_n[ax] < 0 ? -s_s[a][ax][m] : s_s[a][ax][m];
+                            const double t = re * fc - im * fs;
+                            im = re * fs + im * fc;
+                            re = t;
+                        }
+                        o = kv.w == 1 ? re : im;
+                    }
+                    val = T(o);
+                }
+                if (copy_vg) vgv = d.bt[(size_t)(e0 + ag) * np + c];
+            }
+            uo[(size_t)ag * np + c] = val;
+            if (copy_vg) vo[(size_t)ag * np + c] = vgv;
+        }
     }
 }
 
 template <typename T>
 hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
-                              const int4 *kvec, double twopi_over_l, hipStream_t s) {
+                              const int4 *kvec, double twopi_over_l, int nmax, hipStream_t s) {
     int nsplit = np / 256;
     if (nsplit < 1) nsplit = 1;
     while (np % nsplit) --nsplit;
     hipLaunchKernelGGL((k_window_rows<T>), dim3(ndesc, nsplit), dim3(kThreads), 0, s, d, n, np, ktile, e0, kw, kvec,
-                       twopi_over_l, 0, 1);
+                       twopi_over_l, 0, 1, nmax);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_window_props(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
-                               const int4 *kvec, double twopi_over_l, int buf, int copy_vg, hipStream_t s) {
+                               const int4 *kvec, double twopi_over_l, int buf, int copy_vg, int nmax, hipStream_t s) {
     int nsplit = np / 256;
     if (nsplit < 1) nsplit = 1;
     while (np % nsplit) --nsplit;
     hipLaunchKernelGGL((k_window_rows<T>), dim3(ndesc, nsplit), dim3(kThreads), 0, s, d, n, np, ktile, e0, kw, kvec,
-                       twopi_over_l, buf, copy_vg);
+                       twopi_over_l, buf, copy_vg, nmax);
     return hipGetLastError();
 }
 template hipError_t launch_window_props<float>(const DetDesc<float> *, int, int, int, int, int, int, const int4 *,
-                                               double, int, int, hipStream_t);
+                                               double, int, int, int, hipStream_t);
 template hipError_t launch_window_props<double>(const DetDesc<double> *, int, int, int, int, int, int, const int4 *,
-                                                double, int, int, hipStream_t);
+                                                double, int, int, int, hipStream_t);
 template hipError_t launch_window_rows<float>(const DetDesc<float> *, int, int, int, int, int, int, const int4 *,
-                                              double, hipStream_t);
+                                              double, int, hipStream_t);
 template hipError_t launch_window_rows<double>(const DetDesc<double> *, int, int, int, int, int, int, const int4 *,
-                                               double, hipStream_t);
+                                               double, int, hipStream_t);
 
 // ---------------------------------------------- window look-ahead products
 // gpart[s][b][a] = sum over the s-th column range of BT[e0+b, c] * U[a, c]
