@@ -38,7 +38,7 @@ BucketShape BucketShape::make(int n, int kmax, int prec) {
 }
 
 // Piece sizes in carve order.
-static constexpr int kPieces = 14;
+static constexpr int kPieces = 15;
 static void pieces(const BucketShape &s, size_t out[kPieces]) {
     const size_t e = elem_size(s.prec), np = s.np, kp = s.kp;
     out[0] = np * np * e;                           // bt
@@ -55,6 +55,7 @@ static void pieces(const BucketShape &s, size_t out[kPieces]) {
     out[11] = kp * np * e;                          // u2
     out[12] = kp * np * e;                          // vg2
     out[13] = np * kp * e;                          // y
+    out[14] = kp * 4 * 8;                           // prop2
 }
 
 size_t BucketShape::det_bytes() const {
@@ -88,6 +89,7 @@ DetSlot BucketShape::carve(char *base) const {
     d.u2 = ptr[11];
     d.vg2 = ptr[12];
     d.y = ptr[13];
+    d.prop2 = (double *)ptr[14];
     return d;
 }
 
@@ -97,6 +99,8 @@ int Bucket::init(const BucketShape &shape, int k_delay, double box_l, void *stre
     L = box_l;
     twopi_l = 2.0 * M_PI / box_l;
     CHK(make_stream(stream_or_null, &stream, &own_stream));
+    HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    for (hipEvent_t &e : ev_ring_) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     CHK(dalloc(&kvec, (size_t)sh.n));
     std::vector<int4> kv(sh.n);
     build_kvectors(sh.n, kv.data());
@@ -109,6 +113,7 @@ int Bucket::init(const BucketShape &shape, int k_delay, double box_l, void *stre
 
 void Bucket::release() {
     if (stream) (void)hipStreamSynchronize(stream);
+    if (side) (void)hipStreamSynchronize(side);
     drop_graph();
     for (void *p : {(void *)kvec, ddesc_, fdesc_, sub_ddesc_, (void *)sub_pos_, (void *)sub_bt_, (void *)drift_})
         dfree(p);
@@ -124,6 +129,12 @@ void Bucket::release() {
     drift_ = nullptr;
     cap_ = 0;
     gj_.release();
+    for (hipEvent_t &e : ev_ring_) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    if (side) (void)hipStreamDestroy(side);
+    side = nullptr;
     for (auto &e : ev_free_) (void)hipEventDestroy(e);
     for (auto &e : ev_used_) {
         (void)hipEventDestroy(e.second.first);
@@ -189,6 +200,7 @@ template <typename T> static DetDesc<T> to_desc(const DetSlot &s) {
     d.u2 = (T *)s.u2;
     d.vg2 = (T *)s.vg2;
     d.y = (T *)s.y;
+    d.prop2 = s.prop2;
     return d;
 }
 
@@ -230,7 +242,8 @@ void Bucket::drop_graph() {
     graph_force_ = -1;
 }
 
-template <typename F> int Bucket::timed(int phase, F fn) {
+template <typename F> int Bucket::timed(int phase, F fn, hipStream_t on) {
+    if (!on) on = stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timing) {
         for (hipEvent_t *e : {&e0, &e1}) {
@@ -241,11 +254,11 @@ template <typename F> int Bucket::timed(int phase, F fn) {
                 HIPCHK(hipEventCreate(e));
             }
         }
-        HIPCHK(hipEventRecord(e0, stream));
+        HIPCHK(hipEventRecord(e0, on));
     }
     HIPCHK(fn());
     if (timing) {
-        HIPCHK(hipEventRecord(e1, stream));
+        HIPCHK(hipEventRecord(e1, on));
         ev_used_.push_back({phase, {e0, e1}});
     }
     return DSU_OK;
@@ -254,6 +267,7 @@ template <typename F> int Bucket::timed(int phase, F fn) {
 int Bucket::harvest_events() {
     if (ev_used_.empty()) return DSU_OK;
     HIPCHK(hipStreamSynchronize(stream));
+    HIPCHK(hipStreamSynchronize(side));
     for (auto &e : ev_used_) {
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, e.second.first, e.second.second));
@@ -299,25 +313,32 @@ template <typename T> int Bucket::enqueue_sweep_stream_t(int force) {
         return launch_window_props<T>(dd, nd, sh.n, sh.np, kt, 0, kw_of(0), kvec, twopi_l, 0, 1, kmax_comp, stream);
     }));
     CHK(timed(PH_G, [&] { return launch_window_prime<T>(dd, nd, sh.np, kt, sh.kp, 0, stream); }));
-    CHK(timed(PH_DECIDE, [&] {
-        return launch_window_decide<T>(dd, nd, kt, sh.kp, 0, kw_of(0), 1, force, nwin == 1, stream, 1);
-    }));
+    int ring = 0;
     for (int w = 0; w < nwin; ++w) {
         const int cur = w & 1, nxt = cur ^ 1;
         const bool has_next = w + 1 < nwin;
-        const int e0n = (w + 1) * K, kwn = has_next ? kw_of(w + 1) : 0;
-        if (has_next)
+        const int e0 = w * K, e0n = (w + 1) * K, kwn = has_next ? kw_of(w + 1) : 0;
+        // The next window's proposals depend only on sweep-start positions of
+        // its own electrons: draw them on the side stream while this window is
+        // decided.  Their U/proposal buffers were last read by the previous
+        // flush, which the fork point follows.
+        hipEvent_t fork = ev_ring_[ring++ & 7], join = ev_ring_[ring++ & 7];
+        if (has_next) {
+            HIPCHK(hipEventRecord(fork, stream));
+            HIPCHK(hipStreamWaitEvent(side, fork, 0));
             CHK(timed(PH_ROWS, [&] {
                 return launch_window_props<T>(dd, nd, sh.n, sh.np, kt, e0n, kwn, kvec, twopi_l, nxt, 0, kmax_comp,
-                                              stream);
-            }));
+                                              side);
+            }, side));
+            HIPCHK(hipEventRecord(join, side));
+        }
+        CHK(timed(PH_DECIDE, [&] {
+            return launch_window_decide<T>(dd, nd, kt, sh.kp, e0, kw_of(w), 1, force, w + 1 == nwin, stream, 1, cur);
+        }));
+        if (has_next) HIPCHK(hipStreamWaitEvent(stream, join, 0));
         CHK(timed(PH_FLUSH, [&] {
             return launch_flush_stream<T>(dd, nd, sh.np, kt, sh.kp, kw_of(w), cur, has_next ? 1 : 0, e0n, kwn, stream);
         }));
-        if (has_next)
-            CHK(timed(PH_DECIDE, [&] {
-                return launch_window_decide<T>(dd, nd, kt, sh.kp, e0n, kwn, 1, force, w + 2 == nwin, stream, 1);
-            }));
     }
     return DSU_OK;
 }

@@ -15,7 +15,7 @@ namespace dsu {
 // Device storage of one determinant.
 struct DetSlot {
     void *bt = nullptr, *u = nullptr, *vg = nullptr, *gpart = nullptr, *u2 = nullptr, *vg2 = nullptr, *y = nullptr;
-    double *cfl = nullptr, *cwork = nullptr, *gwork = nullptr, *prop = nullptr, *pos = nullptr;
+    double *cfl = nullptr, *cwork = nullptr, *gwork = nullptr, *prop = nullptr, *pos = nullptr, *prop2 = nullptr;
     int *idx = nullptr;
     DetState *st = nullptr;
     double *trace_r = nullptr;
@@ -43,6 +43,7 @@ class Bucket {
     double L = 0.0, twopi_l = 0.0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t side = nullptr;  // proposals of the next window, beside the current window's decisions
     int4 *kvec = nullptr;
     int kmax_comp = 0;  // largest |component| of the plane-wave integer vectors
     std::vector<DetSlot> dets;
@@ -95,7 +96,8 @@ class Bucket {
     int enqueue_sweep(int force_accept);
     int build_graph(int force_accept);
     void drop_graph();
-    template <typename F> int timed(int phase, F fn);
+    hipEvent_t ev_ring_[8] = {};
+    template <typename F> int timed(int phase, F fn, hipStream_t on = nullptr);
     template <typename T> int upload_t();
     template <typename T> int enqueue_sweep_t(int force_accept);
     template <typename T> int enqueue_sweep_stream_t(int force_accept);

@@ -101,6 +101,8 @@ template <typename T> struct DetDesc {
     T *u2;           // kp x np
     T *vg2;          // kp x np
     T *y;            // np x kp
+    double *prop2;   // kp x 4: proposals of the odd windows (the next window's are drawn
+                     // while the current window is decided)
 };
 
 // ------------------------------------------------------- launchers (host)
@@ -187,7 +189,7 @@ hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int np, int ktile, in
                            hipStream_t s);
 template <typename T>
 hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int nsplit,
-                                int force_accept, int last_window, hipStream_t s, int g_from_y = 0);
+                                int force_accept, int last_window, hipStream_t s, int g_from_y = 0, int pbuf = 0);
 
 // Streaming path (one pass over BT per window):
 //   props : proposals and orbital rows of a window into U buffer `buf`

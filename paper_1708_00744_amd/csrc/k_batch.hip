@@ -103,7 +103,8 @@ __global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__re
         const double z = d.pos[3 * e + 2] + d.sigma * g[2];
         s_r[a][0] = x; s_r[a][1] = y; s_r[a][2] = z;
         if (blockIdx.y == 0) {
-            d.prop[4 * a + 0] = x; d.prop[4 * a + 1] = y; d.prop[4 * a + 2] = z; d.prop[4 * a + 3] = u;
+            double *pr = buf ? d.prop2 : d.prop;
+            pr[4 * a + 0] = x; pr[4 * a + 1] = y; pr[4 * a + 2] = z; pr[4 * a + 3] = u;
         }
     }
     __syncthreads();
@@ -262,7 +263,7 @@ template <typename T, int KP>
 __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const DetDesc<T> *__restrict__ descs,
                                                                           int kp, int e0, int kw, int nsplit,
                                                                           int force_accept, int last_window,
-                                                                          int g_from_y) {
+                                                                          int g_from_y, int pbuf) {
     typedef DecideCfg<KP> C;
     constexpr int LD = C::ld, NT = C::threads;
     __shared__ double s_g[C::lds_g];
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
         G[a * LD + b] = acc;
     }
     for (int a = tid; a < KP; a += NT) {
-        s_u[a] = a < kw ? d.prop[4 * a + 3] : 0.0;
+        s_u[a] = a < kw ? (pbuf ? d.prop2 : d.prop)[4 * a + 3] : 0.0;
         s_pos[a] = -1;
     }
     __syncthreads();
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
     for (int a = tid; a < KP; a += NT) d.idx[a] = a < kw ? e0 + a : -1;
     for (int v = tid; v < kw * 3; v += NT) {
         const int a = v / 3, c = v % 3;
-        if (s_ok[a]) d.pos[3 * (e0 + a) + c] = d.prop[4 * a + c];
+        if (s_ok[a]) d.pos[3 * (e0 + a) + c] = (pbuf ? d.prop2 : d.prop)[4 * a + c];
     }
     if (tid == 0) {
         DetState *st = d.st;
@@ -391,7 +392,7 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__restrict__ descs, int kp, int e0,
                                                           int kw, int nsplit, int force_accept, int last_window,
-                                                          int g_from_y) {
+                                                          int g_from_y, int pbuf) {
     constexpr int RW = KP / 4;
     __shared__ double s_row[2][64];
     __shared__ double s_u[KP], s_ratio[KP];
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
         g[r] = v;
     }
     for (int a = tid; a < KP; a += 256) {
-        s_u[a] = a < kw ? d.prop[4 * a + 3] : 0.0;
+        s_u[a] = a < kw ? (pbuf ? d.prop2 : d.prop)[4 * a + 3] : 0.0;
         s_ok[a] = 0;
     }
     // |prod R| kept as mantissa * 2^exponent; one log at the end
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
     for (int a = tid; a < KP; a += 256) d.idx[a] = a < kw ? e0 + a : -1;
     for (int v = tid; v < kw * 3; v += 256) {
         const int a = v / 3, c = v % 3;
-        if (s_ok[a]) d.pos[3 * (e0 + a) + c] = d.prop[4 * a + c];
+        if (s_ok[a]) d.pos[3 * (e0 + a) + c] = (pbuf ? d.prop2 : d.prop)[4 * a + c];
     }
     if (tid == 0) {
         DetState *st = d.st;
@@ -494,17 +495,17 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
 
 template <typename T>
 hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int nsplit,
-                                int force_accept, int last_window, hipStream_t s, int g_from_y) {
+                                int force_accept, int last_window, hipStream_t s, int g_from_y, int pbuf) {
 #define DSU_G(KPV)                                                                                                \
     if (ktile == KPV) {                                                                                           \
         hipLaunchKernelGGL((k_window_decide_gj<T, KPV>), dim3(ndesc), dim3(256), 0, s, d, kp, e0, kw, nsplit,     \
-                           force_accept, last_window, g_from_y);                                                  \
+                           force_accept, last_window, g_from_y, pbuf);                                            \
         return hipGetLastError();                                                                                 \
     }
 #define DSU_D(KPV)                                                                                                \
     if (ktile == KPV) {                                                                                           \
         hipLaunchKernelGGL((k_window_decide<T, KPV>), dim3(ndesc), dim3(DecideCfg<KPV>::threads), 0, s, d, kp,    \
-                           e0, kw, nsplit, force_accept, last_window, g_from_y);                                  \
+                           e0, kw, nsplit, force_accept, last_window, g_from_y, pbuf);                            \
         return hipGetLastError();                                                                                 \
     }
     DSU_G(16) DSU_G(32) DSU_G(64) DSU_D(128) DSU_D(256)
@@ -513,9 +514,9 @@ hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int k
     return hipErrorInvalidValue;
 }
 template hipError_t launch_window_decide<float>(const DetDesc<float> *, int, int, int, int, int, int, int, int,
-                                                hipStream_t, int);
+                                                hipStream_t, int, int);
 template hipError_t launch_window_decide<double>(const DetDesc<double> *, int, int, int, int, int, int, int, int,
-                                                 hipStream_t, int);
+                                                 hipStream_t, int, int);
 
 // ------------------------------------------------------- streaming path
 // y[i][a] = BT[i,:] . U[buf][a,:] for every row i (the look-ahead products of
