@@ -37,12 +37,12 @@ PEAK_HBM = 8000.0        # GB/s
 # counter reads for a plain 1 GiB device copy (fetch x 2.000, write x 1.000).
 # Valid only for the kernel sources it was taken on; null once they change.
 FLUSH_TRAFFIC = {
-    "kernel": "k_flush_stream<float,64>",
-    "bytes_per_launch": 4587698995.0,
+    "kernel": "k_flush_stream32<64>",
+    "bytes_per_launch": 4565547008.0,
     "sources_sha256": {
-        "k_batch.hip": "5a27fdb789e1c8cd8da6b4bca821413088045c89675d48f8490a323e5e30eaa3",
+        "k_batch.hip": "68aa2947d0c8913684e9b894044492cb497da82991aa397917c57d9307d5bbbe",
         "tiles.hpp": "922215d624556b60ccf0f15ae683635301cd30a16be6b554702694307bfa1413",
-        "dsu_internal.hpp": "34ca2e42b2241767dbc593b8ae865def4ab30181d7161cc98ca43a3d1d06579f",
+        "dsu_internal.hpp": "5df570fc9249c35c465dd8d59d444747613872db6a4b0b93c594aaee8876581b",
     },
 }
 
@@ -123,7 +123,8 @@ def headline(args, cache):
     else:
         roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = "k_flush_stream<float,%d>" % (16 if K <= 16 else 1 << math.ceil(math.log2(K)))
+    kp = 16 if K <= 16 else 1 << math.ceil(math.log2(K))
+    roof["kernel"] = ("k_flush_stream32<%d>" if kp in (32, 64) else "k_flush_stream<float,%d>") % kp
     roof["traffic"] = measured_traffic(roof["kernel"])
     roof["mfma_frac"] = flops / avg_s / 1e12 / PEAK_FP32_MFMA
     roof["avg_launch_ms"] = ms / cnt
