@@ -140,12 +140,14 @@ def test_force_accept_fp64():
     b.close()
 
 
-def test_graph_replay_equals_eager():
+@pytest.mark.parametrize("prec,n,K", [(dsu.FP32_MIXED, 128, 16), (dsu.FP32_MIXED, 192, 64), (dsu.FP64, 160, 32)])
+def test_graph_replay_equals_eager(prec, n, K):
+    """A captured sweep (main and side stream) replayed three times, with host
+    synchronisation between replays, gives bit-identical results to eager launches."""
     require_gpu()
-    n, K = 128, 16
     outs = []
     for graph in (False, True):
-        b, _ = make_batch(n, 2, 1, K, dsu.FP32_MIXED, 0.25, seed=11, graph=graph)
+        b, _ = make_batch(n, 2, 1, K, prec, 0.25, seed=11, graph=graph)
         b.set_trace(3)
         for _ in range(3):
             b.sweep(1)
