@@ -150,15 +150,53 @@ def k_curve(b, steps=1):
     return res
 
 
-def batched_at(n, walkers, cache, steps=2):
+def batched_at(n, walkers, cache, steps=2, precision=None, k_curve_ks=()):
+    """Batched form at size n: moves/s at the tuned K, and optionally at other K."""
     from paper_1708_00744_amd import dsu, tune
+    precision = dsu.FP32_MIXED if precision is None else precision
     sigma = sigma_or_default(n, 0.99, cache)
     K = int(cache["delay"].get(tune.delay_key(n, walkers, dsu.FP32_MIXED), {}).get("best", 64))
     pos = batch_positions(n, walkers)
-    with dsu.Batch(n, pos, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, K,
-                   precision=dsu.FP32_MIXED, box_l=BOX_L) as b:
+    kmax = max((K,) + tuple(k_curve_ks))
+    out = {"walkers": walkers, "K": K, "precision": "fp64" if precision == dsu.FP64 else "fp32_mixed"}
+    with dsu.Batch(n, pos, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, kmax,
+                   precision=precision, box_l=BOX_L) as b:
+        b.set_delay(K)
         dt = time_sweeps(b, steps, 1)
-    return {"walkers": walkers, "K": K, "moves_per_s": walkers * n * steps / dt}
+        out["moves_per_s"] = walkers * n * steps / dt
+        if k_curve_ks:
+            curve = {}
+            for k in k_curve_ks:
+                b.set_delay(k)
+                curve[str(k)] = walkers * n / time_sweeps(b, 1, 1)
+            out["k_curve_moves_per_s"] = curve
+    return out
+
+
+def ratio_products(b, K):
+    """The look-ahead ratio step as its own launch (the four-launch window
+    schedule): G[a][b] = phi_a . BT[e0+b] for every determinant reads the K
+    stale rows of BT and the K proposed orbital rows -- a memory-bound
+    product (K/(2s) flop/B).  Achieved HBM bandwidth of that launch from HIP
+    events on the batch stream, over one sweep."""
+    from paper_1708_00744_amd import dsu
+    b.set_delay(K)
+    b.set_flush_path(False)
+    b.sweep(1)
+    b.sync()
+    b.set_timing(True)
+    b.sweep(1)
+    b.sync()
+    cnt, ms = b.kernel_time(dsu.PHASE_G)
+    b.set_timing(False)
+    b.set_flush_path(True)
+    kp = 16 if K <= 16 else 1 << math.ceil(math.log2(K))
+    np_ = (b.n + 63) // 64 * 64
+    nbytes = b.walkers * 2.0 * kp * np_ * 4
+    avg = ms / cnt / 1e3
+    return {"kernel": "k_window_g<float,%d>" % kp, "launches": cnt, "avg_launch_us": avg * 1e6,
+            "bytes_per_launch": nbytes, "achieved_GBps": nbytes / avg / 1e9,
+            "frac_of_hbm_peak": nbytes / avg / 1e9 / PEAK_HBM}
 
 
 def fp64_single_walker(cache, n=1024, sweeps=1):
@@ -291,11 +329,15 @@ def main():
     if not args.quick:
         log("K curve")
         extras["k_curve_n4096_moves_per_s"] = k_curve(b)
+        log("ratio step as a separate launch")
+        extras["ratio_step_n4096"] = ratio_products(b, h["K"])
     b.close()
     if not args.quick:
-        log("batched N=1024 / 2048")
-        extras["fp32_batched_n1024"] = batched_at(1024, 256, cache)
-        extras["fp32_batched_n2048"] = batched_at(2048, 64, cache)
+        log("batched N=1024 / 2048, FP32 and FP64")
+        extras["fp32_batched_n1024"] = batched_at(1024, 256, cache, k_curve_ks=(16, 32, 128))
+        extras["fp32_batched_n2048"] = batched_at(2048, 64, cache, k_curve_ks=(16, 32, 128))
+        extras["fp64_batched_n1024"] = batched_at(1024, 256, cache, precision=dsu.FP64)
+        extras["fp64_batched_n2048"] = batched_at(2048, 64, cache, precision=dsu.FP64)
         log("FP64 single walker N=1024")
         extras["fp64_single_walker_n1024"] = fp64_single_walker(cache)
         log("serving")

@@ -19,7 +19,12 @@ namespace dsu {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static int choose_nsplit(int np) {
+// Column splits of the window look-ahead product: one 512-byte column range
+// per workgroup when np allows it (np is a multiple of 64 elements; 512 bytes
+// are 128 FP32 or 64 FP64 elements), else ranges of a multiple of 64 elements.
+static int choose_nsplit(int np, int prec) {
+    const int w = prec == DSU_FP64 ? 64 : 128;
+    if (np % w == 0) return np / w;
     int s = np / 512;
     if (s < 1) s = 1;
     while (s > 1 && (np % s != 0 || (np / s) % 64 != 0)) --s;
@@ -33,7 +38,7 @@ BucketShape BucketShape::make(int n, int kmax, int prec) {
     s.kmax = kmax;
     s.kp = kpad(kmax);
     s.prec = prec;
-    s.nsplit = choose_nsplit(s.np);
+    s.nsplit = choose_nsplit(s.np, prec);
     return s;
 }
 

@@ -230,9 +230,77 @@ __global__ __launch_bounds__(kThreads) void k_window_g(const DetDesc<T> *__restr
         }
 }
 
+// The same for K <= 64, one launch-wide burst: each workgroup takes one
+// 512-byte column range of the window's 64 stale rows and of the K orbital
+// rows and issues all of its loads at once (the product is small, so the
+// launch is bound by how many bytes are in flight).  Lane group g = lane/16
+// contracts over its own contiguous quarter of the range.
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_window_g_wide(const DetDesc<T> *__restrict__ descs, int np, int kp,
+                                                            int e0, int nsplit) {
+    constexpr int CWB = 512 / (int)sizeof(T), VEC = 16 / (int)sizeof(T), LDU = CWB + VEC, Q = CWB / 4;
+    constexpr int NU = KP * (CWB / VEC) / kThreads;
+    static_assert(NU >= 1 && NU * kThreads == KP * (CWB / VEC), "staging split");
+    typedef typename Vec16<T>::type vec_t;
+    __shared__ __attribute__((aligned(16))) T lds[KP * LDU];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int d = b / nsplit, sp = b % nsplit;
+    const DetDesc<T> dd = descs[d];
+    const int c_begin = sp * CWB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int arow = 16 * wave + (lane & 15);
+    const bool avalid = e0 + arow < np && arow < KP;
+    DSU_GLOBAL const T *ap = gmem<const T>(dd.bt) + (size_t)(avalid ? e0 + arow : 0) * np + c_begin + Q * (lane >> 4);
+    DSU_GLOBAL const T *u = gmem<const T>(dd.u);
+    vec_t a[Q / VEC], st[NU];
+#pragma unroll
+    for (int h = 0; h < Q / VEC; ++h) a[h] = avalid ? *(DSU_GLOBAL const vec_t *)(ap + h * VEC) : vec_t{};
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+        const int v = tid + q * kThreads, r = v / (CWB / VEC), cc = (v % (CWB / VEC)) * VEC;
+        st[q] = *(DSU_GLOBAL const vec_t *)(u + (size_t)r * np + c_begin + cc);
+    }
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+        const int v = tid + q * kThreads, r = v / (CWB / VEC), cc = (v % (CWB / VEC)) * VEC;
+        *reinterpret_cast<vec_t *>(lds + r * LDU + cc) = st[q];
+    }
+    __syncthreads();
+    typename Mma<T>::acc_t acc[KP / 16];
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t) acc[t] = typename Mma<T>::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int h = 0; h < Q / VEC; ++h)
+#pragma unroll
+        for (int t = 0; t < KP / 16; ++t) {
+            const vec_t bv = *reinterpret_cast<const vec_t *>(lds + (16 * t + (lane & 15)) * LDU + Q * (lane >> 4) +
+                                                              h * VEC);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[t] = Mma<T>::mma(a[h][e], bv[e], acc[t]);
+        }
+    T *out = dd.gpart + (size_t)sp * kp * kp;
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int br = 16 * wave + Mma<T>::row0(lane) + i * Mma<T>::row_step;
+            if (br < KP) out[(size_t)br * kp + 16 * t + (lane & 15)] = acc[t][i];
+        }
+}
+
 template <typename T>
 hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int e0, int nsplit,
                            hipStream_t s) {
+    if (ktile <= 64 && np == nsplit * (512 / (int)sizeof(T))) {
+        const dim3 grid(ndesc * nsplit);
+        if (ktile == 16)
+            hipLaunchKernelGGL((k_window_g_wide<T, 16>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit);
+        else if (ktile == 32)
+            hipLaunchKernelGGL((k_window_g_wide<T, 32>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit);
+        else
+            hipLaunchKernelGGL((k_window_g_wide<T, 64>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit);
+        return hipGetLastError();
+    }
     const int nrb = ktile > 64 ? ktile / 64 : 1;
     const dim3 grid(ndesc * nsplit * nrb);
 #define DSU_G(KPV)                                                                                          \

@@ -106,3 +106,29 @@ def test_continuous_batching_overlaps_arrivals():
     # the first request was still running when the later ones were admitted
     assert min(r["admit_s"] for r in results[1:]) < results[0]["finish_s"]
     assert np.all(np.isfinite([r["logdet"][0] for r in results]))
+
+
+def test_singular_walker_is_reported_not_fatal():
+    """A walker whose Slater matrix is singular (two electrons at one point)
+    is refused by dsu_server_add and ends with DSU_ESINGULAR in a run, while
+    the other requests of the run complete unchanged."""
+    require_gpu()
+    K, n, sweeps = 16, 128, 2
+    bad = positions(5, 1, n, 1).copy()
+    bad[0, 7] = bad[0, 3]
+    with dsu.Server(K, precision=dsu.FP32_MIXED, box_l=L, budget_bytes=1 << 30) as s:
+        with pytest.raises(dsu.DsuError) as ex:
+            s.add(1, n, 1, 5, 0.1, sweeps, bad)
+        assert ex.value.code == dsu.ESINGULAR
+        assert s.usage() == (0, 0)
+    good = {"request_id": 2, "n": n, "spins": 1, "seed": 5, "sigma": 0.1, "sweeps": sweeps, "arrival_s": 0.0,
+            "positions": positions(5, 2, n, 1)}
+    reqs = [dict(good), {"request_id": 1, "n": n, "spins": 1, "seed": 5, "sigma": 0.1, "sweeps": sweeps,
+                         "arrival_s": 0.0, "positions": bad}]
+    with dsu.Server(K, precision=dsu.FP32_MIXED, box_l=L, budget_bytes=1 << 30) as s:
+        results, lat = s.run(reqs)
+        assert s.usage() == (0, 0)
+    assert results[0]["status"] == dsu.OK and results[0]["sweeps_done"] == sweeps
+    assert results[1]["status"] == dsu.ESINGULAR
+    alone = run_alone(dsu.FP32_MIXED, K, good, sweeps)
+    assert results[0]["logdet"] == alone["logdet"] and results[0]["accepted"] == alone["accepted"]
