@@ -40,7 +40,7 @@ FLUSH_TRAFFIC = {
     "kernel": "k_flush_stream32<64>",
     "bytes_per_launch": 4565547008.0,
     "sources_sha256": {
-        "k_batch.hip": "68aa2947d0c8913684e9b894044492cb497da82991aa397917c57d9307d5bbbe",
+        "k_stream.hip": "0",
         "tiles.hpp": "922215d624556b60ccf0f15ae683635301cd30a16be6b554702694307bfa1413",
         "dsu_internal.hpp": "5df570fc9249c35c465dd8d59d444747613872db6a4b0b93c594aaee8876581b",
     },
