@@ -448,39 +448,41 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
     }
 }
 
-// The same decisions for windows of up to 64 slots as an in-place
+// The same decisions for windows of up to 128 slots as an in-place
 // Gauss-Jordan sweep over G in slot order, pivoting only on accepted slots:
 // before slot a is decided, G[a][a] has had every earlier accepted slot
 // eliminated, so it is the Schur complement r0 - p^T C^{-1} q of the
 // look-ahead; after the window, G restricted to the accepted slots is C^{-1}.
-// Four waves; wave w holds rows w*KP/4 .. of G, lane y column y, in registers
-// (the loop over slots is unrolled, so every register index is fixed).  A
-// step is one LDS exchange of the pivot row and one barrier; the pivot
-// column comes from lane j of each wave.
+// Four waves; wave w holds rows w*KP/4 .. of G, lane y columns y (and y + 64
+// at K = 128), in registers (the loop over slots is unrolled, so every
+// register index is fixed).  A step is one LDS exchange of the pivot row and
+// one barrier; the pivot column comes from one lane of each wave.
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__restrict__ descs, int kp, int e0,
                                                           int kw, int nsplit, int force_accept, int last_window,
                                                           int g_from_y, int pbuf) {
-    constexpr int RW = KP / 4;
-    __shared__ double s_row[2][64];
+    constexpr int RW = KP / 4, CPL = KP > 64 ? KP / 64 : 1, NC = 64 * CPL;
+    __shared__ double s_row[2][NC];
     __shared__ double s_u[KP], s_ratio[KP];
     __shared__ int s_ok[KP];
     const DetDesc<T> d = descs[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double g[RW];
+    double g[RW][CPL];
 #pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const int a = wave * RW + r, b = lane;
-        double v = a == b ? 1.0 : 0.0;
-        if (a < kw && b < kw) {
-            if (g_from_y) v = (double)d.y[(size_t)(e0 + b) * kp + a];
-            else {
-                v = 0.0;
-                for (int q = 0; q < nsplit; ++q) v += (double)d.gpart[((size_t)q * kp + b) * kp + a];
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int h = 0; h < CPL; ++h) {
+            const int a = wave * RW + r, b = lane + 64 * h;
+            double v = a == b ? 1.0 : 0.0;
+            if (a < kw && b < kw) {
+                if (g_from_y) v = (double)d.y[(size_t)(e0 + b) * kp + a];
+                else {
+                    v = 0.0;
+                    for (int q = 0; q < nsplit; ++q) v += (double)d.gpart[((size_t)q * kp + b) * kp + a];
+                }
             }
+            g[r][h] = v;
         }
-        g[r] = v;
-    }
     for (int a = tid; a < KP; a += 256) {
         s_u[a] = a < kw ? (pbuf ? d.prop2 : d.prop)[4 * a + 3] : 0.0;
         s_ok[a] = 0;
@@ -490,12 +492,14 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
     double pman = 1.0;
 #pragma unroll 1
     for (int jb = 0; jb < 4; ++jb) {
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int jj = 0; jj < RW; ++jj) {
             const int j = jb * RW + jj;
             if (j < kw) {
                 double *row = s_row[j & 1];
-                if (wave == jb) row[lane] = g[jj];
+                if (wave == jb)
+#pragma unroll
+                    for (int h = 0; h < CPL; ++h) row[lane + 64 * h] = g[jj][h];
                 __syncthreads();
                 const double r = row[j];
                 const bool finite_nz = fabs(r) > RatioFloor<T>::value && fabs(r) <= 1.7976931348623157e308;
@@ -507,16 +511,24 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
                 }
                 if (ok) {
                     const double dinv = 1.0 / r;
-                    const double rj = lane == j ? dinv : row[lane] * dinv;
+                    const int jl = j & 63, jh = j >> 6;  // lane and column half holding column j
+                    double rj[CPL];
+#pragma unroll
+                    for (int h = 0; h < CPL; ++h) rj[h] = lane + 64 * h == j ? dinv : row[lane + 64 * h] * dinv;
 #pragma unroll
                     for (int q = 0; q < RW; ++q) {
-                        // column j of this wave's rows, from lane j (a uniform lane index)
-                        const double gq = g[q];
-                        const int lo = __builtin_amdgcn_readlane(__double2loint(gq), j);
-                        const int hi = __builtin_amdgcn_readlane(__double2hiint(gq), j);
+                        double gq = g[q][0];
+#pragma unroll
+                        for (int h = 1; h < CPL; ++h) gq = jh == h ? g[q][h] : gq;
+                        const int lo = __builtin_amdgcn_readlane(__double2loint(gq), jl);
+                        const int hi = __builtin_amdgcn_readlane(__double2hiint(gq), jl);
                         const double f = __hiloint2double(hi, lo);
-                        if (wave * RW + q == j) g[q] = rj;
-                        else g[q] = lane == j ? -f * dinv : gq - f * rj;
+                        const bool pivot_row = wave * RW + q == j;
+#pragma unroll
+                        for (int h = 0; h < CPL; ++h) {
+                            if (pivot_row) g[q][h] = rj[h];
+                            else g[q][h] = lane + 64 * h == j ? -f * dinv : g[q][h] - f * rj[h];
+                        }
                     }
                     int e;
                     pman *= frexp(fabs(r), &e);
@@ -533,10 +545,12 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
     __syncthreads();
     // zero-embedded C^{-1} for the flush, electrons, positions, state, trace
 #pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const int a = wave * RW + r;
-        if (lane < KP) d.cfl[(size_t)a * kp + lane] = (s_ok[a] && s_ok[lane]) ? g[r] : 0.0;
-    }
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int h = 0; h < CPL; ++h) {
+            const int a = wave * RW + r, b = lane + 64 * h;
+            if (b < KP) d.cfl[(size_t)a * kp + b] = (s_ok[a] && s_ok[b]) ? g[r][h] : 0.0;
+        }
     for (int a = tid; a < KP; a += 256) d.idx[a] = a < kw ? e0 + a : -1;
     for (int v = tid; v < kw * 3; v += 256) {
         const int a = v / 3, c = v % 3;
@@ -576,7 +590,7 @@ hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int k
                            e0, kw, nsplit, force_accept, last_window, g_from_y, pbuf);                            \
         return hipGetLastError();                                                                                 \
     }
-    DSU_G(16) DSU_G(32) DSU_G(64) DSU_D(128) DSU_D(256)
+    DSU_G(16) DSU_G(32) DSU_G(64) DSU_G(128) DSU_D(256)
 #undef DSU_D
 #undef DSU_G
     return hipErrorInvalidValue;

@@ -209,12 +209,12 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kRowBlock32 = 128;
 
 template <int KP> struct Stream32Cfg {
-    static constexpr int CW = 64, VEC = 4, KH = KP / 2;
+    static constexpr int CW = KP <= 64 ? 64 : 32, VEC = 4, KH = KP / 2;
     static constexpr int LDVT = KP + 4, LDU = CW + 4, LDY = KP + 4;
     static constexpr int NV = KP * (CW / VEC) / kThreads;
     static constexpr int buf = CW * LDVT + KP * LDU;
     static constexpr int chunk = 2 * buf;
-    static constexpr int wpart = kRowBlock32 * LDY + WCfg<float, KP>::elems;
+    static constexpr int wpart = 64 * LDY + WCfg<float, KP>::elems;  // one 64-row half of W at a time
     static constexpr int elems = chunk > wpart ? chunk : wpart;
     static_assert(NV >= 1 && NV * kThreads == KP * (CW / VEC), "staging split");
 };
@@ -238,34 +238,33 @@ __global__ __launch_bounds__(kThreads, 2) void k_flush_stream32(const DetDesc<fl
     const int rows = np - r0 < kRowBlock32 ? np - r0 : kRowBlock32;  // 64 or 128
     const bool wvalid = 32 * wave < rows;                              // wave-uniform
 
-    // W = (y - E) C^{-T} for this block's rows, in two 64-row halves
-    for (int v = tid; v < kRowBlock32 * KP; v += kThreads) {
-        const int i = v / KP, j = v % KP;
-        lds[i * LDY + j] = i < rows ? y[(size_t)(r0 + i) * kp + j] : 0.0f;
-    }
-    __syncthreads();
-    for (int j = tid; j < kslots; j += kThreads) {
-        const int e = dd.idx[j];
-        if (e >= r0 && e < r0 + rows) lds[(e - r0) * LDY + j] -= 1.0f;
-    }
-    __syncthreads();
+    // W = (y - E) C^{-T} for this block's rows, one 64-row half at a time;
+    // waves 0-1 keep the first half's rows as B operands, waves 2-3 the second's
     float wa[KH];
-    {
-        f32x4 w0[KP / 16], w1[KP / 16];
-        w_from_y<float, KP>(lds, LDY, dd.cfl, kp, kslots, lds + kRowBlock32 * LDY, w0);
-        w_from_y<float, KP>(lds + 64 * LDY, LDY, dd.cfl, kp, kslots, lds + kRowBlock32 * LDY, w1);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int h0 = 64 * half;
+        for (int v = tid; v < 64 * KP; v += kThreads) {
+            const int i = v / KP, j = v % KP;
+            lds[i * LDY + j] = h0 + i < rows ? y[(size_t)(r0 + h0 + i) * kp + j] : 0.0f;
+        }
+        __syncthreads();
+        for (int j = tid; j < kslots; j += kThreads) {
+            const int e = dd.idx[j] - r0 - h0;
+            if (e >= 0 && e < 64 && h0 + e < rows) lds[e * LDY + j] -= 1.0f;
+        }
+        __syncthreads();
+        f32x4 w[KP / 16];
+        w_from_y<float, KP>(lds, LDY, dd.cfl, kp, kslots, lds + 64 * LDY, w);
 #pragma unroll
         for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int rr = 16 * wave + 4 * (lane >> 4) + i, cc = 16 * t + (lane & 15);
-                lds[rr * LDY + cc] = w0[t][i];
-                lds[(64 + rr) * LDY + cc] = w1[t][i];
-            }
+            for (int i = 0; i < 4; ++i) lds[(16 * wave + 4 * (lane >> 4) + i) * LDY + 16 * t + (lane & 15)] = w[t][i];
         __syncthreads();
         // B operand of the V^T W^T product; contraction over slot (lane/32)*KH + s
+        if ((wave >> 1) == half)
 #pragma unroll
-        for (int s = 0; s < KH; ++s) wa[s] = -lds[(32 * wave + (lane & 31)) * LDY + (lane >> 5) * KH + s];
+            for (int s = 0; s < KH; ++s) wa[s] = -lds[(32 * (wave & 1) + (lane & 31)) * LDY + (lane >> 5) * KH + s];
         __syncthreads();
     }
 
@@ -355,23 +354,31 @@ __global__ __launch_bounds__(kThreads, 2) void k_flush_stream32(const DetDesc<fl
                 }
         if (has_next) {
             const float *up = Us + (lane & 31) * LDU + 4 * (lane >> 5);
-            vec_t ub[2][JT];
+            // read one group ahead, except at K = 128 where a group is already
+            // 16 products long and the registers are needed elsewhere
+            constexpr int UB = JT >= 4 ? 1 : 2;
+            vec_t ub[UB][JT];
 #pragma unroll
             for (int jt = 0; jt < JT; ++jt) ub[0][jt] = *reinterpret_cast<const vec_t *>(up + 32 * jt * LDU);
 #pragma unroll
             for (int q = 0; q < NT * 4; ++q) {  // q = 4t + gq
-                if (q + 1 < NT * 4)
+                if (UB == 2 && q + 1 < NT * 4) {
 #pragma unroll
                     for (int jt = 0; jt < JT; ++jt)
-                        ub[(q + 1) & 1][jt] = *reinterpret_cast<const vec_t *>(
+                        ub[(q + 1) % UB][jt] = *reinterpret_cast<const vec_t *>(
                             up + 32 * jt * LDU + 32 * ((q + 1) / 4) + 8 * ((q + 1) % 4));
-                __builtin_amdgcn_sched_barrier(0);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if (UB == 1 && q > 0)
+#pragma unroll
+                    for (int jt = 0; jt < JT; ++jt)
+                        ub[0][jt] = *reinterpret_cast<const vec_t *>(up + 32 * jt * LDU + 32 * (q / 4) + 8 * (q % 4));
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
 #pragma unroll
                     for (int jt = 0; jt < JT; ++jt)
-                        accy[jt] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[q / 4][4 * (q % 4) + e], ub[q & 1][jt][e],
-                                                                        accy[jt], 0, 0, 0);
+                        accy[jt] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[q / 4][4 * (q % 4) + e],
+                                                                        ub[q % UB][jt][e], accy[jt], 0, 0, 0);
             }
         }
         if (c1 < np) {
@@ -398,14 +405,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_flush_stream32(const DetDesc<fl
 template <typename T>
 hipError_t launch_flush_stream(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int kslots, int cur,
                                int has_next, int e0n, int kwn, hipStream_t s) {
-    if (sizeof(T) == 4 && (ktile == 32 || ktile == 64)) {
+    if (sizeof(T) == 4 && (ktile == 32 || ktile == 64 || ktile == 128)) {
         const int nblk = (np + kRowBlock32 - 1) / kRowBlock32;
         const DetDesc<float> *df = (const DetDesc<float> *)d;
         if (ktile == 32)
             hipLaunchKernelGGL((k_flush_stream32<32>), dim3(ndesc * nblk), dim3(kThreads), 0, s, df, np, nblk, kp,
                                kslots, cur, has_next, e0n, kwn);
-        else
+        else if (ktile == 64)
             hipLaunchKernelGGL((k_flush_stream32<64>), dim3(ndesc * nblk), dim3(kThreads), 0, s, df, np, nblk, kp,
+                               kslots, cur, has_next, e0n, kwn);
+        else
+            hipLaunchKernelGGL((k_flush_stream32<128>), dim3(ndesc * nblk), dim3(kThreads), 0, s, df, np, nblk, kp,
                                kslots, cur, has_next, e0n, kwn);
         return hipGetLastError();
     }
