@@ -37,10 +37,10 @@ PEAK_HBM = 8000.0        # GB/s
 # counter reads for a plain 1 GiB device copy (fetch x 2.000, write x 1.000).
 # Valid only for the kernel sources it was taken on; null once they change.
 FLUSH_TRAFFIC = {
-    "kernel": "k_flush_stream32<64>",
-    "bytes_per_launch": 4565547008.0,
+    "kernel": "k_flush_stream32<128>",
+    "bytes_per_launch": 4799995904.0,
     "sources_sha256": {
-        "k_stream.hip": "0",
+        "k_stream.hip": "a74063f2831479e4202cc30840d36f384b0306dc2e69526e33f3464b608eb417",
         "tiles.hpp": "922215d624556b60ccf0f15ae683635301cd30a16be6b554702694307bfa1413",
         "dsu_internal.hpp": "5df570fc9249c35c465dd8d59d444747613872db6a4b0b93c594aaee8876581b",
     },
@@ -124,7 +124,7 @@ def headline(args, cache):
         roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     kp = 16 if K <= 16 else 1 << math.ceil(math.log2(K))
-    roof["kernel"] = ("k_flush_stream32<%d>" if kp in (32, 64) else "k_flush_stream<float,%d>") % kp
+    roof["kernel"] = ("k_flush_stream32<%d>" if kp in (32, 64, 128) else "k_flush_stream<float,%d>") % kp
     roof["traffic"] = measured_traffic(roof["kernel"])
     roof["mfma_frac"] = flops / avg_s / 1e12 / PEAK_FP32_MFMA
     roof["avg_launch_ms"] = ms / cnt
