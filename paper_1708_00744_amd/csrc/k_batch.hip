@@ -237,18 +237,18 @@ __global__ __launch_bounds__(kThreads) void k_window_g(const DetDesc<T> *__restr
 // contracts over its own contiguous quarter of the range.
 template <typename T, int KP>
 __global__ __launch_bounds__(kThreads) void k_window_g_wide(const DetDesc<T> *__restrict__ descs, int np, int kp,
-                                                            int e0, int nsplit) {
+                                                            int e0, int nsplit, int nrb) {
     constexpr int CWB = 512 / (int)sizeof(T), VEC = 16 / (int)sizeof(T), LDU = CWB + VEC, Q = CWB / 4;
     constexpr int NU = KP * (CWB / VEC) / kThreads;
     static_assert(NU >= 1 && NU * kThreads == KP * (CWB / VEC), "staging split");
     typedef typename Vec16<T>::type vec_t;
     __shared__ __attribute__((aligned(16))) T lds[KP * LDU];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int d = b / nsplit, sp = b % nsplit;
+    const int d = b / (nsplit * nrb), sp = (b / nrb) % nsplit, rb = b % nrb;
     const DetDesc<T> dd = descs[d];
     const int c_begin = sp * CWB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int arow = 16 * wave + (lane & 15);
+    const int arow = 64 * rb + 16 * wave + (lane & 15);  // stale row of the window (G row b)
     const bool avalid = e0 + arow < np && arow < KP;
     DSU_GLOBAL const T *ap = gmem<const T>(dd.bt) + (size_t)(avalid ? e0 + arow : 0) * np + c_begin + Q * (lane >> 4);
     DSU_GLOBAL const T *u = gmem<const T>(dd.u);
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_window_g_wide(const DetDesc<T> *__
     for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int br = 16 * wave + Mma<T>::row0(lane) + i * Mma<T>::row_step;
+            const int br = 64 * rb + 16 * wave + Mma<T>::row0(lane) + i * Mma<T>::row_step;
             if (br < KP) out[(size_t)br * kp + 16 * t + (lane & 15)] = acc[t][i];
         }
 }
@@ -291,14 +291,19 @@ __global__ __launch_bounds__(kThreads) void k_window_g_wide(const DetDesc<T> *__
 template <typename T>
 hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int e0, int nsplit,
                            hipStream_t s) {
+    // (at K = 128 the 64-row blocks would each stage all 128 orbital rows and
+    // halve the occupancy; the chunked kernel below is faster there)
     if (ktile <= 64 && np == nsplit * (512 / (int)sizeof(T))) {
-        const dim3 grid(ndesc * nsplit);
+        const int nrb = ktile > 64 ? ktile / 64 : 1;
+        const dim3 grid(ndesc * nsplit * nrb);
         if (ktile == 16)
-            hipLaunchKernelGGL((k_window_g_wide<T, 16>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit);
+            hipLaunchKernelGGL((k_window_g_wide<T, 16>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);
         else if (ktile == 32)
-            hipLaunchKernelGGL((k_window_g_wide<T, 32>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit);
+            hipLaunchKernelGGL((k_window_g_wide<T, 32>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);
+        else if (ktile == 64)
+            hipLaunchKernelGGL((k_window_g_wide<T, 64>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);
         else
-            hipLaunchKernelGGL((k_window_g_wide<T, 64>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit);
+            hipLaunchKernelGGL((k_window_g_wide<T, 128>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);
         return hipGetLastError();
     }
     const int nrb = ktile > 64 ? ktile / 64 : 1;

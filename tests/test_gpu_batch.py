@@ -295,7 +295,7 @@ def test_c4_shape_sampled():
 
 
 @pytest.mark.parametrize("prec,n,K", [(dsu.FP64, 100, 16), (dsu.FP64, 200, 64), (dsu.FP32_MIXED, 256, 64),
-                                      (dsu.FP32_MIXED, 192, 128)])
+                                      (dsu.FP32_MIXED, 192, 128), (dsu.FP32_MIXED, 256, 128), (dsu.FP64, 256, 128)])
 def test_two_window_schedules_agree(prec, n, K):
     """The one-pass streaming flush and the four-launch window schedule compute
     the same ratios and decisions (to rounding)."""
