@@ -235,15 +235,16 @@ def test_bad_arguments():
     assert ex.value.code == dsu.ESINGULAR
 
 
-def test_c4_shape_sampled():
-    """N = 4096, FP32, K = 64, sigma = 0.0015 (acceptance 0.99): the bench's
-    launch configuration on two walkers.  Properties checked at full size:
+@pytest.mark.parametrize("K", [128, 64])
+def test_c4_shape_sampled(K):
+    """N = 4096, FP32, K = 128 (and 64), sigma = 0.0015 (acceptance 0.99): the
+    bench's launch configuration on two walkers.  Properties checked at full size:
     after a sweep the running log-determinant against a direct (LAPACK)
     calculation and the inverse residual on sampled rows; on walker 0 the
     first window's ratios and decisions against the oracle's Sherman-Morrison
     steps."""
     require_gpu()
-    n, K, walkers, sigma = 4096, 64, 2, 0.0015
+    n, walkers, sigma = 4096, 2, 0.0015
     b, pos = make_batch(n, walkers, 1, K, dsu.FP32_MIXED, sigma, seed=1000)
     b.set_trace(1)
     b.sweep(1)
