@@ -178,6 +178,27 @@ void orc_pw_row(int n, const int *kv, double L, const double r[3], double *row)
     }
 }
 
+/* Gradient rows of one Slater-matrix row with respect to the electron
+ * position: drow[a*n + j] = d phi_j(r) / d r_a (a = x, y, z).  With
+ * g = 2 pi / L and phase ph = g (n . r):  d cos(ph) = -g n_a sin(ph),
+ * d sin(ph) = g n_a cos(ph), the constant orbital has zero gradient. */
+void orc_pw_row_grad(int n, const int *kv, double L, const double r[3], double *drow)
+{
+    double twopi_l = 2.0 * ORC_PI / L;
+    for (int j = 0; j < n; ++j) {
+        int kind = kv[4 * j + 3];
+        double t = ((double)kv[4 * j + 0] * r[0] + (double)kv[4 * j + 1] * r[1]) + (double)kv[4 * j + 2] * r[2];
+        double ph = twopi_l * t;
+        for (int a = 0; a < 3; ++a) {
+            double ga = twopi_l * (double)kv[4 * j + a];
+            double d = 0.0;
+            if (kind == 1) d = -ga * sin(ph);
+            else if (kind == 2) d = ga * cos(ph);
+            drow[(size_t)a * n + j] = d;
+        }
+    }
+}
+
 /* Slater matrix A (n x n, row-major, row i = electron i). */
 void orc_pw_matrix(int n, const int *kv, double L, const double *pos, double *a)
 {
@@ -285,6 +306,22 @@ double orc_sm_ratio(int n, const double *ainv, int e, const double *phi)
     double r = 0.0;
     for (int j = 0; j < n; ++j) r += phi[j] * ainv[(size_t)j * n + e];
     return r;
+}
+
+/* Gradient of the eq. (1) ratio with respect to the new position of
+ * electron e.  The determinant is linear in row e, so differentiating the
+ * new row phi(r') and applying eq. (1) to each derivative row gives
+ *   d R / d r'_a = (d phi / d r'_a) . Ainv[:,e],   a = x, y, z.
+ * Called with the electron's present row and its gradient rows this is the
+ * drift grad_e ln|det A| (R = 1 there).  Returns R, writes grad[3]. */
+double orc_sm_ratio_grad(int n, const double *ainv, int e, const double *phi, const double *dphi, double *grad)
+{
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += dphi[(size_t)a * n + j] * ainv[(size_t)j * n + e];
+        grad[a] = s;
+    }
+    return orc_sm_ratio(n, ainv, e, phi);
 }
 
 /* Eq. (2): rank-1 Sherman-Morrison update of Ainv after row e -> phi with

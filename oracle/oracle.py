@@ -44,6 +44,8 @@ def _declare(L):
     L.orc_pw_kvectors.restype = C.c_int
     L.orc_pw_row.argtypes = [C.c_int, _ip, C.c_double, _dp, _dp]
     L.orc_pw_row.restype = None
+    L.orc_pw_row_grad.argtypes = [C.c_int, _ip, C.c_double, _dp, _dp]
+    L.orc_pw_row_grad.restype = None
     L.orc_pw_matrix.argtypes = [C.c_int, _ip, C.c_double, _dp, _dp]
     L.orc_pw_matrix.restype = None
     L.orc_lu.argtypes = [C.c_int, _dp, _ip, C.POINTER(C.c_double), C.POINTER(C.c_int)]
@@ -56,6 +58,8 @@ def _declare(L):
     L.orc_residual.restype = C.c_double
     L.orc_sm_ratio.argtypes = [C.c_int, _dp, C.c_int, _dp]
     L.orc_sm_ratio.restype = C.c_double
+    L.orc_sm_ratio_grad.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp, _dp]
+    L.orc_sm_ratio_grad.restype = C.c_double
     L.orc_sm_accept.argtypes = [C.c_int, _dp, C.c_void_p, C.c_int, _dp, C.c_double, _dp]
     L.orc_sm_accept.restype = None
     vp = C.c_void_p
@@ -110,6 +114,14 @@ def pw_row(kv, L, r):
     return row
 
 
+def pw_row_grad(kv, L, r):
+    """(3, n): d phi_j / d r_a of one plane-wave row."""
+    n = kv.shape[0]
+    d = np.zeros((3, n))
+    lib().orc_pw_row_grad(n, np.ascontiguousarray(kv, np.int32), float(L), np.ascontiguousarray(r, np.float64), d)
+    return d
+
+
 def pw_matrix(kv, L, pos):
     n = kv.shape[0]
     a = np.zeros((n, n))
@@ -144,6 +156,14 @@ def residual(ainv, a):
 
 def sm_ratio(ainv, e, phi):
     return lib().orc_sm_ratio(ainv.shape[0], np.ascontiguousarray(ainv), int(e), np.ascontiguousarray(phi, np.float64))
+
+
+def sm_ratio_grad(ainv, e, phi, dphi):
+    """(R, grad R) of eq. (1) for row e -> phi with gradient rows dphi (3, n)."""
+    g = np.zeros(3)
+    r = lib().orc_sm_ratio_grad(ainv.shape[0], np.ascontiguousarray(ainv), int(e),
+                                np.ascontiguousarray(phi, np.float64), np.ascontiguousarray(dphi, np.float64), g)
+    return r, g
 
 
 def sm_accept(ainv, a, e, phi, r):

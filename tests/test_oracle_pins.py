@@ -332,3 +332,80 @@ def test_walkers_run_matches_single():
         np.testing.assert_array_equal(ratio[w], t.ratio)
         np.testing.assert_array_equal(ld[w], t.logdet_run)
     assert threads >= 1
+
+
+# ------------------------------------- gradient rows and ratio gradients
+def test_plane_wave_gradient_values_and_differences():
+    # Closed form at the point of test_plane_wave_values (phases pi, pi/2,
+    # pi/4 along z, y, x), then central differences everywhere else.
+    kv = oracle.pw_kvectors(7)
+    L = 10.0
+    g = 2 * math.pi / L
+    r = np.array([1.25, 2.5, 5.0])
+    d = oracle.pw_row_grad(kv, L, r)
+    s = math.sqrt(0.5)
+    want = np.zeros((3, 7))
+    want[2, 1], want[2, 2] = 0.0, -g        # cos, sin of n = (0,0,1) at pi
+    want[1, 3], want[1, 4] = -g, 0.0        # n = (0,1,0) at pi/2
+    want[0, 5], want[0, 6] = -g * s, g * s  # n = (1,0,0) at pi/4
+    np.testing.assert_allclose(d, want, atol=1e-15)
+    kv = oracle.pw_kvectors(65)
+    rng = np.random.default_rng(5)
+    h = 1e-5
+    for r in rng.uniform(0, 7.0, size=(4, 3)):
+        d = oracle.pw_row_grad(kv, 7.0, r)
+        for a in range(3):
+            dr = np.zeros(3); dr[a] = h
+            fd = (oracle.pw_row(kv, 7.0, r + dr) - oracle.pw_row(kv, 7.0, r - dr)) / (2 * h)
+            np.testing.assert_allclose(d[a], fd, atol=1e-7)
+
+
+def _ratio_by_det(a, e, row):
+    # det(A') / det(A) through numpy's LU: independent of eq. (1)
+    b = a.copy(); b[e] = row
+    s1, l1 = np.linalg.slogdet(b)
+    s0, l0 = np.linalg.slogdet(a)
+    return s1 * s0 * math.exp(l1 - l0)
+
+
+def test_ratio_gradient_is_derivative_of_determinant_ratio():
+    n, L = 24, 4.0
+    kv = oracle.pw_kvectors(n)
+    pos = inputs.positions(11, 0, n, L)
+    a = oracle.pw_matrix(kv, L, pos)
+    ainv, _, _ = oracle.inverse(a)
+    h = 1e-6
+    for e in (0, 7, n - 1):
+        rp = pos[e] + np.array([0.03, -0.02, 0.05]) * L
+        r, grad = oracle.sm_ratio_grad(ainv, e, oracle.pw_row(kv, L, rp), oracle.pw_row_grad(kv, L, rp))
+        assert abs(r - _ratio_by_det(a, e, oracle.pw_row(kv, L, rp))) < 1e-10 * max(1, abs(r))
+        fd = np.zeros(3)
+        for k in range(3):
+            dr = np.zeros(3); dr[k] = h
+            fd[k] = (_ratio_by_det(a, e, oracle.pw_row(kv, L, rp + dr))
+                     - _ratio_by_det(a, e, oracle.pw_row(kv, L, rp - dr))) / (2 * h)
+        np.testing.assert_allclose(grad, fd, rtol=1e-6, atol=1e-7 * np.abs(fd).max())
+        # a transposed inverse (plausible slip) is caught by the same check
+        _, bad = oracle.sm_ratio_grad(np.ascontiguousarray(ainv.T), e, oracle.pw_row(kv, L, rp),
+                                      oracle.pw_row_grad(kv, L, rp))
+        assert np.abs(bad - fd).max() > 1e-3 * np.abs(fd).max()
+
+
+def test_ratio_gradient_two_electron_closed_form():
+    # Orbitals {1, cos(g n.r)}: det A = cos(ph_2) - cos(ph_1), so moving
+    # electron 1 (row 0) to r' gives R = (cos ph_2 - cos ph') / det A and
+    # grad R = g n sin(ph') / det A; at r' = r_1 it is the drift.
+    kv = oracle.pw_kvectors(2)
+    L = 3.0
+    g = 2 * math.pi / L
+    nv = kv[1, :3].astype(float)
+    assert kv[1, 3] == 1
+    r1, r2 = np.array([0.2, 0.9, 1.7]), np.array([1.1, 0.4, 2.6])
+    a = oracle.pw_matrix(kv, L, np.array([r1, r2]))
+    ainv, _, _ = oracle.inverse(a)
+    det = math.cos(g * nv @ r2) - math.cos(g * nv @ r1)
+    for rp in (r1, np.array([0.5, 2.0, 0.1])):
+        ph = g * nv @ rp
+        r, grad = oracle.sm_ratio_grad(ainv, 0, oracle.pw_row(kv, L, rp), oracle.pw_row_grad(kv, L, rp))
+        assert abs(r - (math.cos(g * nv @ r2) - math.cos(ph)) / det) < 1e-13
+        np.testing.assert_allclose(grad, g * nv * math.sin(ph) / det, rtol=1e-12, atol=1e-14)
