@@ -42,7 +42,7 @@ FLUSH_TRAFFIC = {
     "sources_sha256": {
         "k_stream.hip": "a74063f2831479e4202cc30840d36f384b0306dc2e69526e33f3464b608eb417",
         "tiles.hpp": "922215d624556b60ccf0f15ae683635301cd30a16be6b554702694307bfa1413",
-        "dsu_internal.hpp": "5df570fc9249c35c465dd8d59d444747613872db6a4b0b93c594aaee8876581b",
+        "dsu_internal.hpp": "e723f94fbf6a0830c84a5ae0f960cc2729e2ef007c2a3e89eb79b6b529f0eba8",
     },
 }
 
@@ -234,6 +234,63 @@ def fp64_single_walker(cache, n=1024, sweeps=1):
     return res
 
 
+def drift_single_walker(n=1024, moves=1024, tau=0.002):
+    """Host-driven drift-diffusion (DMC-style) moves in FP64: per move the
+    drift at the present position (dsu_eval_grad), R and grad R at the
+    proposed one (dsu_propose_ratio_grad), accept with the Green's-function
+    ratio.  The caller evaluates the plane-wave rows and their gradients with
+    numpy; `library_us_per_move` counts only the library calls."""
+    from paper_1708_00744_amd import dsu, inputs
+    kv = dsu.plane_wave_table(n).astype(np.float64)
+    kind = kv[:, 3]
+    g2 = 2 * np.pi / BOX_L
+
+    def rows(r):
+        ph = g2 * (kv[:, :3] @ r)
+        c, s = np.cos(ph), np.sin(ph)
+        row = np.where(kind == 0, 1.0, np.where(kind == 1, c, s))
+        d = np.where(kind == 1, -s, np.where(kind == 2, c, 0.0))
+        return row, (g2 * kv[:, :3].T) * d
+
+    pos = inputs.positions(2, 0, n, BOX_L)
+    a0 = dsu.plane_wave_rows(n, BOX_L, pos)
+    chi = inputs.normals(5, (moves, 3))
+    us = inputs.uniforms(6, moves)
+    res = {"n": n, "tau": tau, "moves": moves}
+    for K in (1, 64):
+        p = pos.copy()
+        acc, t_lib = 0, 0.0
+        with dsu.Walker(a0, K, precision=dsu.FP64, policy=dsu.FLUSH_K_ACCEPTED) as w:
+            t0 = time.perf_counter()
+            for m in range(moves):
+                e = m % n
+                _, d_old = rows(p[e])
+                t1 = time.perf_counter()
+                v_old = w.grad(e, d_old)
+                t_lib += time.perf_counter() - t1
+                rp = p[e] + tau * v_old + np.sqrt(tau) * chi[m]
+                row, drow = rows(rp)
+                t1 = time.perf_counter()
+                r, g = w.propose_grad(e, row, drow)
+                t_lib += time.perf_counter() - t1
+                v_new = g / r
+                log_g = (np.sum((rp - p[e] - tau * v_old) ** 2) - np.sum((p[e] - rp - tau * v_new) ** 2)) / (2 * tau)
+                t1 = time.perf_counter()
+                if us[m] < r * r * np.exp(log_g):
+                    w.accept()
+                    p[e] = rp
+                    acc += 1
+                else:
+                    w.reject()
+                t_lib += time.perf_counter() - t1
+            w.flush()
+            dt = time.perf_counter() - t0
+        res[f"K{K}_moves_per_s"] = moves / dt
+        res[f"K{K}_library_us_per_move"] = 1e6 * t_lib / moves
+        res[f"K{K}_acceptance"] = acc / moves
+    return res
+
+
 def serving(cache, count=40, seed=7):
     from paper_1708_00744_amd import dsu, inputs
     sizes, accs, seeds = inputs.serving_mix(seed, count)
@@ -340,6 +397,8 @@ def main():
         extras["fp64_batched_n2048"] = batched_at(2048, 64, cache, precision=dsu.FP64)
         log("FP64 single walker N=1024")
         extras["fp64_single_walker_n1024"] = fp64_single_walker(cache)
+        log("FP64 drift-diffusion walker N=1024")
+        extras["fp64_drift_walker_n1024"] = drift_single_walker()
         log("serving")
         extras["serving"] = serving(cache)
     cpu = None

@@ -117,6 +117,27 @@ int dsu_propose_ratio(dsu_walker *w, int32_t electron, const double *phi_host, d
  * (double for DSU_FP64, float for DSU_FP32_MIXED), n values. */
 int dsu_propose_ratio_dev(dsu_walker *w, int32_t electron, const void *phi_dev, double *ratio_out);
 
+/* Ratio and its gradient with respect to the proposed position: the
+ * drift-diffusion move of DMC (Sec. II: short time steps, high acceptance)
+ * needs grad R / R at the proposed point.  The determinant is linear in the
+ * replaced row, so the eq. (3) look-ahead applied to the three derivative
+ * rows gives grad R with the same C_k^{-1} q as R (3 more products of
+ * length n against BT row e and each pending Vg row).  dphi_host is 3*n FP64,
+ * row-major: dphi_host[a*n + j] = d phi_j / d r_a (a = x, y, z) at the
+ * proposed position.  grad_out receives 3 values (grad R, not grad R / R).
+ * The proposal stays pending exactly as for dsu_propose_ratio (same repeat
+ * rule, same dsu_accept / dsu_reject).  Synchronises.  DSU_EINVAL on a NULL
+ * pointer or an electron out of range. */
+int dsu_propose_ratio_grad(dsu_walker *w, int32_t electron, const double *phi_host, const double *dphi_host,
+                           double *ratio_out, double *grad_out);
+/* Drift at the present configuration: grad_e ln|det A| = dphi . A_k^{-1}[:, e]
+ * with dphi (3*n FP64, as above) the gradient rows of electron `electron`'s
+ * present row, A_k the matrix with every pending accepted move applied (the
+ * same look-ahead; if the electron itself holds a pending move, its slot's
+ * unit vector is taken out of the right-hand side).  Reads only: a pending
+ * proposal stays pending and nothing is flushed.  Synchronises. */
+int dsu_eval_grad(dsu_walker *w, int32_t electron, const double *dphi_host, double *grad_out);
+
 /* Accept the pending proposal: queue it in the delayed buffer (Sec. II),
  * border the K x K inverse, update A's row and the running log-determinant.
  * When the delay limit is reached the queued moves are applied en bloc by

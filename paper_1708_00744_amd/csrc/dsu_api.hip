@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "host_common.hpp"
+#include "walker.hpp"
 
 using namespace dsu;
 
@@ -35,8 +36,8 @@ struct dsu_walker {
     double **a_ptr = nullptr;       // device array {a}
     void **bt_ptr = nullptr;        // device array {bt}
     double *inv_tmp = nullptr;      // n x n FP64 for dsu_get_inverse
-    double *row_stage = nullptr;    // pinned host staging for proposal rows
-    double *ratio_h = nullptr;      // pinned host word the propose kernel writes R into
+    double *row_stage = nullptr;    // pinned host staging: proposal row, then its 3 gradient rows
+    double *ratio_h = nullptr;      // pinned host words the propose kernel writes R and grad R into
     GjWork gj;
     // host mirror of the state machine
     int k = 0, slots = 0;
@@ -53,6 +54,7 @@ static size_t elem(int prec) { return dsu::elem_size(prec); }
 static void walker_free(dsu_walker *w) {
     if (w->wd.phi != (void *)w->wd.phi64) dfree(w->wd.phi);  // FP64 walkers share one row buffer
     for (void *p : {w->wd.bt, w->wd.u, w->wd.vg, (void *)w->wd.a, (void *)w->wd.phi64, (void *)w->wd.cinv,
+                    (void *)w->wd.gdots,
                     (void *)w->wd.dots, (void *)w->wd.t, (void *)w->wd.ratio, (void *)w->wd.idx, (void *)w->wd.counter,
                     w->flush_desc, (void *)w->a_ptr, (void *)w->bt_ptr, (void *)w->inv_tmp})
         dfree(p);
@@ -115,9 +117,12 @@ extern "C" int dsu_walker_create(int32_t n, int32_t k_delay, int32_t precision, 
     TRY(dev_alloc(&w->wd.u, kp * np * s));
     TRY(dev_alloc(&w->wd.vg, kp * np * s));
     TRY(dalloc(&w->wd.a, np * np));
-    TRY(dalloc(&w->wd.phi64, np));
+    // proposal row and its three gradient rows, contiguous (np each)
+    TRY(dalloc(&w->wd.phi64, 4 * np));
     if (precision == DSU_FP64) w->wd.phi = w->wd.phi64;
-    else TRY(dev_alloc(&w->wd.phi, np * s));
+    else TRY(dev_alloc(&w->wd.phi, 4 * np * s));
+    w->wd.dphi = static_cast<char *>(w->wd.phi) + np * s;
+    TRY(dalloc(&w->wd.gdots, 3 * (kp + 1) + kp));
     TRY(dalloc(&w->wd.cinv, kp * (kp + 1)));
     TRY(dalloc(&w->wd.dots, 1 + 2 * kp));
     TRY(dalloc(&w->wd.t, kp));
@@ -125,9 +130,9 @@ extern "C" int dsu_walker_create(int32_t n, int32_t k_delay, int32_t precision, 
     TRY(dalloc(&w->wd.idx, kp));
     TRY(dalloc(&w->wd.counter, 1));
     w->wd.ldc = (int)kp + 1;
-    if (hipHostMalloc((void **)&w->ratio_h, sizeof(double), hipHostMallocMapped) != hipSuccess)
+    if (hipHostMalloc((void **)&w->ratio_h, 4 * sizeof(double), hipHostMallocMapped) != hipSuccess)
         TRY(fail(DSU_ENOMEM, "hipHostMalloc failed"));
-    if (hipHostMalloc((void **)&w->row_stage, np * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&w->row_stage, 4 * np * sizeof(double), hipHostMallocDefault) != hipSuccess)
         TRY(fail(DSU_ENOMEM, "hipHostMalloc failed"));
     {
         void *dptr = nullptr;
@@ -192,21 +197,44 @@ extern "C" int dsu_flush(dsu_walker *w) {
     return walker_do_flush(w);
 }
 
-static int walker_propose_common(dsu_walker *w, int e, double *ratio_out) {
+static int walker_propose_common(dsu_walker *w, int e, double *ratio_out, double *grad_out = nullptr) {
     // an electron may hold at most one pending move: apply the window first
     for (int j = 0; j < w->k; ++j)
         if (w->idx[j] == e) {
             CHK(walker_do_flush(w));
             break;
         }
-    if (w->prec == DSU_FP64) HIPCHK(launch_walker_propose<double>(&w->wd, w->n, w->np, w->k, e, w->stream));
-    else HIPCHK(launch_walker_propose<float>(&w->wd, w->n, w->np, w->k, e, w->stream));
+    const int gm = grad_out ? 1 : 0;
+    if (w->prec == DSU_FP64) HIPCHK(launch_walker_propose<double>(&w->wd, w->n, w->np, w->k, e, gm, -1, w->stream));
+    else HIPCHK(launch_walker_propose<float>(&w->wd, w->n, w->np, w->k, e, gm, -1, w->stream));
     HIPCHK(hipStreamSynchronize(w->stream));
-    const double r = *(volatile double *)w->ratio_h;
+    const volatile double *h = w->ratio_h;
+    const double r = h[0];
     w->has_prop = true;
     w->prop_e = e;
     w->prop_r = r;
     if (ratio_out) *ratio_out = r;
+    if (grad_out)
+        for (int a = 0; a < 3; ++a) grad_out[a] = h[1 + a];
+    return DSU_OK;
+}
+
+// Stage `nrows` host rows (n FP64 each) at row `first` of the walker's
+// 4-row block (0 = proposal, 1..3 = gradient rows), zero padded to np, and
+// convert them to the walker's precision.
+static int walker_stage_rows(dsu_walker *w, int first, int nrows, const double *const *rows) {
+    // the staging buffer may still feed a previous copy: wait for the stream
+    HIPCHK(hipStreamSynchronize(w->stream));
+    const size_t np = w->np;
+    double *st = w->row_stage + first * np;
+    for (int r = 0; r < nrows; ++r) {
+        std::memcpy(st + r * np, rows[r], sizeof(double) * w->n);
+        std::memset(st + r * np + w->n, 0, sizeof(double) * (np - w->n));
+    }
+    HIPCHK(hipMemcpyAsync(w->wd.phi64 + first * np, st, sizeof(double) * nrows * np, hipMemcpyHostToDevice, w->stream));
+    if (w->prec != DSU_FP64)
+        HIPCHK(launch_row_to(w->wd.phi64 + first * np, static_cast<float *>(w->wd.phi) + first * np, 1,
+                             (int)(nrows * np), (int)(nrows * np), w->stream));
     return DSU_OK;
 }
 
@@ -214,13 +242,35 @@ extern "C" int dsu_propose_ratio(dsu_walker *w, int32_t electron, const double *
     if (!w) return fail(DSU_EINVAL, "walker is NULL");
     if (electron < 0 || electron >= w->n) return fail(DSU_EINVAL, "electron %d out of range", electron);
     if (!phi_host) return fail(DSU_EINVAL, "row is NULL");
-    // the staging buffer may still feed a previous copy: wait for the stream
-    HIPCHK(hipStreamSynchronize(w->stream));
-    std::memcpy(w->row_stage, phi_host, sizeof(double) * w->n);
-    std::memset(w->row_stage + w->n, 0, sizeof(double) * (w->np - w->n));
-    HIPCHK(hipMemcpyAsync(w->wd.phi64, w->row_stage, sizeof(double) * w->np, hipMemcpyHostToDevice, w->stream));
-    if (w->prec != DSU_FP64) HIPCHK(launch_row_to(w->wd.phi64, w->wd.phi, 1, w->n, w->np, w->stream));
+    CHK(walker_stage_rows(w, 0, 1, &phi_host));
     return walker_propose_common(w, electron, ratio_out);
+}
+
+extern "C" int dsu_propose_ratio_grad(dsu_walker *w, int32_t electron, const double *phi_host, const double *dphi_host,
+                                      double *ratio_out, double *grad_out) {
+    if (!w) return fail(DSU_EINVAL, "walker is NULL");
+    if (electron < 0 || electron >= w->n) return fail(DSU_EINVAL, "electron %d out of range", electron);
+    if (!phi_host || !dphi_host || !grad_out) return fail(DSU_EINVAL, "NULL argument");
+    const double *rows[4] = {phi_host, dphi_host, dphi_host + w->n, dphi_host + 2 * (size_t)w->n};
+    CHK(walker_stage_rows(w, 0, 4, rows));
+    return walker_propose_common(w, electron, ratio_out, grad_out);
+}
+
+extern "C" int dsu_eval_grad(dsu_walker *w, int32_t electron, const double *dphi_host, double *grad_out) {
+    if (!w) return fail(DSU_EINVAL, "walker is NULL");
+    if (electron < 0 || electron >= w->n) return fail(DSU_EINVAL, "electron %d out of range", electron);
+    if (!dphi_host || !grad_out) return fail(DSU_EINVAL, "NULL argument");
+    const double *rows[3] = {dphi_host, dphi_host + w->n, dphi_host + 2 * (size_t)w->n};
+    CHK(walker_stage_rows(w, 1, 3, rows));
+    int m = -1;  // pending slot holding this electron's accepted move, if any
+    for (int j = 0; j < w->k; ++j)
+        if (w->idx[j] == electron) m = j;
+    if (w->prec == DSU_FP64) HIPCHK(launch_walker_propose<double>(&w->wd, w->n, w->np, w->k, electron, 2, m, w->stream));
+    else HIPCHK(launch_walker_propose<float>(&w->wd, w->n, w->np, w->k, electron, 2, m, w->stream));
+    HIPCHK(hipStreamSynchronize(w->stream));
+    const volatile double *h = w->ratio_h;
+    for (int a = 0; a < 3; ++a) grad_out[a] = h[1 + a];
+    return DSU_OK;
 }
 
 extern "C" int dsu_propose_ratio_dev(dsu_walker *w, int32_t electron, const void *phi_dev, double *ratio_out) {

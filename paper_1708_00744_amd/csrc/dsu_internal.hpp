@@ -151,32 +151,8 @@ hipError_t launch_build_pw_transpose(const double *const *pos_dev, double *const
 template <typename T>
 hipError_t launch_untranspose(const T *bt, double *out, int n, int np, hipStream_t s);
 
-// Single-walker device state (one walker, precision T behind the void*).
+// Largest delay a kernel stages per-slot values for in LDS.
 #define DSU_KMAX_LDS 256
-struct WalkerDev {
-    void *bt;          // np x np, T
-    void *u;           // kp x np, T
-    void *vg;          // kp x np, T
-    double *a;         // np x np, FP64 Slater matrix
-    void *phi;         // np, T: pending proposal row
-    double *phi64;     // np, FP64 copy of the proposal row
-    double *cinv;      // kp x (kp+1): C_k^{-1} in pending order
-    double *dots;      // 1 + 2 kp: r0, p[0..k), q[0..k)
-    double *t;         // kp: C_k^{-1} q
-    double *ratio;     // device copy of R
-    double *ratio_host;// pinned host memory (mapped): R for the caller
-    int *idx;          // kp pending electrons
-    unsigned *counter; // blocks finished (last-block reduction)
-    int ldc;           // kp + 1
-};
-
-// Single-walker look-ahead ratio and accept (bordering).
-template <typename T>
-hipError_t launch_walker_propose(WalkerDev *wd, int n, int np, int k, int e, hipStream_t s);
-template <typename T>
-hipError_t launch_walker_accept(WalkerDev *wd, int n, int np, int k, int kp, int e, hipStream_t s);
-// Row copy into a padded device row: mode 0 FP64->FP64, 1 FP64->float, 2 float->FP64.
-hipError_t launch_row_to(const double *src, void *dst, int mode, int n, int np, hipStream_t s);
 
 // Batched window kernels.  ktile = padded delay of the launch (template tile
 // count, 16..256), kp = padded delay the buffers were allocated for (stride),

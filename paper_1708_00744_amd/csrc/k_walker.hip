@@ -10,64 +10,122 @@
 // to date by bordering when a move is accepted, so the look-ahead costs
 // (2k+1) dot products of length n plus O(k^2) -- no explicit k x k
 // determinants.
-#include "dsu_internal.hpp"
+#include "walker.hpp"
 
 namespace dsu {
 
 
-template <typename T>
-__device__ __forceinline__ T block_sum(T v, T *sbuf) {
+// Sum NV values over the block; every thread gets the totals.
+template <typename T, int NV>
+__device__ __forceinline__ void block_sum_n(T (&v)[NV], T (*sbuf)[kThreads / 64]) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) sbuf[wave] = v;
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sbuf[i][wave] = v[i];
     __syncthreads();
-    T s = T(0);
-    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += sbuf[q];
-    return s;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        T s = T(0);
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += sbuf[i][q];
+        v[i] = s;
+    }
 }
 
-// Grid of 2k+1 blocks: block 0 -> r0, 1..k -> p, k+1..2k -> q.  The last
-// block to finish forms t = C_k^{-1} q and R = r0 - p.t.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_walker_propose(WalkerDev w, int np, int k, int e) {
-    __shared__ T sbuf[kThreads / 64];
-    __shared__ double dbuf[kThreads / 64];
+// Look-ahead products of a set of x rows against one electron (Sec. II,
+// eq. (3)).  R(x) = x.BT[e] - sum_j (x.Vg[j]) t_j with t = C_k^{-1} q is
+// linear in x, so the ratio (x = phi) and its gradient with respect to the
+// new position (x = d phi / d r_a, a = x, y, z) share q and t; so does the
+// drift grad_e ln|det A| at the present position (x = gradient rows of the
+// present row, whose own ratio is 1).
+//   GR = 0: x = {phi};  GR = 1: x = {phi, dphi_x, dphi_y, dphi_z};
+//   GR = 2: x = {dphi_x, dphi_y, dphi_z}, the present position's gradient:
+//           results go to gdots and ratio_host[1..3] and leave the pending
+//           proposal (dots, t, ratio) untouched.  If e itself holds pending
+//           slot m, row e of the delayed matrix is U[m], and the lemma's
+//           right-hand side becomes q - 1_m.
+// Grid of 2k+1 blocks: block 0 -> x.BT[e], 1..k -> x.Vg[j], k+1..2k -> q.
+// The last block to finish forms t and the results.
+template <typename T, int GR>
+__global__ __launch_bounds__(kThreads) void k_walker_propose(WalkerDev w, int np, int k, int e, int m) {
+    constexpr int NX = GR == 0 ? 1 : (GR == 1 ? 4 : 3);
+    constexpr int X0 = GR == 1 ? 1 : 0;  // first gradient row
+    __shared__ T sbuf[NX][kThreads / 64];
+    __shared__ double dbuf[4][kThreads / 64];
     __shared__ int is_last;
     __shared__ double s_t[DSU_KMAX_LDS];
     const int b = blockIdx.x, tid = threadIdx.x;
     const T *bt = static_cast<const T *>(w.bt), *u = static_cast<const T *>(w.u), *vg = static_cast<const T *>(w.vg);
-    const T *phi = static_cast<const T *>(w.phi);
-    const T *x, *y;
-    if (b == 0) { x = phi; y = bt + (size_t)e * np; }
-    else if (b <= k) { x = phi; y = vg + (size_t)(b - 1) * np; }
-    else { x = u + (size_t)(b - 1 - k) * np; y = bt + (size_t)e * np; }
-    T acc = T(0);
-    for (int c = tid; c < np; c += kThreads) acc += x[c] * y[c];
-    acc = block_sum(acc, sbuf);
+    const T *phi = static_cast<const T *>(w.phi), *dphi = static_cast<const T *>(w.dphi);
+    const int ld = k + 1;
+    if (b <= k) {
+        const T *x[NX];
+        if (GR != 2) x[0] = phi;
+        if (GR != 0)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) x[X0 + a] = dphi + (size_t)a * np;
+        const T *y = b == 0 ? bt + (size_t)e * np : vg + (size_t)(b - 1) * np;
+        T acc[NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) acc[i] = T(0);
+        for (int c = tid; c < np; c += kThreads) {
+            const T yc = y[c];
+#pragma unroll
+            for (int i = 0; i < NX; ++i) acc[i] += x[i][c] * yc;
+        }
+        block_sum_n<T, NX>(acc, sbuf);
+        if (tid == 0) {
+            if (GR != 2) w.dots[b] = double(acc[0]);
+            if (GR != 0)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) w.gdots[a * ld + b] = double(acc[X0 + a]);
+        }
+    } else {
+        const T *x = u + (size_t)(b - 1 - k) * np, *y = bt + (size_t)e * np;
+        T acc[1] = {T(0)};
+        for (int c = tid; c < np; c += kThreads) acc[0] += x[c] * y[c];
+        block_sum_n<T, 1>(acc, sbuf);
+        if (tid == 0) (GR == 2 ? w.gdots + 3 * ld : w.dots + 1 + k)[b - 1 - k] = double(acc[0]);
+    }
     if (tid == 0) {
-        w.dots[b] = double(acc);
         __threadfence();
         is_last = atomicAdd(w.counter, 1u) == gridDim.x - 1;
     }
     __syncthreads();
     if (!is_last) return;
     __threadfence();
+    const double *q = GR == 2 ? w.gdots + 3 * ld : w.dots + 1 + k;
     for (int i = tid; i < k; i += kThreads) {
         double s = 0.0;
-        for (int j = 0; j < k; ++j) s += w.cinv[(size_t)i * w.ldc + j] * w.dots[1 + k + j];
+        for (int j = 0; j < k; ++j) s += w.cinv[(size_t)i * w.ldc + j] * (q[j] - (j == m ? 1.0 : 0.0));
         s_t[i] = s;
-        w.t[i] = s;
+        if (GR != 2) w.t[i] = s;
     }
     __syncthreads();
-    double part = 0.0;
-    for (int i = tid; i < k; i += kThreads) part += w.dots[1 + i] * s_t[i];
-    part = block_sum(part, dbuf);
+    constexpr int NO = GR == 0 ? 1 : (GR == 1 ? 4 : 3);  // ratio and / or three gradient components
+    double part[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) part[o] = 0.0;
+    for (int i = tid; i < k; i += kThreads) {
+        if (GR != 2) part[0] += w.dots[1 + i] * s_t[i];
+        if (GR != 0)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) part[X0 + a] += w.gdots[a * ld + 1 + i] * s_t[i];
+    }
+    block_sum_n<double, NO>(part, dbuf);
     if (tid == 0) {
-        const double r = w.dots[0] - part;
-        w.ratio[0] = r;
-        *w.ratio_host = r;
+        if (GR != 2) {
+            const double r = w.dots[0] - part[0];
+            w.ratio[0] = r;
+            w.ratio_host[0] = r;
+        }
+        if (GR != 0)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) w.ratio_host[1 + a] = w.gdots[a * ld] - part[X0 + a];
         *w.counter = 0u;
     }
 }
@@ -110,9 +168,11 @@ __global__ __launch_bounds__(kThreads) void k_walker_accept(WalkerDev w, int np,
 }
 
 template <typename T>
-hipError_t launch_walker_propose(WalkerDev *wd, int n, int np, int k, int e, hipStream_t s) {
+hipError_t launch_walker_propose(WalkerDev *wd, int n, int np, int k, int e, int grad_mode, int m, hipStream_t s) {
     (void)n;
-    hipLaunchKernelGGL((k_walker_propose<T>), dim3(2 * k + 1), dim3(kThreads), 0, s, *wd, np, k, e);
+    if (grad_mode == 0) hipLaunchKernelGGL((k_walker_propose<T, 0>), dim3(2 * k + 1), dim3(kThreads), 0, s, *wd, np, k, e, -1);
+    else if (grad_mode == 1) hipLaunchKernelGGL((k_walker_propose<T, 1>), dim3(2 * k + 1), dim3(kThreads), 0, s, *wd, np, k, e, -1);
+    else hipLaunchKernelGGL((k_walker_propose<T, 2>), dim3(2 * k + 1), dim3(kThreads), 0, s, *wd, np, k, e, m);
     return hipGetLastError();
 }
 template <typename T>
@@ -122,8 +182,8 @@ hipError_t launch_walker_accept(WalkerDev *wd, int n, int np, int k, int kp, int
     hipLaunchKernelGGL((k_walker_accept<T>), dim3(1), dim3(kThreads), 0, s, *wd, np, k, e);
     return hipGetLastError();
 }
-template hipError_t launch_walker_propose<float>(WalkerDev *, int, int, int, int, hipStream_t);
-template hipError_t launch_walker_propose<double>(WalkerDev *, int, int, int, int, hipStream_t);
+template hipError_t launch_walker_propose<float>(WalkerDev *, int, int, int, int, int, int, hipStream_t);
+template hipError_t launch_walker_propose<double>(WalkerDev *, int, int, int, int, int, int, hipStream_t);
 template hipError_t launch_walker_accept<float>(WalkerDev *, int, int, int, int, int, hipStream_t);
 template hipError_t launch_walker_accept<double>(WalkerDev *, int, int, int, int, int, hipStream_t);
 

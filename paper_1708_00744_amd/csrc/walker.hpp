@@ -1,0 +1,38 @@
+// walker.hpp -- device state and kernel launchers of the host-driven single
+// walker (look-ahead ratio, its gradient, accept with bordering).
+#pragma once
+#include "dsu_internal.hpp"
+
+namespace dsu {
+
+// Single-walker device state (one walker, precision T behind the void*).
+struct WalkerDev {
+    void *bt;          // np x np, T
+    void *u;           // kp x np, T
+    void *vg;          // kp x np, T
+    double *a;         // np x np, FP64 Slater matrix
+    void *phi;         // np, T: pending proposal row
+    double *phi64;     // np, FP64 copy of the proposal row
+    double *cinv;      // kp x (kp+1): C_k^{-1} in pending order
+    double *dots;      // 1 + 2 kp: r0, p[0..k), q[0..k)
+    double *t;         // kp: C_k^{-1} q
+    double *ratio;     // device copy of R
+    double *ratio_host;// pinned host memory (mapped): R, then grad R (or the drift) for the caller
+    void *dphi;        // 3 x np, T: gradient rows (x, y, z) of the proposal or of the present row
+    double *gdots;     // 3 (kp + 1) + kp: gradient rows against BT[e] and Vg, then q of the drift call
+    int *idx;          // kp pending electrons
+    unsigned *counter; // blocks finished (last-block reduction)
+    int ldc;           // kp + 1
+};
+
+// Single-walker look-ahead ratio and accept (bordering).
+// grad_mode 0: ratio; 1: ratio and its gradient; 2: gradient of the present
+// row only (m = pending slot held by e, or -1).
+template <typename T>
+hipError_t launch_walker_propose(WalkerDev *wd, int n, int np, int k, int e, int grad_mode, int m, hipStream_t s);
+template <typename T>
+hipError_t launch_walker_accept(WalkerDev *wd, int n, int np, int k, int kp, int e, hipStream_t s);
+// Row copy into a padded device row: mode 0 FP64->FP64, 1 FP64->float, 2 float->FP64.
+hipError_t launch_row_to(const double *src, void *dst, int mode, int n, int np, hipStream_t s);
+
+}  // namespace dsu

@@ -59,6 +59,8 @@ SIGNATURES = {
     "dsu_walker_destroy": (C.c_int, [_vp]),
     "dsu_propose_ratio": (C.c_int, [_vp, _i32, _pd, _pd]),
     "dsu_propose_ratio_dev": (C.c_int, [_vp, _i32, _vp, _pd]),
+    "dsu_propose_ratio_grad": (C.c_int, [_vp, _i32, _pd, _pd, _pd, _pd]),
+    "dsu_eval_grad": (C.c_int, [_vp, _i32, _pd, _pd]),
     "dsu_accept": (C.c_int, [_vp]),
     "dsu_reject": (C.c_int, [_vp]),
     "dsu_flush": (C.c_int, [_vp]),
@@ -185,6 +187,21 @@ class Walker:
         r = C.c_double()
         _check(lib().dsu_propose_ratio_dev(self._h, int(electron), C.c_void_p(row_ptr), C.byref(r)))
         return r.value
+
+    def propose_grad(self, electron, row, drows):
+        """(R, grad R) for moving `electron` to the row `row` whose gradient
+        rows (3, n) are `drows`; the proposal stays pending."""
+        r, g = C.c_double(), np.zeros(3)
+        d = _f64(drows, (3, self.n))
+        _check(lib().dsu_propose_ratio_grad(self._h, int(electron), _dp(_f64(row)), _dp(d), C.byref(r), _dp(g)))
+        return r.value, g
+
+    def grad(self, electron, drows):
+        """grad_e ln|det A| at the present configuration, given the gradient
+        rows (3, n) of the electron's present row."""
+        g = np.zeros(3)
+        _check(lib().dsu_eval_grad(self._h, int(electron), _dp(_f64(drows, (3, self.n))), _dp(g)))
+        return g
 
     def accept(self):
         _check(lib().dsu_accept(self._h))
