@@ -42,7 +42,7 @@ FLUSH_TRAFFIC = {
     "sources_sha256": {
         "k_stream.hip": "a74063f2831479e4202cc30840d36f384b0306dc2e69526e33f3464b608eb417",
         "tiles.hpp": "922215d624556b60ccf0f15ae683635301cd30a16be6b554702694307bfa1413",
-        "dsu_internal.hpp": "e723f94fbf6a0830c84a5ae0f960cc2729e2ef007c2a3e89eb79b6b529f0eba8",
+        "dsu_internal.hpp": "e1b46a3270f3f13c8ebc4493896903ea0a81a27474dc40ea84a4179788fdcf2b",
     },
 }
 

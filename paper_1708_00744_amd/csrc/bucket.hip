@@ -342,6 +342,9 @@ template <typename T> int Bucket::enqueue_sweep_stream_t(int force) {
         }));
         if (has_next) HIPCHK(hipStreamWaitEvent(stream, join, 0));
         CHK(timed(PH_FLUSH, [&] {
+            if (sizeof(T) == 4 && flush_path == 2 && (kt == 32 || kt == 64 || kt == 128))
+                return launch_flush_stream_x6((const DetDesc<float> *)dd, nd, sh.np, kt, sh.kp, kw_of(w), cur,
+                                              has_next ? 1 : 0, e0n, kwn, stream);
             return launch_flush_stream<T>(dd, nd, sh.np, kt, sh.kp, kw_of(w), cur, has_next ? 1 : 0, e0n, kwn, stream);
         }));
     }
@@ -349,7 +352,7 @@ template <typename T> int Bucket::enqueue_sweep_stream_t(int force) {
 }
 
 int Bucket::enqueue_sweep(int force) {
-    if (streaming)
+    if (flush_path != 0)
         return sh.prec == DSU_FP64 ? enqueue_sweep_stream_t<double>(force) : enqueue_sweep_stream_t<float>(force);
     return sh.prec == DSU_FP64 ? enqueue_sweep_t<double>(force) : enqueue_sweep_t<float>(force);
 }
@@ -762,9 +765,10 @@ extern "C" int dsu_batch_use_graph(dsu_batch *b, int32_t enable) {
     return DSU_OK;
 }
 
-extern "C" int dsu_batch_set_flush_path(dsu_batch *b, int32_t streaming) {
+extern "C" int dsu_batch_set_flush_path(dsu_batch *b, int32_t path) {
     if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (path < 0 || path > 2) return fail(DSU_EINVAL, "bad flush path %d", path);
     HIPCHK(hipStreamSynchronize(b->bk.stream));
-    b->bk.streaming = streaming != 0;
+    b->bk.flush_path = path;
     return b->bk.set_dets(b->bk.dets);  // drops any captured graph
 }

@@ -49,7 +49,10 @@ class Bucket {
     std::vector<DetSlot> dets;
     bool use_graph = false;
     bool timing = false;
-    bool streaming = true;  // one-pass flush with the next window's products (else 4-launch windows)
+    // 0: four launches per window; 1: one-pass flush with the next window's
+    // products, FP32 matrix-core products; 2: the same pass with split-bf16
+    // products (FP32 determinants only; FP64 buckets take 1)
+    int flush_path = 1;
 
     int init(const BucketShape &shape, int k_delay, double box_l, void *stream_or_null, int gj_group);
     void release();

@@ -182,6 +182,11 @@ hipError_t launch_window_prime(const DetDesc<T> *d, int ndesc, int np, int ktile
 template <typename T>
 hipError_t launch_flush_stream(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int kslots, int cur,
                                int has_next, int e0n, int kwn, hipStream_t s);
+// The same pass for FP32 determinants with both products on the bf16 matrix
+// cores at FP32 accuracy (operands split into three bf16 parts); ktile 32, 64
+// or 128.
+hipError_t launch_flush_stream_x6(const DetDesc<float> *d, int ndesc, int np, int ktile, int kp, int kslots, int cur,
+                                  int has_next, int e0n, int kwn, hipStream_t s);
 template <typename T>
 hipError_t launch_reset_state(const DetDesc<T> *d, const GjDesc *gj, double *drift, int ndesc, hipStream_t s);
 

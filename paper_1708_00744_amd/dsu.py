@@ -17,6 +17,7 @@ OK, EINVAL, ENOMEM, ESINGULAR, ESTATE, EDEVICE, EBUDGET = 0, -1, -2, -3, -4, -5,
 FP64, FP32_MIXED = 0, 1
 FLUSH_K_ACCEPTED, FLUSH_K_PROPOSED = 0, 1
 FLUSH_AUTO, FLUSH_VALU, FLUSH_MFMA = 0, 1, 2
+PATH_WINDOWS, PATH_STREAM, PATH_STREAM_X6 = 0, 1, 2
 PHASE_ROWS, PHASE_G, PHASE_DECIDE, PHASE_FLUSH, PHASE_RECOMPUTE = 0, 1, 2, 3, 4
 MAX_K = 256
 
@@ -321,8 +322,10 @@ class Batch:
     def use_graph(self, enable):
         _check(lib().dsu_batch_use_graph(self._h, int(bool(enable))))
 
-    def set_flush_path(self, streaming):
-        _check(lib().dsu_batch_set_flush_path(self._h, int(bool(streaming))))
+    def set_flush_path(self, path):
+        """0: four launches per window; 1 (or True): one-pass streaming flush;
+        2: streaming flush with split-bf16 products (FP32 batches)."""
+        _check(lib().dsu_batch_set_flush_path(self._h, int(path)))
 
     def set_delay(self, k_delay):
         _check(lib().dsu_batch_set_delay(self._h, int(k_delay)))

@@ -235,10 +235,11 @@ def test_bad_arguments():
     assert ex.value.code == dsu.ESINGULAR
 
 
-@pytest.mark.parametrize("K", [128, 64])
-def test_c4_shape_sampled(K):
+@pytest.mark.parametrize("K,path", [(128, dsu.PATH_STREAM), (64, dsu.PATH_STREAM), (128, dsu.PATH_STREAM_X6)])
+def test_c4_shape_sampled(K, path):
     """N = 4096, FP32, K = 128 (and 64), sigma = 0.0015 (acceptance 0.99): the
-    bench's launch configuration on two walkers.  Properties checked at full size:
+    bench's launch configuration on two walkers, with FP32 and with split-bf16
+    flush products.  Properties checked at full size:
     after a sweep the running log-determinant against a direct (LAPACK)
     calculation and the inverse residual on sampled rows; on walker 0 the
     first window's ratios and decisions against the oracle's Sherman-Morrison
@@ -246,6 +247,7 @@ def test_c4_shape_sampled(K):
     require_gpu()
     n, walkers, sigma = 4096, 2, 0.0015
     b, pos = make_batch(n, walkers, 1, K, dsu.FP32_MIXED, sigma, seed=1000)
+    b.set_flush_path(path)
     b.set_trace(1)
     b.sweep(1)
     st = b.stats()
