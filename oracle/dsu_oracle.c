@@ -496,3 +496,162 @@ int orc_walkers_moves(int nw, int n, double L, const uint64_t *seeds, const uint
                                          NULL);
     return threads;
 }
+
+/* ======================================================================== */
+/* Complex orbitals (twisted boundary conditions).  The same definitions in */
+/* complex arithmetic: no conjugation anywhere, transposes are plain.       */
+/* Complex arrays are interleaved (re, im), i.e. C99 double complex.        */
+/* ======================================================================== */
+#include <complex.h>
+
+typedef struct { int nx, ny, nz; double k2; } orc_zrep;
+
+static int orc_zrep_cmp(const void *pa, const void *pb)
+{
+    const orc_zrep *a = (const orc_zrep *)pa, *b = (const orc_zrep *)pb;
+    if (a->k2 != b->k2) return a->k2 < b->k2 ? -1 : 1;
+    if (a->nx != b->nx) return a->nx < b->nx ? -1 : 1;
+    if (a->ny != b->ny) return a->ny < b->ny ? -1 : 1;
+    return a->nz < b->nz ? -1 : (a->nz > b->nz);
+}
+
+/* Twisted plane waves phi_j(r) = exp(i (2 pi / L) (n_j + theta) . r): the n
+ * integer vectors n_j with the smallest |n + theta|^2, ties in lexicographic
+ * order of (nx, ny, nz).  A cube [-m, m]^3 holds every candidate once the n-th
+ * value is below (m - 1/2)^2 (a vector outside has some |n_a + theta_a| >= m - 1/2
+ * for |theta_a| <= 1/2).  out: n x 3. */
+int orc_zpw_kvectors(int n, const double theta[3], int *out)
+{
+    if (n <= 0) return -1;
+    for (int m = 2;; ++m) {
+        int side = 2 * m + 1;
+        orc_zrep *reps = (orc_zrep *)malloc(sizeof(orc_zrep) * side * side * side);
+        int cnt = 0;
+        for (int x = -m; x <= m; ++x)
+            for (int y = -m; y <= m; ++y)
+                for (int z = -m; z <= m; ++z) {
+                    double a = x + theta[0], b = y + theta[1], c = z + theta[2];
+                    reps[cnt].nx = x; reps[cnt].ny = y; reps[cnt].nz = z;
+                    reps[cnt].k2 = a * a + b * b + c * c;
+                    ++cnt;
+                }
+        qsort(reps, cnt, sizeof(orc_zrep), orc_zrep_cmp);
+        if (n <= cnt && reps[n - 1].k2 < (m - 0.5) * (m - 0.5)) {
+            for (int j = 0; j < n; ++j) { out[3 * j] = reps[j].nx; out[3 * j + 1] = reps[j].ny; out[3 * j + 2] = reps[j].nz; }
+            free(reps);
+            return 0;
+        }
+        free(reps);
+    }
+}
+
+void orc_zpw_row(int n, const int *kv, const double theta[3], double L, const double r[3], double complex *row)
+{
+    double g = 2.0 * ORC_PI / L;
+    for (int j = 0; j < n; ++j) {
+        double ph = g * (((kv[3 * j] + theta[0]) * r[0] + (kv[3 * j + 1] + theta[1]) * r[1]) + (kv[3 * j + 2] + theta[2]) * r[2]);
+        row[j] = cos(ph) + I * sin(ph);
+    }
+}
+
+/* LU with partial pivoting by modulus (lowest row on ties), as orc_lu.
+ * logabs = log|det|, phase = arg(det) in (-pi, pi]. */
+int orc_zlu(int n, double complex *a, int *piv, double *logabs, double *phase)
+{
+    double la = 0.0, ph = 0.0;
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = cabs(a[(size_t)k * n + k]);
+        for (int i = k + 1; i < n; ++i) {
+            double v = cabs(a[(size_t)i * n + k]);
+            if (v > best) { best = v; p = i; }
+        }
+        piv[k] = p;
+        if (best == 0.0) return -3;
+        if (p != k) {
+            for (int j = 0; j < n; ++j) {
+                double complex t = a[(size_t)k * n + j];
+                a[(size_t)k * n + j] = a[(size_t)p * n + j];
+                a[(size_t)p * n + j] = t;
+            }
+            ph += ORC_PI;
+        }
+        double complex d = a[(size_t)k * n + k];
+        la += log(cabs(d));
+        ph += carg(d);
+        for (int i = k + 1; i < n; ++i) {
+            double complex l = a[(size_t)i * n + k] / d;
+            a[(size_t)i * n + k] = l;
+            for (int j = k + 1; j < n; ++j) a[(size_t)i * n + j] -= l * a[(size_t)k * n + j];
+        }
+    }
+    ph = fmod(ph, 2.0 * ORC_PI);
+    if (ph > ORC_PI) ph -= 2.0 * ORC_PI;
+    if (ph <= -ORC_PI) ph += 2.0 * ORC_PI;
+    if (logabs) *logabs = la;
+    if (phase) *phase = ph;
+    return 0;
+}
+
+int orc_zinverse(int n, const double complex *a, double complex *ainv, double *logabs, double *phase)
+{
+    double complex *w = (double complex *)malloc(sizeof(double complex) * (size_t)n * n);
+    double complex *col = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    int *piv = (int *)malloc(sizeof(int) * (size_t)n);
+    memcpy(w, a, sizeof(double complex) * (size_t)n * n);
+    int rc = orc_zlu(n, w, piv, logabs, phase);
+    if (rc == 0 && ainv) {
+        for (int c = 0; c < n; ++c) {
+            for (int i = 0; i < n; ++i) col[i] = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < n; ++k) { double complex t = col[k]; col[k] = col[piv[k]]; col[piv[k]] = t; }
+            for (int i = 0; i < n; ++i)
+                for (int k = 0; k < i; ++k) col[i] -= w[(size_t)i * n + k] * col[k];
+            for (int i = n - 1; i >= 0; --i) {
+                for (int k = i + 1; k < n; ++k) col[i] -= w[(size_t)i * n + k] * col[k];
+                col[i] /= w[(size_t)i * n + i];
+            }
+            for (int i = 0; i < n; ++i) ainv[(size_t)i * n + c] = col[i];
+        }
+    }
+    free(w); free(col); free(piv);
+    return rc;
+}
+
+/* Eq. (1) in complex arithmetic: R = phi . Ainv[:, e]. */
+double complex orc_zsm_ratio(int n, const double complex *ainv, int e, const double complex *phi)
+{
+    double complex r = 0.0;
+    for (int j = 0; j < n; ++j) r += phi[j] * ainv[(size_t)j * n + e];
+    return r;
+}
+
+/* Eq. (2) in complex arithmetic (as orc_sm_accept); work holds 2n values. */
+void orc_zsm_accept(int n, double complex *ainv, double complex *a, int e, const double complex *phi, double complex r,
+                    double complex *work)
+{
+    double complex *w = work, *c = work + n;
+    for (int k = 0; k < n; ++k) {
+        double complex s = 0.0;
+        for (int j = 0; j < n; ++j) s += phi[j] * ainv[(size_t)j * n + k];
+        w[k] = s;
+    }
+    w[e] -= 1.0;
+    for (int i = 0; i < n; ++i) c[i] = ainv[(size_t)i * n + e];
+    for (int i = 0; i < n; ++i) {
+        double complex f = c[i] / r;
+        for (int k = 0; k < n; ++k) ainv[(size_t)i * n + k] -= f * w[k];
+    }
+    if (a) memcpy(a + (size_t)e * n, phi, sizeof(double complex) * (size_t)n);
+}
+
+/* ctypes cannot return a C complex: ratio through an out-parameter. */
+void orc_zsm_ratio_out(int n, const double complex *ainv, int e, const double complex *phi, double complex *out)
+{
+    *out = orc_zsm_ratio(n, ainv, e, phi);
+}
+
+void orc_zsm_accept_r(int n, double complex *ainv, double complex *a, int e, const double complex *phi,
+                      const double complex *r, double complex *work)
+{
+    orc_zsm_accept(n, ainv, a, e, phi, *r, work);
+}

@@ -62,6 +62,17 @@ def _declare(L):
     L.orc_sm_ratio_grad.restype = C.c_double
     L.orc_sm_accept.argtypes = [C.c_int, _dp, C.c_void_p, C.c_int, _dp, C.c_double, _dp]
     L.orc_sm_accept.restype = None
+    _zp = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
+    L.orc_zpw_kvectors.argtypes = [C.c_int, _dp, _ip]
+    L.orc_zpw_kvectors.restype = C.c_int
+    L.orc_zpw_row.argtypes = [C.c_int, _ip, _dp, C.c_double, _dp, _zp]
+    L.orc_zpw_row.restype = None
+    L.orc_zinverse.argtypes = [C.c_int, _zp, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.orc_zinverse.restype = C.c_int
+    L.orc_zsm_ratio_out.argtypes = [C.c_int, _zp, C.c_int, _zp, _zp]
+    L.orc_zsm_ratio_out.restype = None
+    L.orc_zsm_accept_r.argtypes = [C.c_int, _zp, C.c_void_p, C.c_int, _zp, _zp, _zp]
+    L.orc_zsm_accept_r.restype = None
     vp = C.c_void_p
     L.orc_walker_run.argtypes = [C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_int, C.c_double,
                                  C.c_int, C.c_int, C.c_int, _dp,
@@ -253,3 +264,65 @@ def walkers_moves(n, L, seeds, walker_ids, sigma, sweep, e_first, nmoves, pos, a
                                       np.ascontiguousarray(walker_ids, np.uint64), float(sigma), int(sweep),
                                       int(e_first), int(nmoves), int(bool(force_accept)), pos, a, ainv, nacc)
     return nacc, threads
+
+
+# ------------------------------------------------------------- complex orbitals
+def zpw_kvectors(n, theta):
+    """(n, 3) integer vectors of the twisted plane waves, |n + theta|^2 ascending."""
+    out = np.zeros((n, 3), np.int32)
+    rc = lib().orc_zpw_kvectors(n, np.ascontiguousarray(theta, np.float64), out)
+    if rc != 0:
+        raise ValueError("bad n")
+    return out
+
+
+def zpw_row(kv, theta, L, r):
+    n = kv.shape[0]
+    row = np.zeros(n, np.complex128)
+    lib().orc_zpw_row(n, np.ascontiguousarray(kv, np.int32), np.ascontiguousarray(theta, np.float64), float(L),
+                      np.ascontiguousarray(r, np.float64), row)
+    return row
+
+
+def zpw_matrix(kv, theta, L, pos):
+    return np.stack([zpw_row(kv, theta, L, p) for p in pos])
+
+
+def zinverse(a):
+    """(Ainv, log|det|, arg det); raises on an exactly singular matrix."""
+    a = np.ascontiguousarray(a, np.complex128)
+    n = a.shape[0]
+    inv = np.zeros((n, n), np.complex128)
+    la, ph = C.c_double(), C.c_double()
+    rc = lib().orc_zinverse(n, a, inv.ctypes.data_as(C.c_void_p), C.byref(la), C.byref(ph))
+    if rc != 0:
+        raise np.linalg.LinAlgError("singular")
+    return inv, la.value, ph.value
+
+
+def zslogdet(a):
+    """(log|det|, arg det) by the oracle's LU."""
+    a = np.ascontiguousarray(a, np.complex128)
+    la, ph = C.c_double(), C.c_double()
+    rc = lib().orc_zinverse(a.shape[0], a, None, C.byref(la), C.byref(ph))
+    if rc != 0:
+        return -np.inf, 0.0
+    return la.value, ph.value
+
+
+def zsm_ratio(ainv, e, phi):
+    out = np.zeros(1, np.complex128)
+    lib().orc_zsm_ratio_out(ainv.shape[0], np.ascontiguousarray(ainv), int(e), np.ascontiguousarray(phi, np.complex128),
+                            out)
+    return complex(out[0])
+
+
+def zsm_accept(ainv, a, e, phi, r):
+    """In place: Ainv <- eq. (2) update, A[e,:] <- phi (if a is not None)."""
+    n = ainv.shape[0]
+    assert ainv.flags.c_contiguous and ainv.dtype == np.complex128
+    if a is not None:
+        assert a.flags.c_contiguous and a.dtype == np.complex128
+    work = np.zeros(2 * n, np.complex128)
+    lib().orc_zsm_accept_r(n, ainv, None if a is None else a.ctypes.data_as(C.c_void_p), int(e),
+                           np.ascontiguousarray(phi, np.complex128), np.array([r], np.complex128), work)

@@ -409,3 +409,103 @@ def test_ratio_gradient_two_electron_closed_form():
         r, grad = oracle.sm_ratio_grad(ainv, 0, oracle.pw_row(kv, L, rp), oracle.pw_row_grad(kv, L, rp))
         assert abs(r - (math.cos(g * nv @ r2) - math.cos(ph)) / det) < 1e-13
         np.testing.assert_allclose(grad, g * nv * math.sin(ph) / det, rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------------- complex orbitals (twists)
+def _fc_det(m):
+    """Exact determinant of a matrix of Gaussian integers, as a pair of
+    Fractions (re, im), by elimination with complex-rational pivots."""
+    m = [[(Fraction(int(z.real)), Fraction(int(z.imag))) for z in r] for r in m]
+    n = len(m)
+
+    def mul(a, b):
+        return (a[0] * b[0] - a[1] * b[1], a[0] * b[1] + a[1] * b[0])
+
+    def div(a, b):
+        d = b[0] * b[0] + b[1] * b[1]
+        return ((a[0] * b[0] + a[1] * b[1]) / d, (a[1] * b[0] - a[0] * b[1]) / d)
+
+    det = (Fraction(1), Fraction(0))
+    for k in range(n):
+        p = next((i for i in range(k, n) if m[i][k] != (0, 0)), None)
+        if p is None:
+            return (Fraction(0), Fraction(0))
+        if p != k:
+            m[k], m[p] = m[p], m[k]
+            det = (-det[0], -det[1])
+        det = mul(det, m[k][k])
+        for i in range(k + 1, n):
+            f = div(m[i][k], m[k][k])
+            for j in range(k, n):
+                t = mul(f, m[k][j])
+                m[i][j] = (m[i][j][0] - t[0], m[i][j][1] - t[1])
+    return det
+
+
+def _gauss_int_matrix(seed, n):
+    rng = np.random.default_rng(seed)
+    while True:
+        a = rng.integers(-3, 4, (n, n)) + 1j * rng.integers(-3, 4, (n, n)) + 4 * np.eye(n)
+        if _fc_det(a) != (0, 0):
+            return a.astype(np.complex128)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 48])
+def test_zinverse_matches_lapack(n):
+    rng = np.random.default_rng(40 + n)
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    inv, la, ph = oracle.zinverse(a)
+    s, l = np.linalg.slogdet(a)
+    np.testing.assert_allclose(inv, np.linalg.inv(a), rtol=1e-9, atol=1e-11)
+    assert abs(la - l) < 1e-10 * max(1, abs(l))
+    assert abs(np.exp(1j * ph) - s) < 1e-10
+
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_zsm_exact_gaussian_integer_chain(n):
+    """Each complex ratio equals det(A_new)/det(A_old) in exact arithmetic;
+    a conjugated operand or a transposed inverse fails this."""
+    a = _gauss_int_matrix(90 + n, n)
+    ainv, _, _ = oracle.zinverse(a)
+    rng = np.random.default_rng(91 + n)
+    cur = a.copy()
+    for step in range(6):
+        e = int(rng.integers(0, n))
+        row = (rng.integers(-3, 4, n) + 1j * rng.integers(-3, 4, n)).astype(np.complex128)
+        new = cur.copy(); new[e] = row
+        d0, d1 = _fc_det(cur), _fc_det(new)
+        if d1 == (0, 0):
+            continue
+        den = d0[0] ** 2 + d0[1] ** 2
+        exact = complex(float((d1[0] * d0[0] + d1[1] * d0[1]) / den), float((d1[1] * d0[0] - d1[0] * d0[1]) / den))
+        r = oracle.zsm_ratio(ainv, e, row)
+        assert abs(r - exact) <= 1e-12 * max(1.0, abs(exact))
+        if n > 1:
+            assert abs(oracle.zsm_ratio(np.ascontiguousarray(ainv.T), e, row) - exact) > 1e-9 or \
+                np.allclose(ainv, ainv.T)
+        oracle.zsm_accept(ainv, cur, e, row, r)
+    np.testing.assert_allclose(ainv, np.linalg.inv(cur), rtol=1e-9, atol=1e-12)
+
+
+def test_twisted_plane_waves():
+    theta = np.array([0.3, -0.25, 0.1])
+    n, L, M = 33, 4.0, 9
+    kv = oracle.zpw_kvectors(n, theta)
+    # the n vectors with the smallest |n + theta|^2, by brute force over a larger cube
+    g = np.arange(-6, 7)
+    cube = np.array(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1).T
+    k2 = ((cube + theta) ** 2).sum(1)
+    order = np.lexsort((cube[:, 2], cube[:, 1], cube[:, 0], k2))
+    np.testing.assert_array_equal(kv, cube[order[:n]])
+    # twisted boundary condition: phi(r + L e_a) = exp(2 pi i theta_a) phi(r)
+    r = np.array([0.7, 1.9, 3.1])
+    row = oracle.zpw_row(kv, theta, L, r)
+    for a in range(3):
+        sh = np.zeros(3); sh[a] = L
+        np.testing.assert_allclose(oracle.zpw_row(kv, theta, L, r + sh), np.exp(2j * np.pi * theta[a]) * row,
+                                   atol=1e-12)
+    # closed form at one point, orthonormality on an M^3 grid (the twist cancels in phi_j^* phi_k)
+    np.testing.assert_allclose(row, np.exp(2j * np.pi / L * ((kv + theta) @ r)), atol=1e-13)
+    pts = (np.array(np.meshgrid(np.arange(M), np.arange(M), np.arange(M), indexing="ij")).reshape(3, -1).T + 0.3) * (L / M)
+    A = oracle.zpw_matrix(kv, theta, L, pts)
+    np.testing.assert_allclose(A.conj().T @ A / M**3, np.eye(n), atol=1e-12)
