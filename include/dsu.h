@@ -169,6 +169,49 @@ int dsu_walker_pending(dsu_walker *w, int32_t *k_out);
 int dsu_walker_set_flush_kernel(dsu_walker *w, int32_t mode);
 
 /* ======================================================================
+ * Single walker with complex orbitals (twisted boundary conditions).
+ * The same look-ahead (eq. (3)), bordering and en-bloc update (eq. (4)) in
+ * FP64 complex arithmetic: the determinant lemma and the Woodbury identity
+ * hold over the complex field with plain transposes.  Complex arrays are
+ * interleaved (re, im) doubles, row-major, row i = electron i.  The
+ * Metropolis weight of a move is |R|^2; the walker tracks log|det A| and
+ * arg det A in (-pi, pi].
+ * ====================================================================== */
+typedef struct dsu_zwalker dsu_zwalker;
+
+/* Create from the complex Slater matrix (2*n*n doubles).  Computes A^{-1},
+ * log|det A| and arg det A in FP64 complex on the device (Gauss-Jordan with
+ * partial pivoting by modulus).  n in [1, 16384], k_delay in [1, DSU_MAX_K],
+ * policy as for dsu_walker_create.  DSU_ESINGULAR if A is singular to working
+ * precision (a pivot at or below n * 2^-52 times the largest pivot). */
+int dsu_zwalker_create(int32_t n, int32_t k_delay, int32_t policy, const double *slater_host, void *hip_stream,
+                       dsu_zwalker **out);
+int dsu_zwalker_destroy(dsu_zwalker *w);
+/* Complex ratio for replacing row `electron` by phi_host (2*n doubles):
+ * eq. (3) look-ahead; ratio_out receives (re, im).  The proposal stays
+ * pending until dsu_zaccept / dsu_zreject; an electron holding a pending
+ * accepted move flushes the pending moves first.  Synchronises. */
+int dsu_zpropose_ratio(dsu_zwalker *w, int32_t electron, const double *phi_host, double *ratio_out);
+/* Accept the pending proposal (bordering; flush by the walker's policy).
+ * DSU_ESTATE without a pending proposal; DSU_ESINGULAR (walker unchanged) if
+ * |R| <= 1e-12 or R is not finite. */
+int dsu_zaccept(dsu_zwalker *w);
+int dsu_zreject(dsu_zwalker *w);
+/* Apply the pending moves now (eq. (4)). */
+int dsu_zflush(dsu_zwalker *w);
+/* Fresh inverse from the walker's current A (or from slater_host_or_null,
+ * which then replaces A); log|det|, arg det and running-minus-fresh log|det|
+ * out (each may be NULL).  Clears pending moves. */
+int dsu_zrecompute_inverse(dsu_zwalker *w, const double *slater_host_or_null, double *logabs_out, double *phase_out,
+                           double *drift_out);
+/* A^{-1} (2*n*n doubles, row-major) after flushing pending moves. */
+int dsu_zget_inverse(dsu_zwalker *w, double *out_host);
+/* Running log|det A| and arg det A (sum of log|R| and arg R of accepted moves
+ * since the last fresh inverse). */
+int dsu_zget_logdet(dsu_zwalker *w, double *logabs, double *phase);
+int dsu_zwalker_pending(dsu_zwalker *w, int32_t *k_out);
+
+/* ======================================================================
  * Batched form: many walker determinants of one size n, proposals drawn on
  * the device, lock-step windows of K proposals per determinant.
  * ====================================================================== */

@@ -101,11 +101,6 @@ template <int KP> struct X6Cfg {
     static_assert(SPT >= 1 && SPT * 4 * kThreads == KP * CW, "staging split");
 };
 
-template <int N> struct BfVec;
-template <> struct BfVec<1> { typedef unsigned short type; };
-template <> struct BfVec<2> { typedef unsigned type; };
-template <> struct BfVec<4> { typedef u32x2 type; };
-
 // Split one chunk's staged V (SPT slots x 4 columns per thread) and U into
 // the planes of buffer `buf`.
 template <int KP>
@@ -113,7 +108,6 @@ __device__ __forceinline__ void x6_put(__bf16 *buf, const f32x4 (&sv)[X6Cfg<KP>:
                                        const f32x4 (&su)[X6Cfg<KP>::SPT], bool has_next, int cq, int sg, int pq) {
     typedef X6Cfg<KP> C;
     constexpr int SPT = C::SPT;
-    typedef typename BfVec<SPT>::type sv_t;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         unsigned h[2], m[2], l[2];  // SPT <= 4 slots, packed in pairs

@@ -70,6 +70,16 @@ SIGNATURES = {
     "dsu_get_logdet": (C.c_int, [_vp, _pd, _pi32]),
     "dsu_walker_pending": (C.c_int, [_vp, _pi32]),
     "dsu_walker_set_flush_kernel": (C.c_int, [_vp, _i32]),
+    "dsu_zwalker_create": (C.c_int, [_i32, _i32, _i32, _pd, _vp, _pvp]),
+    "dsu_zwalker_destroy": (C.c_int, [_vp]),
+    "dsu_zpropose_ratio": (C.c_int, [_vp, _i32, _pd, _pd]),
+    "dsu_zaccept": (C.c_int, [_vp]),
+    "dsu_zreject": (C.c_int, [_vp]),
+    "dsu_zflush": (C.c_int, [_vp]),
+    "dsu_zrecompute_inverse": (C.c_int, [_vp, _pd, _pd, _pd, _pd]),
+    "dsu_zget_inverse": (C.c_int, [_vp, _pd]),
+    "dsu_zget_logdet": (C.c_int, [_vp, _pd, _pd]),
+    "dsu_zwalker_pending": (C.c_int, [_vp, _pi32]),
     "dsu_batch_create": (C.c_int, [_i32, _i32, _i32, _i32, _i32, _dbl, _pu64, _pu64, _pd, _pd, _i32, _vp, _pvp]),
     "dsu_batch_destroy": (C.c_int, [_vp]),
     "dsu_batch_sweep": (C.c_int, [_vp, _i32, _i32]),
@@ -236,6 +246,80 @@ class Walker:
 
     def set_flush_kernel(self, mode):
         _check(lib().dsu_walker_set_flush_kernel(self._h, mode))
+
+
+def _c128(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _zp(a):
+    """Pointer to an interleaved (re, im) complex128 array as double*."""
+    return a.ctypes.data_as(_pd)
+
+
+class ZWalker:
+    """Host-driven single walker with complex orbitals (dsu_zwalker_*)."""
+
+    def __init__(self, slater, k_delay, policy=FLUSH_K_ACCEPTED, stream=None):
+        a = _c128(slater)
+        n = a.shape[0]
+        if a.shape != (n, n):
+            raise ValueError("slater must be square")
+        self.n, self.k_delay, self.policy = n, k_delay, policy
+        h = C.c_void_p()
+        _check(lib().dsu_zwalker_create(n, k_delay, policy, _zp(a), _stream_ptr(stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dsu_zwalker_destroy(self._h)
+        self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def propose(self, electron, row):
+        r = np.zeros(2)
+        _check(lib().dsu_zpropose_ratio(self._h, int(electron), _zp(_c128(row, (self.n,))), _dp(r)))
+        return complex(r[0], r[1])
+
+    def accept(self):
+        _check(lib().dsu_zaccept(self._h))
+
+    def reject(self):
+        _check(lib().dsu_zreject(self._h))
+
+    def flush(self):
+        _check(lib().dsu_zflush(self._h))
+
+    def recompute(self, slater=None):
+        la, ph, dr = C.c_double(), C.c_double(), C.c_double()
+        a = None if slater is None else _zp(_c128(slater, (self.n, self.n)))
+        _check(lib().dsu_zrecompute_inverse(self._h, a, C.byref(la), C.byref(ph), C.byref(dr)))
+        return la.value, ph.value, dr.value
+
+    def inverse(self):
+        out = np.empty((self.n, self.n), np.complex128)
+        _check(lib().dsu_zget_inverse(self._h, _zp(out)))
+        return out
+
+    def logdet(self):
+        la, ph = C.c_double(), C.c_double()
+        _check(lib().dsu_zget_logdet(self._h, C.byref(la), C.byref(ph)))
+        return la.value, ph.value
+
+    def pending(self):
+        k = C.c_int32()
+        _check(lib().dsu_zwalker_pending(self._h, C.byref(k)))
+        return k.value
 
 
 class Batch:
