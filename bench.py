@@ -291,6 +291,54 @@ def drift_single_walker(n=1024, moves=1024, tau=0.002):
     return res
 
 
+def complex_single_walker(n=1024, sigma=0.02, sweeps=1):
+    """Complex orbitals (twisted plane waves, FP64 complex), host-driven through
+    the C ABI: one propose/accept call per move.  The caller evaluates the
+    orbital rows with numpy (a sweep's proposals do not depend on its
+    decisions, so they are evaluated before the timed loop).  Also the time of
+    one fresh inverse (Gauss-Jordan, log|det| and phase)."""
+    from paper_1708_00744_amd import dsu, inputs
+    theta = np.array([0.31, -0.17, 0.42])
+    g = np.arange(-12, 13)
+    cube = np.array(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1).T
+    k2 = ((cube + theta) ** 2).sum(1)
+    kv = cube[np.lexsort((cube[:, 2], cube[:, 1], cube[:, 0], k2))[:n]] + theta
+
+    def rows(p):
+        return np.exp(2j * np.pi / BOX_L * (p @ kv.T))
+
+    pos0 = inputs.positions(2, 0, n, BOX_L)
+    a0 = rows(pos0)
+    res = {"n": n, "sigma": sigma}
+    for K in (1, 16, 64):
+        pos = pos0.copy()
+        gs = inputs.normals(3, (sweeps, n, 3))
+        us = inputs.uniforms(4, sweeps * n)
+        with dsu.ZWalker(a0, K, policy=dsu.FLUSH_K_ACCEPTED) as w:
+            t_rec = time.perf_counter()
+            w.recompute()
+            t_rec = time.perf_counter() - t_rec
+            t0 = time.perf_counter()
+            acc = 0
+            for s in range(sweeps):
+                prop = pos + sigma * gs[s]
+                rws = rows(prop)
+                for e in range(n):
+                    r = w.propose(e, rws[e])
+                    if us[s * n + e] < abs(r) ** 2:
+                        w.accept()
+                        pos[e] = prop[e]
+                        acc += 1
+                    else:
+                        w.reject()
+            w.flush()
+            dt = time.perf_counter() - t0
+        res[f"host_driven_K{K}_moves_per_s"] = n * sweeps / dt
+        res[f"K{K}_acceptance"] = acc / (n * sweeps)
+        res["recompute_s"] = t_rec
+    return res
+
+
 def serving(cache, count=40, seed=7):
     from paper_1708_00744_amd import dsu, inputs
     sizes, accs, seeds = inputs.serving_mix(seed, count)
@@ -345,6 +393,12 @@ def cpu_baseline(n=4096, sigma=0.002, target_s=15.0):
                       f"per walker, set-up by LAPACK inverse not timed)"}
 
 
+EXTRA_LEGS = {
+    "complex_single_walker_n1024": lambda: complex_single_walker(),
+    "fp64_drift_walker_n1024": lambda: drift_single_walker(),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,6 +406,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extra", default=None, choices=sorted(EXTRA_LEGS),
+                    help="run one single-walker leg of the extras alone and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -376,6 +432,9 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         return 1
     torch.cuda.set_device(0)
+    if args.extra:
+        print(json.dumps({args.extra: EXTRA_LEGS[args.extra]()}))
+        return 0
     from paper_1708_00744_amd import dsu, tune
     dsu.lib()
     cache = tune.load_cache()
@@ -397,6 +456,8 @@ def main():
         extras["fp64_batched_n2048"] = batched_at(2048, 64, cache, precision=dsu.FP64)
         log("FP64 single walker N=1024")
         extras["fp64_single_walker_n1024"] = fp64_single_walker(cache)
+        log("complex-orbital walker N=1024")
+        extras["complex_single_walker_n1024"] = complex_single_walker()
         log("FP64 drift-diffusion walker N=1024")
         extras["fp64_drift_walker_n1024"] = drift_single_walker()
         log("serving")

@@ -43,8 +43,7 @@ struct ZWalkerDev {
     double *ratio_host;// mapped pinned: R (re, im)
     int *idx;          // kp pending electrons
     unsigned *counter; // blocks finished (last-block reduction)
-    zc *y;             // np x kp: flush scratch Y, then W
-    zc *w;             // np x kp
+    zc *w;             // np x (kp + 1): flush scratch W
     zc *fcol;          // np: Gauss-Jordan multipliers
     int *piv;          // np: Gauss-Jordan row interchanges
     double *stat;      // log|det|, arg det, largest pivot modulus
@@ -205,10 +204,43 @@ static hipError_t zgemm(const zc *A, int lda, const zc *B, int ldb, zc *C, int l
     return hipGetLastError();
 }
 
-// Y[e_j][j] -= 1 for the k pending slots.
-__global__ void k_zsub_e(zc *y, int ldy, const int *idx, int k) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < k) y[(size_t)idx[j] * ldy + j].x -= 1.0;
+// Flush, first half, one wave per row of BT (4 rows per workgroup): the
+// row's look-ahead products y_j = BT[i] . U[j] (16 slots at a time, lanes
+// striding the columns, then a wave reduction), y_j -= 1 where e_j = i, and
+// the row of W = (Y - E) C^{-T}: w_j = sum_l y_l Cinv[j][l].
+__global__ __launch_bounds__(kThreads) void k_zflush_w(ZWalkerDev w, int np, int k) {
+    __shared__ zc s_y[4][DSU_KMAX_LDS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + wave;  // np is a multiple of 64: every wave has a row
+    const zc *bt = w.bt + (size_t)i * np;
+    for (int j0 = 0; j0 < k; j0 += 16) {
+        const int nj = k - j0 < 16 ? k - j0 : 16;
+        zc acc[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = make_double2(0.0, 0.0);
+        for (int c = lane; c < np; c += 64) {
+            const zc b = bt[c];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (j < nj) acc[j] = zfma(b, w.u[(size_t)(j0 + j) * np + c], acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            zc v = acc[j];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                v.x += __shfl_xor(v.x, o, 64);
+                v.y += __shfl_xor(v.y, o, 64);
+            }
+            if (lane == 0 && j < nj) s_y[wave][j0 + j] = make_double2(v.x - (w.idx[j0 + j] == i ? 1.0 : 0.0), v.y);
+        }
+    }
+    __syncthreads();
+    for (int j = lane; j < k; j += 64) {
+        zc s = make_double2(0.0, 0.0);
+        for (int l = 0; l < k; ++l) s = zfma(s_y[wave][l], w.cinv[(size_t)j * w.ldc + l], s);
+        w.w[(size_t)i * w.ldc + j] = s;
+    }
 }
 
 // BT[i][j] = A[j][i] for i, j < n (zero elsewhere up to np).
@@ -346,7 +378,7 @@ static double wrap_phase(double p) {
 static void zwalker_free(dsu_zwalker *w) {
     for (void *p : {(void *)w->wd.bt, (void *)w->wd.u, (void *)w->wd.vg, (void *)w->wd.a, (void *)w->wd.phi,
                     (void *)w->wd.cinv, (void *)w->wd.dots, (void *)w->wd.t, (void *)w->wd.ratio, (void *)w->wd.idx,
-                    (void *)w->wd.counter, (void *)w->wd.y, (void *)w->wd.w, (void *)w->wd.fcol, (void *)w->wd.piv,
+                    (void *)w->wd.counter, (void *)w->wd.w, (void *)w->wd.fcol, (void *)w->wd.piv,
                     (void *)w->wd.stat, (void *)w->wd.status, (void *)w->inv_tmp})
         dfree(p);
     if (w->ratio_h) (void)hipHostFree(w->ratio_h);
@@ -382,12 +414,10 @@ static int zwalker_recompute(dsu_zwalker *w, double *logabs, double *phase) {
 static int zwalker_flush(dsu_zwalker *w) {
     const int k = w->k, np = w->np, kp = w->kp;
     if (k > 0) {
-        zc *bt = w->wd.bt;
-        HIPCHK((zgemm<true, false>(bt, np, w->wd.u, np, w->wd.y, kp, np, k, np, w->stream)));   // Y = BT U^T
-        hipLaunchKernelGGL(k_zsub_e, dim3(1), dim3(256), 0, w->stream, w->wd.y, kp, (const int *)w->wd.idx, k);
+        // W = (BT U^T - E) C^{-T}, row by row; then BT -= W Vg
+        hipLaunchKernelGGL(k_zflush_w, dim3(np / 4), dim3(kThreads), 0, w->stream, w->wd, np, k);
         HIPCHK(hipGetLastError());
-        HIPCHK((zgemm<true, false>(w->wd.y, kp, w->wd.cinv, w->wd.ldc, w->wd.w, kp, np, k, k, w->stream)));  // W = Y C^-T
-        HIPCHK((zgemm<false, true>(w->wd.w, kp, w->wd.vg, np, bt, np, np, np, k, w->stream)));   // BT -= W Vg
+        HIPCHK((zgemm<false, true>(w->wd.w, w->wd.ldc, w->wd.vg, np, w->wd.bt, np, np, np, k, w->stream)));
     }
     w->k = 0;
     w->slots = 0;
@@ -432,8 +462,7 @@ extern "C" int dsu_zwalker_create(int32_t n, int32_t k_delay, int32_t policy, co
     TRY(dalloc(&w->wd.ratio, 1));
     TRY(dalloc(&w->wd.idx, kp));
     TRY(dalloc(&w->wd.counter, 1));
-    TRY(dalloc(&w->wd.y, np * kp));
-    TRY(dalloc(&w->wd.w, np * kp));
+    TRY(dalloc(&w->wd.w, np * (kp + 1)));
     TRY(dalloc(&w->wd.fcol, np));
     TRY(dalloc(&w->wd.piv, np));
     TRY(dalloc(&w->wd.stat, 3));
