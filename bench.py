@@ -104,7 +104,20 @@ def headline(args, cache):
     b.sweep(args.warmup)
     b.sync()
     b.set_timing(True)
-    dt = time_sweeps(b, args.steps, 0)
+    # timed region: the K sweeps, each followed by a wait so that its own
+    # duration is known (median and spread across the K sweeps)
+    import torch
+    b.sync()
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        b.sweep(1)
+        b.sync()
+        per.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
     st = b.stats()
     cnt, ms = b.kernel_time(dsu.PHASE_FLUSH)
     phases = {name: b.kernel_time(p) for name, p in (("rows", dsu.PHASE_ROWS), ("lookahead_G", dsu.PHASE_G),
@@ -131,12 +144,16 @@ def headline(args, cache):
     roof["launches"] = cnt
     roof["flops_per_launch"] = flops
     roof["bytes_per_launch"] = bytes_
+    per_ms = sorted(1e3 * x for x in per)
     out = {
         "moves_per_s": moves / dt, "ms_per_step": 1e3 * dt / args.steps, "K": K, "sigma": sigma,
+        "sweep_ms": {"median": per_ms[len(per_ms) // 2], "min": per_ms[0], "max": per_ms[-1]},
+        "accepted_moves_per_s": None,
         "acceptance": acc, "setup_s": setup_s,
         "phase_ms_per_sweep": {k: v[1] / args.steps for k, v in phases.items()},
         "roofline": roof, "batch": b,
     }
+    out["accepted_moves_per_s"] = out["moves_per_s"] * acc
     return out
 
 
