@@ -407,7 +407,53 @@ def cpu_baseline(n=4096, sigma=0.002, target_s=15.0):
     dt = time.perf_counter() - t0
     return {"value": walkers * m / dt, "unit": "moves/s", "cores": int(used), "kind": "oracle",
             "sample": f"{walkers} walkers x {m} moves of sweep 0 at N={n} (FP64 Sherman-Morrison, one OpenMP thread "
-                      f"per walker, set-up by LAPACK inverse not timed)"}
+                      f"per walker, set-up by LAPACK inverse not timed)",
+            "walker_forms": cpu_baseline_walkers()}
+
+
+def cpu_baseline_walkers(n=1024, moves=100):
+    """The oracle on the two host-driven walker workloads of the extras (one
+    thread, first `moves` moves from a fresh inverse, set-up not timed)."""
+    import oracle
+    from paper_1708_00744_amd import inputs
+    out = {}
+    # drift-diffusion: drift at the present position, ratio and gradient at the proposal, Sherman-Morrison
+    kv = oracle.pw_kvectors(n)
+    pos = inputs.positions(2, 0, n, BOX_L)
+    a = oracle.pw_matrix(kv, BOX_L, pos)
+    ainv, _, _ = oracle.inverse(a)
+    chi, us, tau = inputs.normals(5, (moves, 3)), inputs.uniforms(6, moves), 0.002
+    t0 = time.perf_counter()
+    for m in range(moves):
+        e = m % n
+        _, v_old = oracle.sm_ratio_grad(ainv, e, a[e], oracle.pw_row_grad(kv, BOX_L, pos[e]))
+        rp = pos[e] + tau * v_old + np.sqrt(tau) * chi[m]
+        row = oracle.pw_row(kv, BOX_L, rp)
+        r, g = oracle.sm_ratio_grad(ainv, e, row, oracle.pw_row_grad(kv, BOX_L, rp))
+        log_g = (np.sum((rp - pos[e] - tau * v_old) ** 2) - np.sum((pos[e] - rp - tau * g / r) ** 2)) / (2 * tau)
+        if us[m] < r * r * np.exp(log_g):
+            oracle.sm_accept(ainv, a, e, row, r)
+            pos[e] = rp
+    out["fp64_drift_walker_n1024"] = {"moves_per_s": moves / (time.perf_counter() - t0), "cores": 1,
+                                      "sample": f"{moves} drift-diffusion moves at N={n}"}
+    # complex orbitals: twisted plane waves, complex Sherman-Morrison
+    theta = np.array([0.31, -0.17, 0.42])
+    kz = oracle.zpw_kvectors(n, theta)
+    pos = inputs.positions(2, 0, n, BOX_L)
+    az = oracle.zpw_matrix(kz, theta, BOX_L, pos)
+    azinv, _, _ = oracle.zinverse(az)
+    gs, us = inputs.normals(3, (1, n, 3))[0], inputs.uniforms(4, n)
+    t0 = time.perf_counter()
+    for e in range(moves):
+        rt = pos[e] + 0.02 * gs[e]
+        row = oracle.zpw_row(kz, theta, BOX_L, rt)
+        r = oracle.zsm_ratio(azinv, e, row)
+        if us[e] < abs(r) ** 2:
+            oracle.zsm_accept(azinv, az, e, row, r)
+            pos[e] = rt
+    out["complex_single_walker_n1024"] = {"moves_per_s": moves / (time.perf_counter() - t0), "cores": 1,
+                                          "sample": f"{moves} moves of the first sweep at N={n}"}
+    return out
 
 
 EXTRA_LEGS = {
