@@ -456,7 +456,13 @@ def cpu_baseline_walkers(n=1024, moves=100):
     return out
 
 
+def _cache():
+    from paper_1708_00744_amd import tune
+    return tune.load_cache()
+
+
 EXTRA_LEGS = {
+    "fp64_single_walker_n1024": lambda: fp64_single_walker(_cache()),
     "complex_single_walker_n1024": lambda: complex_single_walker(),
     "fp64_drift_walker_n1024": lambda: drift_single_walker(),
 }

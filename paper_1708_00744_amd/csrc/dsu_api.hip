@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -36,11 +37,13 @@ struct dsu_walker {
     double **a_ptr = nullptr;       // device array {a}
     void **bt_ptr = nullptr;        // device array {bt}
     double *inv_tmp = nullptr;      // n x n FP64 for dsu_get_inverse
-    double *row_stage = nullptr;    // pinned host staging: proposal row, then its 3 gradient rows
+    double *row_stage = nullptr;    // mapped pinned host staging: proposal row, then its 3 gradient rows
+    const double *row_stage_dev = nullptr;  // its device address
     double *ratio_h = nullptr;      // pinned host words the propose kernel writes R and grad R into
     GjWork gj;
     // host mirror of the state machine
     int k = 0, slots = 0;
+    unsigned tag = 0;               // completion tag of the last look-ahead call
     std::vector<int> idx;
     bool has_prop = false;
     int prop_e = -1;
@@ -130,10 +133,20 @@ extern "C" int dsu_walker_create(int32_t n, int32_t k_delay, int32_t precision, 
     TRY(dalloc(&w->wd.idx, kp));
     TRY(dalloc(&w->wd.counter, 1));
     w->wd.ldc = (int)kp + 1;
-    if (hipHostMalloc((void **)&w->ratio_h, 4 * sizeof(double), hipHostMallocMapped) != hipSuccess)
+    // coherent: the host watches the completion tag while the kernel runs
+    if (hipHostMalloc((void **)&w->ratio_h, 5 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
         TRY(fail(DSU_ENOMEM, "hipHostMalloc failed"));
-    if (hipHostMalloc((void **)&w->row_stage, 4 * np * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    std::memset(w->ratio_h, 0, 5 * sizeof(double));
+    if (hipHostMalloc((void **)&w->row_stage, 4 * np * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
         TRY(fail(DSU_ENOMEM, "hipHostMalloc failed"));
+    {
+        void *dptr = nullptr;
+        if (hipHostGetDevicePointer(&dptr, w->row_stage, 0) != hipSuccess)
+            TRY(fail(DSU_EDEVICE, "hipHostGetDevicePointer failed"));
+        w->row_stage_dev = static_cast<const double *>(dptr);
+    }
     {
         void *dptr = nullptr;
         if (hipHostGetDevicePointer(&dptr, w->ratio_h, 0) != hipSuccess)
@@ -197,6 +210,22 @@ extern "C" int dsu_flush(dsu_walker *w) {
     return walker_do_flush(w);
 }
 
+// Wait for the look-ahead kernel of call `tag`: it writes the tag to mapped
+// host memory after its results, so watching that word returns as soon as the
+// results are there.  After 2 s of no tag the stream is synchronised instead,
+// which reports a failed kernel.
+static int walker_wait(dsu_walker *w, unsigned tag) {
+    const volatile double *h = w->ratio_h;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spin = 0;; ++spin) {
+        if (h[4] == (double)tag) return DSU_OK;
+        if ((spin & 4095u) == 4095u && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) break;
+    }
+    HIPCHK(hipStreamSynchronize(w->stream));
+    if (h[4] != (double)tag) return fail(DSU_EDEVICE, "look-ahead kernel did not report");
+    return DSU_OK;
+}
+
 static int walker_propose_common(dsu_walker *w, int e, double *ratio_out, double *grad_out = nullptr) {
     // an electron may hold at most one pending move: apply the window first
     for (int j = 0; j < w->k; ++j)
@@ -205,9 +234,10 @@ static int walker_propose_common(dsu_walker *w, int e, double *ratio_out, double
             break;
         }
     const int gm = grad_out ? 1 : 0;
-    if (w->prec == DSU_FP64) HIPCHK(launch_walker_propose<double>(&w->wd, w->n, w->np, w->k, e, gm, -1, w->stream));
-    else HIPCHK(launch_walker_propose<float>(&w->wd, w->n, w->np, w->k, e, gm, -1, w->stream));
-    HIPCHK(hipStreamSynchronize(w->stream));
+    const unsigned tag = ++w->tag;
+    if (w->prec == DSU_FP64) HIPCHK(launch_walker_propose<double>(&w->wd, w->n, w->np, w->k, e, gm, -1, tag, w->stream));
+    else HIPCHK(launch_walker_propose<float>(&w->wd, w->n, w->np, w->k, e, gm, -1, tag, w->stream));
+    CHK(walker_wait(w, tag));
     const volatile double *h = w->ratio_h;
     const double r = h[0];
     w->has_prop = true;
@@ -223,18 +253,18 @@ static int walker_propose_common(dsu_walker *w, int e, double *ratio_out, double
 // 4-row block (0 = proposal, 1..3 = gradient rows), zero padded to np, and
 // convert them to the walker's precision.
 static int walker_stage_rows(dsu_walker *w, int first, int nrows, const double *const *rows) {
-    // the staging buffer may still feed a previous copy: wait for the stream
-    HIPCHK(hipStreamSynchronize(w->stream));
+    // every earlier copy out of the staging buffer was followed on the stream
+    // by a look-ahead kernel the host waited for, so the buffer is free
     const size_t np = w->np;
     double *st = w->row_stage + first * np;
     for (int r = 0; r < nrows; ++r) {
         std::memcpy(st + r * np, rows[r], sizeof(double) * w->n);
         std::memset(st + r * np + w->n, 0, sizeof(double) * (np - w->n));
     }
-    HIPCHK(hipMemcpyAsync(w->wd.phi64 + first * np, st, sizeof(double) * nrows * np, hipMemcpyHostToDevice, w->stream));
-    if (w->prec != DSU_FP64)
-        HIPCHK(launch_row_to(w->wd.phi64 + first * np, static_cast<float *>(w->wd.phi) + first * np, 1,
-                             (int)(nrows * np), (int)(nrows * np), w->stream));
+    // read over the host link by one small kernel (no runtime copy)
+    HIPCHK(launch_rows_from_host(w->row_stage_dev + first * np, w->wd.phi64 + first * np,
+                                 w->prec == DSU_FP64 ? nullptr : static_cast<float *>(w->wd.phi) + first * np,
+                                 (int)(nrows * np), w->stream));
     return DSU_OK;
 }
 
@@ -265,9 +295,11 @@ extern "C" int dsu_eval_grad(dsu_walker *w, int32_t electron, const double *dphi
     int m = -1;  // pending slot holding this electron's accepted move, if any
     for (int j = 0; j < w->k; ++j)
         if (w->idx[j] == electron) m = j;
-    if (w->prec == DSU_FP64) HIPCHK(launch_walker_propose<double>(&w->wd, w->n, w->np, w->k, electron, 2, m, w->stream));
-    else HIPCHK(launch_walker_propose<float>(&w->wd, w->n, w->np, w->k, electron, 2, m, w->stream));
-    HIPCHK(hipStreamSynchronize(w->stream));
+    const unsigned tag = ++w->tag;
+    if (w->prec == DSU_FP64)
+        HIPCHK(launch_walker_propose<double>(&w->wd, w->n, w->np, w->k, electron, 2, m, tag, w->stream));
+    else HIPCHK(launch_walker_propose<float>(&w->wd, w->n, w->np, w->k, electron, 2, m, tag, w->stream));
+    CHK(walker_wait(w, tag));
     const volatile double *h = w->ratio_h;
     for (int a = 0; a < 3; ++a) grad_out[a] = h[1 + a];
     return DSU_OK;

@@ -51,7 +51,7 @@ __device__ __forceinline__ void block_sum_n(T (&v)[NV], T (*sbuf)[kThreads / 64]
 // Grid of 2k+1 blocks: block 0 -> x.BT[e], 1..k -> x.Vg[j], k+1..2k -> q.
 // The last block to finish forms t and the results.
 template <typename T, int GR>
-__global__ __launch_bounds__(kThreads) void k_walker_propose(WalkerDev w, int np, int k, int e, int m) {
+__global__ __launch_bounds__(kThreads) void k_walker_propose(WalkerDev w, int np, int k, int e, int m, unsigned tag) {
     constexpr int NX = GR == 0 ? 1 : (GR == 1 ? 4 : 3);
     constexpr int X0 = GR == 1 ? 1 : 0;  // first gradient row
     __shared__ T sbuf[NX][kThreads / 64];
@@ -127,6 +127,8 @@ __global__ __launch_bounds__(kThreads) void k_walker_propose(WalkerDev w, int np
 #pragma unroll
             for (int a = 0; a < 3; ++a) w.ratio_host[1 + a] = w.gdots[a * ld] - part[X0 + a];
         *w.counter = 0u;
+        __threadfence_system();  // results reach host memory before the tag
+        w.ratio_host[4] = (double)tag;
     }
 }
 
@@ -168,11 +170,13 @@ __global__ __launch_bounds__(kThreads) void k_walker_accept(WalkerDev w, int np,
 }
 
 template <typename T>
-hipError_t launch_walker_propose(WalkerDev *wd, int n, int np, int k, int e, int grad_mode, int m, hipStream_t s) {
+hipError_t launch_walker_propose(WalkerDev *wd, int n, int np, int k, int e, int grad_mode, int m, unsigned tag,
+                                 hipStream_t s) {
     (void)n;
-    if (grad_mode == 0) hipLaunchKernelGGL((k_walker_propose<T, 0>), dim3(2 * k + 1), dim3(kThreads), 0, s, *wd, np, k, e, -1);
-    else if (grad_mode == 1) hipLaunchKernelGGL((k_walker_propose<T, 1>), dim3(2 * k + 1), dim3(kThreads), 0, s, *wd, np, k, e, -1);
-    else hipLaunchKernelGGL((k_walker_propose<T, 2>), dim3(2 * k + 1), dim3(kThreads), 0, s, *wd, np, k, e, m);
+    const dim3 g(2 * k + 1), b(kThreads);
+    if (grad_mode == 0) hipLaunchKernelGGL((k_walker_propose<T, 0>), g, b, 0, s, *wd, np, k, e, -1, tag);
+    else if (grad_mode == 1) hipLaunchKernelGGL((k_walker_propose<T, 1>), g, b, 0, s, *wd, np, k, e, -1, tag);
+    else hipLaunchKernelGGL((k_walker_propose<T, 2>), g, b, 0, s, *wd, np, k, e, m, tag);
     return hipGetLastError();
 }
 template <typename T>
@@ -182,8 +186,8 @@ hipError_t launch_walker_accept(WalkerDev *wd, int n, int np, int k, int kp, int
     hipLaunchKernelGGL((k_walker_accept<T>), dim3(1), dim3(kThreads), 0, s, *wd, np, k, e);
     return hipGetLastError();
 }
-template hipError_t launch_walker_propose<float>(WalkerDev *, int, int, int, int, int, int, hipStream_t);
-template hipError_t launch_walker_propose<double>(WalkerDev *, int, int, int, int, int, int, hipStream_t);
+template hipError_t launch_walker_propose<float>(WalkerDev *, int, int, int, int, int, int, unsigned, hipStream_t);
+template hipError_t launch_walker_propose<double>(WalkerDev *, int, int, int, int, int, int, unsigned, hipStream_t);
 template hipError_t launch_walker_accept<float>(WalkerDev *, int, int, int, int, int, hipStream_t);
 template hipError_t launch_walker_accept<double>(WalkerDev *, int, int, int, int, int, hipStream_t);
 
@@ -195,6 +199,22 @@ __global__ void k_row_convert(const void *src, void *dst, int mode, int n, int n
     if (mode == 1) static_cast<float *>(dst)[c] = c < n ? float(static_cast<const double *>(src)[c]) : 0.0f;
     else if (mode == 2) static_cast<double *>(dst)[c] = c < n ? double(static_cast<const float *>(src)[c]) : 0.0;
     else static_cast<double *>(dst)[c] = c < n ? static_cast<const double *>(src)[c] : 0.0;
+}
+
+// Rows staged by the host in mapped pinned memory, read once over the host
+// link: dst64[c] = src[c] and, when dst32 is given, dst32[c] = float(src[c]),
+// for c < count (padding already zero in the staging rows).
+__global__ void k_rows_from_host(const double *src, double *dst64, float *dst32, int count) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= count) return;
+    const double v = src[c];
+    dst64[c] = v;
+    if (dst32) dst32[c] = float(v);
+}
+
+hipError_t launch_rows_from_host(const double *src_mapped, double *dst64, float *dst32, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_rows_from_host, dim3((count + 255) / 256), dim3(256), 0, s, src_mapped, dst64, dst32, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_row_to(const double *src, void *dst, int mode, int n, int np, hipStream_t s) {

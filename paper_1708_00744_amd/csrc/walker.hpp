@@ -17,7 +17,7 @@ struct WalkerDev {
     double *dots;      // 1 + 2 kp: r0, p[0..k), q[0..k)
     double *t;         // kp: C_k^{-1} q
     double *ratio;     // device copy of R
-    double *ratio_host;// pinned host memory (mapped): R, then grad R (or the drift) for the caller
+    double *ratio_host;// pinned host memory (mapped): R, grad R (or the drift), then the call's completion tag
     void *dphi;        // 3 x np, T: gradient rows (x, y, z) of the proposal or of the present row
     double *gdots;     // 3 (kp + 1) + kp: gradient rows against BT[e] and Vg, then q of the drift call
     int *idx;          // kp pending electrons
@@ -27,12 +27,18 @@ struct WalkerDev {
 
 // Single-walker look-ahead ratio and accept (bordering).
 // grad_mode 0: ratio; 1: ratio and its gradient; 2: gradient of the present
-// row only (m = pending slot held by e, or -1).
+// row only (m = pending slot held by e, or -1).  The results are written to
+// ratio_host, then `tag` to ratio_host[4] (after a system-scope fence), so the
+// host can wait for the call by watching that word.
 template <typename T>
-hipError_t launch_walker_propose(WalkerDev *wd, int n, int np, int k, int e, int grad_mode, int m, hipStream_t s);
+hipError_t launch_walker_propose(WalkerDev *wd, int n, int np, int k, int e, int grad_mode, int m, unsigned tag,
+                                 hipStream_t s);
 template <typename T>
 hipError_t launch_walker_accept(WalkerDev *wd, int n, int np, int k, int kp, int e, hipStream_t s);
 // Row copy into a padded device row: mode 0 FP64->FP64, 1 FP64->float, 2 float->FP64.
 hipError_t launch_row_to(const double *src, void *dst, int mode, int n, int np, hipStream_t s);
+// count FP64 values from mapped pinned host memory (device address) into
+// dst64 and, if dst32 is not NULL, their float casts into dst32.
+hipError_t launch_rows_from_host(const double *src_mapped, double *dst64, float *dst32, int count, hipStream_t s);
 
 }  // namespace dsu

@@ -10,6 +10,7 @@
 // Complex values are stored interleaved (re, im) as double2.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -40,7 +41,7 @@ struct ZWalkerDev {
     zc *dots;          // 1 + 2 kp: r0, p[0..k), q[0..k)
     zc *t;             // kp: C_k^{-1} q
     zc *ratio;         // device copy of R
-    double *ratio_host;// mapped pinned: R (re, im)
+    double *ratio_host;// mapped pinned: R (re, im), then the call's completion tag
     int *idx;          // kp pending electrons
     unsigned *counter; // blocks finished (last-block reduction)
     zc *w;             // np x (kp + 1): flush scratch W
@@ -68,7 +69,7 @@ __device__ __forceinline__ zc block_zsum(zc v, zc *sbuf) {
 
 // Look-ahead ratio: 2k+1 blocks (r0, p, q dot products); the last block to
 // finish forms t = C_k^{-1} q and R = r0 - p.t.
-__global__ __launch_bounds__(kThreads) void k_zpropose(ZWalkerDev w, int np, int k, int e) {
+__global__ __launch_bounds__(kThreads) void k_zpropose(ZWalkerDev w, int np, int k, int e, unsigned tag) {
     __shared__ zc sbuf[kThreads / 64];
     __shared__ int is_last;
     __shared__ zc s_t[DSU_KMAX_LDS];
@@ -104,6 +105,8 @@ __global__ __launch_bounds__(kThreads) void k_zpropose(ZWalkerDev w, int np, int
         w.ratio_host[0] = r.x;
         w.ratio_host[1] = r.y;
         *w.counter = 0u;
+        __threadfence_system();  // the ratio reaches host memory before the tag
+        w.ratio_host[2] = (double)tag;
     }
 }
 
@@ -342,6 +345,12 @@ __global__ void k_zgj_unperm(ZWalkerDev w, int ld, int n) {
     }
 }
 
+// The proposal row from mapped pinned host memory (read once over the host link).
+__global__ void k_zrow_from_host(const double *src, zc *phi, int np) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < np) phi[c] = make_double2(src[2 * c], src[2 * c + 1]);
+}
+
 // out[i][j] = BT[j][i] (A^{-1}, n x n).
 __global__ void k_zuntranspose(const zc *bt, zc *out, int n, int np) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
@@ -358,9 +367,11 @@ struct dsu_zwalker {
     bool own_stream = false;
     ZWalkerDev wd{};
     double *ratio_h = nullptr;
-    double *row_stage = nullptr;
+    double *row_stage = nullptr;            // mapped pinned host staging of a proposal row
+    const double *row_stage_dev = nullptr;  // its device address
     zc *inv_tmp = nullptr;
     int k = 0, slots = 0;
+    unsigned tag = 0;  // completion tag of the last look-ahead call
     std::vector<int> idx;
     bool has_prop = false;
     int prop_e = -1;
@@ -468,10 +479,20 @@ extern "C" int dsu_zwalker_create(int32_t n, int32_t k_delay, int32_t policy, co
     TRY(dalloc(&w->wd.stat, 3));
     TRY(dalloc(&w->wd.status, 1));
     w->wd.ldc = (int)kp + 1;
-    if (hipHostMalloc((void **)&w->ratio_h, 2 * sizeof(double), hipHostMallocMapped) != hipSuccess)
+    // coherent: the host watches the completion tag while the kernel runs
+    if (hipHostMalloc((void **)&w->ratio_h, 3 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
         TRY(fail(DSU_ENOMEM, "hipHostMalloc failed"));
-    if (hipHostMalloc((void **)&w->row_stage, 2 * np * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    std::memset(w->ratio_h, 0, 3 * sizeof(double));
+    if (hipHostMalloc((void **)&w->row_stage, 2 * np * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
         TRY(fail(DSU_ENOMEM, "hipHostMalloc failed"));
+    {
+        void *dptr = nullptr;
+        if (hipHostGetDevicePointer(&dptr, w->row_stage, 0) != hipSuccess)
+            TRY(fail(DSU_EDEVICE, "hipHostGetDevicePointer failed"));
+        w->row_stage_dev = static_cast<const double *>(dptr);
+    }
     {
         void *dptr = nullptr;
         if (hipHostGetDevicePointer(&dptr, w->ratio_h, 0) != hipSuccess)
@@ -506,14 +527,32 @@ extern "C" int dsu_zpropose_ratio(dsu_zwalker *w, int32_t electron, const double
             CHK(zwalker_flush(w));
             break;
         }
-    HIPCHK(hipStreamSynchronize(w->stream));  // the staging buffer may still feed a previous copy
+    // every earlier copy out of the staging buffer was followed on the stream by
+    // a look-ahead kernel the host waited for, so the buffer is free
     std::memcpy(w->row_stage, phi_host, sizeof(double) * 2 * w->n);
     std::memset(w->row_stage + 2 * w->n, 0, sizeof(double) * 2 * (w->np - w->n));
-    HIPCHK(hipMemcpyAsync(w->wd.phi, w->row_stage, sizeof(zc) * w->np, hipMemcpyHostToDevice, w->stream));
-    hipLaunchKernelGGL(k_zpropose, dim3(2 * w->k + 1), dim3(kThreads), 0, w->stream, w->wd, w->np, w->k, electron);
+    hipLaunchKernelGGL(k_zrow_from_host, dim3((w->np + 255) / 256), dim3(256), 0, w->stream, w->row_stage_dev, w->wd.phi,
+                       w->np);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(w->stream));
+    const unsigned tag = ++w->tag;
+    hipLaunchKernelGGL(k_zpropose, dim3(2 * w->k + 1), dim3(kThreads), 0, w->stream, w->wd, w->np, w->k, electron,
+                       tag);
+    HIPCHK(hipGetLastError());
+    // the kernel writes the tag to mapped memory after the ratio; after 2 s
+    // without it the stream is synchronised instead (reports a failed kernel)
     const volatile double *h = w->ratio_h;
+    {
+        const auto t0 = std::chrono::steady_clock::now();
+        bool seen = false;
+        for (unsigned spin = 0; !seen; ++spin) {
+            if (h[2] == (double)tag) seen = true;
+            else if ((spin & 4095u) == 4095u && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) break;
+        }
+        if (!seen) {
+            HIPCHK(hipStreamSynchronize(w->stream));
+            if (h[2] != (double)tag) return fail(DSU_EDEVICE, "look-ahead kernel did not report");
+        }
+    }
     w->prop_re = h[0];
     w->prop_im = h[1];
     w->has_prop = true;
