@@ -655,3 +655,43 @@ void orc_zsm_accept_r(int n, double complex *ainv, double complex *a, int e, con
 {
     orc_zsm_accept(n, ainv, a, e, phi, *r, work);
 }
+
+/* ======================================================================== */
+/* Multideterminant wave functions on a single reference.  Psi = sum_I c_I  */
+/* det(A_I), where A_I is the reference Slater matrix A (row i = electron   */
+/* i, column j = occupied orbital j) with the columns occ[I][a] replaced by */
+/* the virtual-orbital columns V[:, virt[I][a]], a < order[I] (order 0 is   */
+/* the reference itself).  Evaluated by definition: one LU per term.        */
+/* Returns log|Psi| and sign(Psi) (0 if Psi = 0).                           */
+/* ======================================================================== */
+int orc_md_psi(int n, int m, const double *a, const double *v, int ndet, const int *order, const int *occ,
+               const int *virt, const double *coef, double *logabs, int *sign)
+{
+    for (int d = 0; d < ndet; ++d) {
+        if (order[d] < 0 || order[d] > 4) return -1;
+        for (int q = 0; q < order[d]; ++q)
+            if (occ[4 * d + q] < 0 || occ[4 * d + q] >= n || virt[4 * d + q] < 0 || virt[4 * d + q] >= m) return -1;
+    }
+    double *w = (double *)malloc(sizeof(double) * (size_t)n * n);
+    int *piv = (int *)malloc(sizeof(int) * (size_t)n);
+    double *ld = (double *)malloc(sizeof(double) * (size_t)ndet);
+    int *sg = (int *)malloc(sizeof(int) * (size_t)ndet);
+    double lmax = -INFINITY;
+    for (int d = 0; d < ndet; ++d) {
+        memcpy(w, a, sizeof(double) * (size_t)n * n);
+        for (int q = 0; q < order[d]; ++q) {
+            int j = occ[4 * d + q], vv = virt[4 * d + q];
+            for (int i = 0; i < n; ++i) w[(size_t)i * n + j] = v[(size_t)i * m + vv];
+        }
+        if (orc_lu(n, w, piv, &ld[d], &sg[d]) != 0) { sg[d] = 0; ld[d] = -INFINITY; }
+        if (sg[d] != 0 && coef[d] != 0.0 && ld[d] > lmax) lmax = ld[d];
+    }
+    double s = 0.0;
+    for (int d = 0; d < ndet; ++d)
+        if (sg[d] != 0) s += coef[d] * sg[d] * exp(ld[d] - lmax);
+    free(w); free(piv); free(ld); free(sg);
+    if (s == 0.0 || !isfinite(lmax)) { *logabs = -INFINITY; *sign = 0; return 0; }
+    *logabs = lmax + log(fabs(s));
+    *sign = s > 0 ? 1 : -1;
+    return 0;
+}

@@ -73,6 +73,9 @@ def _declare(L):
     L.orc_zsm_ratio_out.restype = None
     L.orc_zsm_accept_r.argtypes = [C.c_int, _zp, C.c_void_p, C.c_int, _zp, _zp, _zp]
     L.orc_zsm_accept_r.restype = None
+    L.orc_md_psi.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_int, _ip, _ip, _ip, _dp, C.POINTER(C.c_double),
+                             C.POINTER(C.c_int)]
+    L.orc_md_psi.restype = C.c_int
     vp = C.c_void_p
     L.orc_walker_run.argtypes = [C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_int, C.c_double,
                                  C.c_int, C.c_int, C.c_int, _dp,
@@ -326,3 +329,41 @@ def zsm_accept(ainv, a, e, phi, r):
     work = np.zeros(2 * n, np.complex128)
     lib().orc_zsm_accept_r(n, ainv, None if a is None else a.ctypes.data_as(C.c_void_p), int(e),
                            np.ascontiguousarray(phi, np.complex128), np.array([r], np.complex128), work)
+
+
+# ------------------------------------------------------- multideterminant
+def md_pack(dets):
+    """dets: list of (coef, [(occ, virt), ...]) -> (order, occ, virt, coef) arrays."""
+    nd = len(dets)
+    order = np.zeros(nd, np.int32)
+    occ = np.zeros((nd, 4), np.int32)
+    virt = np.zeros((nd, 4), np.int32)
+    coef = np.zeros(nd)
+    for d, (c, subs) in enumerate(dets):
+        order[d] = len(subs)
+        coef[d] = c
+        for q, (j, v) in enumerate(subs):
+            occ[d, q], virt[d, q] = j, v
+    return order, occ, virt, coef
+
+
+def md_psi(a, v, dets):
+    """(sign, log|Psi|) of Psi = sum_I c_I det(A_I) by one LU per term."""
+    a = np.ascontiguousarray(a, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    order, occ, virt, coef = md_pack(dets)
+    la, sg = C.c_double(), C.c_int()
+    rc = lib().orc_md_psi(a.shape[0], v.shape[1], a, v, len(dets), order, np.ascontiguousarray(occ.ravel()),
+                          np.ascontiguousarray(virt.ravel()), coef, C.byref(la), C.byref(sg))
+    if rc != 0:
+        raise ValueError("bad excitation list")
+    return sg.value, la.value
+
+
+def md_ratio(a, v, dets, e, phi, vphi):
+    """Psi(A with row e -> phi, V with row e -> vphi) / Psi(A, V)."""
+    s0, l0 = md_psi(a, v, dets)
+    a1, v1 = a.copy(), v.copy()
+    a1[e], v1[e] = phi, vphi
+    s1, l1 = md_psi(a1, v1, dets)
+    return s1 * s0 * np.exp(l1 - l0) if s1 != 0 else 0.0

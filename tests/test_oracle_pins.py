@@ -509,3 +509,58 @@ def test_twisted_plane_waves():
     pts = (np.array(np.meshgrid(np.arange(M), np.arange(M), np.arange(M), indexing="ij")).reshape(3, -1).T + 0.3) * (L / M)
     A = oracle.zpw_matrix(kv, theta, L, pts)
     np.testing.assert_allclose(A.conj().T @ A / M**3, np.eye(n), atol=1e-12)
+
+
+# ------------------------------------------------------ multideterminant
+MD_DETS = [(1.0, []), (0.35, [(2, 1)]), (-0.2, [(0, 0), (5, 3)]), (0.1, [(4, 2)]), (0.05, [(1, 3), (3, 0)])]
+
+
+def test_md_psi_matches_term_by_term_determinants():
+    # sum of numpy determinants of the substituted matrices (LAPACK)
+    rng = np.random.default_rng(61)
+    for n, m in ((6, 4), (9, 5)):
+        a, v = rng.standard_normal((n, n)), rng.standard_normal((n, m))
+        want = 0.0
+        for c, subs in MD_DETS:
+            b = a.copy()
+            for j, vv in subs:
+                b[:, j] = v[:, vv]
+            want += c * np.linalg.det(b)
+        sg, la = oracle.md_psi(a, v, MD_DETS)
+        assert abs(sg * math.exp(la) - want) < 1e-12 * max(1.0, abs(want))
+
+
+def test_md_psi_exact_rational():
+    rng = np.random.default_rng(62)
+    n, m = 6, 4
+    a = rng.integers(-3, 4, (n, n)) + 3 * np.eye(n, dtype=int)
+    v = rng.integers(-3, 4, (n, m))
+    dets = [(1, []), (2, [(2, 1)]), (-3, [(0, 0), (5, 3)]), (1, [(4, 2)])]
+    exact = Fraction(0)
+    for c, subs in dets:
+        b = a.copy()
+        for j, vv in subs:
+            b[:, j] = v[:, vv]
+        exact += c * frac_det(b.tolist())
+    sg, la = oracle.md_psi(a.astype(float), v.astype(float), [(float(c), s) for c, s in dets])
+    assert abs(sg * math.exp(la) - float(exact)) <= 1e-12 * max(1.0, abs(float(exact)))
+
+
+def test_md_psi_special_cases():
+    # one electron: Psi = c0 a + c1 v0 + c2 v1
+    a, v = np.array([[0.7]]), np.array([[-1.3, 2.2]])
+    sg, la = oracle.md_psi(a, v, [(0.5, []), (0.25, [(0, 0)]), (-1.0, [(0, 1)])])
+    assert abs(sg * math.exp(la) - (0.5 * 0.7 + 0.25 * -1.3 - 2.2)) < 1e-15
+    # reference only: the plain determinant; exchanging two electrons flips the sign
+    rng = np.random.default_rng(63)
+    n, m = 7, 4
+    a, v = rng.standard_normal((n, n)), rng.standard_normal((n, m))
+    s0, l0 = np.linalg.slogdet(a)
+    assert oracle.md_psi(a, v, [(1.0, [])]) == (pytest.approx(s0), pytest.approx(l0, abs=1e-12))
+    sg, la = oracle.md_psi(a, v, MD_DETS[:3] + [(0.4, [(6, 2)])])
+    a2, v2 = a.copy(), v.copy()
+    a2[[1, 4]], v2[[1, 4]] = a[[4, 1]], v[[4, 1]]
+    sg2, la2 = oracle.md_psi(a2, v2, MD_DETS[:3] + [(0.4, [(6, 2)])])
+    assert sg2 == -sg and abs(la2 - la) < 1e-12
+    with pytest.raises(ValueError):
+        oracle.md_psi(a, v[:, :3], MD_DETS)  # virtual index 3 out of range
