@@ -356,6 +356,60 @@ def complex_single_walker(n=1024, sigma=0.02, sweeps=1):
     return res
 
 
+def md_expansion(n, m, nocc=8):
+    """Reference, all singles from the top `nocc` occupied orbitals into the m
+    virtual ones, and doubles from pairs of them into pairs of virtual ones."""
+    top = list(range(n - nocc, n))
+    dets = [(1.0, [])]
+    for a, j in enumerate(top):
+        for v in range(m):
+            dets.append((0.1 / (1 + a + v), [(j, v)]))
+    for a in range(0, nocc - 1, 2):
+        for v in range(0, m - 1, 2):
+            dets.append((0.02 / (1 + a + v), [(top[a], v), (top[a + 1], v + 1)]))
+    return dets
+
+
+def multidet_single_walker(n=1024, m=16, sigma=0.002):
+    """Multideterminant expansion on a single reference (FP64, host-driven):
+    one dsu_propose_ratio_md / accept per move over one sweep, plane waves (the
+    n lowest occupied, the next m virtual), caller-side rows (numpy)."""
+    from paper_1708_00744_amd import dsu, inputs
+    kv = dsu.plane_wave_table(n + m).astype(np.float64)
+    kind, g2 = kv[:, 3], 2 * np.pi / BOX_L
+
+    def rows(p):
+        ph = g2 * (p @ kv[:, :3].T)
+        return np.where(kind == 0, 1.0, np.where(kind == 1, np.cos(ph), np.sin(ph)))
+
+    dets = md_expansion(n, m)
+    pos0 = inputs.positions(2, 0, n, BOX_L)
+    full = rows(pos0)
+    res = {"n": n, "m": m, "determinants": len(dets), "sigma": sigma}
+    for K in (1, 64):
+        pos = pos0.copy()
+        gs, us = inputs.normals(3, (n, 3)), inputs.uniforms(4, n)
+        with dsu.Walker(np.ascontiguousarray(full[:, :n]), K, precision=dsu.FP64) as w:
+            w.set_multidet(np.ascontiguousarray(full[:, n:]), dets)
+            prop = pos + sigma * gs
+            rp = rows(prop)
+            acc = 0
+            t0 = time.perf_counter()
+            for e in range(n):
+                r, _ = w.propose_md(e, rp[e, :n], rp[e, n:])
+                if us[e] < r * r:
+                    w.accept()
+                    pos[e] = prop[e]
+                    acc += 1
+                else:
+                    w.reject()
+            w.flush()
+            dt = time.perf_counter() - t0
+        res[f"host_driven_K{K}_moves_per_s"] = n / dt
+        res[f"K{K}_acceptance"] = acc / n
+    return res
+
+
 def serving(cache, count=40, seed=7):
     from paper_1708_00744_amd import dsu, inputs
     sizes, accs, seeds = inputs.serving_mix(seed, count)
@@ -453,6 +507,20 @@ def cpu_baseline_walkers(n=1024, moves=100):
             pos[e] = rt
     out["complex_single_walker_n1024"] = {"moves_per_s": moves / (time.perf_counter() - t0), "cores": 1,
                                           "sample": f"{moves} moves of the first sweep at N={n}"}
+    # multideterminant: Psi by definition (one LU per determinant) before and after each move
+    m, nmd, md_moves = 16, 256, 4
+    kv = oracle.pw_kvectors(nmd + m)
+    pos = inputs.positions(2, 0, nmd, BOX_L)
+    full = np.stack([oracle.pw_row(kv, BOX_L, p) for p in pos])
+    a, v = np.ascontiguousarray(full[:, :nmd]), np.ascontiguousarray(full[:, nmd:])
+    dets = md_expansion(nmd, m)
+    t0 = time.perf_counter()
+    for e in range(md_moves):
+        row = oracle.pw_row(kv, BOX_L, pos[e] + 0.002 * np.ones(3))
+        oracle.md_ratio(a, v, dets, e, row[:nmd], row[nmd:])
+    out["multidet_single_walker"] = {"moves_per_s": md_moves / (time.perf_counter() - t0), "cores": 1,
+                                     "sample": f"{md_moves} ratios at N={nmd}, m={m}, {len(dets)} determinants "
+                                               f"(the extras leg runs N=1024)"}
     return out
 
 
@@ -464,6 +532,7 @@ def _cache():
 EXTRA_LEGS = {
     "fp64_single_walker_n1024": lambda: fp64_single_walker(_cache()),
     "complex_single_walker_n1024": lambda: complex_single_walker(),
+    "multidet_single_walker_n1024": lambda: multidet_single_walker(),
     "fp64_drift_walker_n1024": lambda: drift_single_walker(),
 }
 
@@ -527,6 +596,8 @@ def main():
         extras["fp64_single_walker_n1024"] = fp64_single_walker(cache)
         log("complex-orbital walker N=1024")
         extras["complex_single_walker_n1024"] = complex_single_walker()
+        log("multideterminant walker N=1024")
+        extras["multidet_single_walker_n1024"] = multidet_single_walker()
         log("FP64 drift-diffusion walker N=1024")
         extras["fp64_drift_walker_n1024"] = drift_single_walker()
         log("serving")

@@ -168,6 +168,38 @@ int dsu_walker_pending(dsu_walker *w, int32_t *k_out);
 /* Choose the flush kernel (DSU_FLUSH_*) -- for the VALU/MFMA crossover study. */
 int dsu_walker_set_flush_kernel(dsu_walker *w, int32_t mode);
 
+/* Multideterminant expansion on a single reference (FP64 walkers; the
+ * combination with single-reference multideterminant schemes noted at the end
+ * of Sec. II).  Psi = sum_I coef[I] det(A_I): A_I is the walker's Slater
+ * matrix with the occupied orbitals occ[4I .. 4I+order[I]) replaced by the
+ * virtual orbitals virt[4I .. 4I+order[I]) (order 0 = the reference itself,
+ * order <= 4, no orbital repeated within a determinant).  virt_host holds the
+ * m virtual orbitals at every electron, n*m FP64, row i = electron i.  The
+ * library keeps the table T = A^{-1} V; det(A_I)/det(A) is the determinant
+ * of a submatrix of T of size order[I], and a move changes T by a rank-1 term
+ * built from the delayed inverse's column of the moved electron (the eq. (3)
+ * look-ahead), so the reference keeps its delayed updates.  Pending moves are
+ * flushed and a pending proposal dropped.  Once set, proposals go through
+ * dsu_propose_ratio_md (the other propose calls return DSU_ESTATE); a
+ * dsu_recompute_inverse with a new matrix drops the expansion.  DSU_EINVAL for
+ * a non-FP64 walker, m outside [1, 4096], a bad excitation; DSU_ESINGULAR if
+ * Psi is zero. */
+int dsu_walker_set_multidet(dsu_walker *w, int32_t m, const double *virt_host, int32_t ndet, const int32_t *order,
+                            const int32_t *occ, const int32_t *virt, const double *coef);
+/* Ratio Psi(new)/Psi(old) for moving `electron` to the point whose occupied
+ * orbital values are phi_host (n) and virtual values vphi_host (m); the
+ * reference ratio det(A_new)/det(A) goes to ratio_ref_out (may be NULL).
+ * The proposal stays pending for dsu_accept / dsu_reject; dsu_accept returns
+ * DSU_ESINGULAR if the reference ratio is below 1e-12 in modulus (the
+ * single-reference update needs it) or Psi vanishes at the new point.
+ * Synchronises. */
+int dsu_propose_ratio_md(dsu_walker *w, int32_t electron, const double *phi_host, const double *vphi_host,
+                         double *ratio_out, double *ratio_ref_out);
+/* log|Psi| and sign(Psi) of the present configuration (running reference
+ * log-determinant plus the expansion's ratio to the reference).  DSU_ESTATE
+ * without an expansion. */
+int dsu_walker_md_value(dsu_walker *w, double *logabs, int32_t *sign);
+
 /* ======================================================================
  * Single walker with complex orbitals (twisted boundary conditions).
  * The same look-ahead (eq. (3)), bordering and en-bloc update (eq. (4)) in

@@ -44,6 +44,12 @@ struct dsu_walker {
     // host mirror of the state machine
     int k = 0, slots = 0;
     unsigned tag = 0;               // completion tag of the last look-ahead call
+    // multideterminant expansion (FP64 walkers): table, excitations, Q
+    MdDev md{};
+    bool md_on = false, prop_md = false;
+    double md_q = 1.0, md_q_pending = 1.0;
+    double *vphi_stage = nullptr;           // mapped pinned staging of the virtual row
+    const double *vphi_stage_dev = nullptr;
     std::vector<int> idx;
     bool has_prop = false;
     int prop_e = -1;
@@ -54,6 +60,17 @@ struct dsu_walker {
 
 static size_t elem(int prec) { return dsu::elem_size(prec); }
 
+static void walker_md_free(dsu_walker *w) {
+    for (void *p : {(void *)w->md.v, (void *)w->md.t, (void *)w->md.c, (void *)w->md.vphi, (void *)w->md.x,
+                    (void *)w->md.order, (void *)w->md.occ, (void *)w->md.virt, (void *)w->md.coef, (void *)w->md.q})
+        dfree(p);
+    if (w->vphi_stage) (void)hipHostFree(w->vphi_stage);
+    w->vphi_stage = nullptr;
+    w->vphi_stage_dev = nullptr;
+    w->md = MdDev{};
+    w->md_on = w->prop_md = false;
+}
+
 static void walker_free(dsu_walker *w) {
     if (w->wd.phi != (void *)w->wd.phi64) dfree(w->wd.phi);  // FP64 walkers share one row buffer
     for (void *p : {w->wd.bt, w->wd.u, w->wd.vg, (void *)w->wd.a, (void *)w->wd.phi64, (void *)w->wd.cinv,
@@ -63,6 +80,7 @@ static void walker_free(dsu_walker *w) {
         dfree(p);
     if (w->ratio_h) (void)hipHostFree(w->ratio_h);
     if (w->row_stage) (void)hipHostFree(w->row_stage);
+    walker_md_free(w);
     w->gj.release();
     if (w->own_stream && w->stream) (void)hipStreamDestroy(w->stream);
 }
@@ -270,6 +288,7 @@ static int walker_stage_rows(dsu_walker *w, int first, int nrows, const double *
 
 extern "C" int dsu_propose_ratio(dsu_walker *w, int32_t electron, const double *phi_host, double *ratio_out) {
     if (!w) return fail(DSU_EINVAL, "walker is NULL");
+    if (w->md_on) return fail(DSU_ESTATE, "multideterminant walker: propose with dsu_propose_ratio_md");
     if (electron < 0 || electron >= w->n) return fail(DSU_EINVAL, "electron %d out of range", electron);
     if (!phi_host) return fail(DSU_EINVAL, "row is NULL");
     CHK(walker_stage_rows(w, 0, 1, &phi_host));
@@ -279,6 +298,7 @@ extern "C" int dsu_propose_ratio(dsu_walker *w, int32_t electron, const double *
 extern "C" int dsu_propose_ratio_grad(dsu_walker *w, int32_t electron, const double *phi_host, const double *dphi_host,
                                       double *ratio_out, double *grad_out) {
     if (!w) return fail(DSU_EINVAL, "walker is NULL");
+    if (w->md_on) return fail(DSU_ESTATE, "multideterminant walker: propose with dsu_propose_ratio_md");
     if (electron < 0 || electron >= w->n) return fail(DSU_EINVAL, "electron %d out of range", electron);
     if (!phi_host || !dphi_host || !grad_out) return fail(DSU_EINVAL, "NULL argument");
     const double *rows[4] = {phi_host, dphi_host, dphi_host + w->n, dphi_host + 2 * (size_t)w->n};
@@ -307,6 +327,7 @@ extern "C" int dsu_eval_grad(dsu_walker *w, int32_t electron, const double *dphi
 
 extern "C" int dsu_propose_ratio_dev(dsu_walker *w, int32_t electron, const void *phi_dev, double *ratio_out) {
     if (!w) return fail(DSU_EINVAL, "walker is NULL");
+    if (w->md_on) return fail(DSU_ESTATE, "multideterminant walker: propose with dsu_propose_ratio_md");
     if (electron < 0 || electron >= w->n) return fail(DSU_EINVAL, "electron %d out of range", electron);
     if (!phi_dev) return fail(DSU_EINVAL, "row is NULL");
     if (w->prec == DSU_FP64) {
@@ -332,8 +353,15 @@ extern "C" int dsu_accept(dsu_walker *w) {
     const double r = w->prop_r;
     const double floor = w->prec == DSU_FP64 ? RatioFloor<double>::value : RatioFloor<float>::value;
     if (!(std::fabs(r) > floor) || !std::isfinite(r)) return fail(DSU_ESINGULAR, "ratio %g cannot be accepted", r);
+    if (w->prop_md && !(std::fabs(w->md_q_pending) > 0.0 && std::isfinite(w->md_q_pending)))
+        return fail(DSU_ESINGULAR, "the expansion vanishes at the proposed configuration");
     if (w->prec == DSU_FP64) HIPCHK(launch_walker_accept<double>(&w->wd, w->n, w->np, w->k, w->kp, w->prop_e, w->stream));
     else HIPCHK(launch_walker_accept<float>(&w->wd, w->n, w->np, w->k, w->kp, w->prop_e, w->stream));
+    if (w->prop_md) {
+        HIPCHK(launch_md_accept(&w->md, w->n, w->np, w->prop_e, w->stream));
+        w->md_q = w->md_q_pending;
+        w->prop_md = false;
+    }
     w->idx[w->k] = w->prop_e;
     ++w->k;
     w->logdet += std::log(std::fabs(r));
@@ -346,9 +374,12 @@ extern "C" int dsu_reject(dsu_walker *w) {
     if (!w) return fail(DSU_EINVAL, "walker is NULL");
     if (!w->has_prop) return fail(DSU_ESTATE, "no pending proposal");
     w->has_prop = false;
+    w->prop_md = false;
     if (w->policy == DSU_FLUSH_K_PROPOSED) return walker_slot_used(w);
     return DSU_OK;
 }
+
+static int walker_md_refresh(dsu_walker *w);
 
 extern "C" int dsu_recompute_inverse(dsu_walker *w, const double *slater_host_or_null, double *logdet_out,
                                      int32_t *sign_out, double *drift_out) {
@@ -359,6 +390,13 @@ extern "C" int dsu_recompute_inverse(dsu_walker *w, const double *slater_host_or
     double ld;
     int sg;
     CHK(walker_recompute(w, &ld, &sg));
+    if (w->md_on) {
+        if (slater_host_or_null) {
+            walker_md_free(w);  // the virtual rows belong to the old configuration
+        } else {
+            CHK(walker_md_refresh(w));
+        }
+    }
     if (drift_out) *drift_out = w->logdet - ld;
     w->logdet = ld;
     w->sign = sg;
@@ -403,3 +441,123 @@ extern "C" int dsu_walker_set_flush_kernel(dsu_walker *w, int32_t mode) {
     return DSU_OK;
 }
 
+
+// ==========================================================================
+// Multideterminant expansion on a single reference (FP64 walkers)
+// ==========================================================================
+// Table T = A^{-1} V from the present (flushed) inverse, and Q of the present table.
+static int walker_md_refresh(dsu_walker *w) {
+    HIPCHK(launch_md_table(&w->wd, &w->md, w->n, w->np, w->stream));
+    const unsigned tag = ++w->tag;
+    HIPCHK(launch_md_init(&w->wd, &w->md, tag, w->stream));
+    CHK(walker_wait(w, tag));
+    const double q = ((const volatile double *)w->ratio_h)[2];
+    if (!(std::fabs(q) > 0.0) || !std::isfinite(q)) return fail(DSU_ESINGULAR, "the expansion vanishes (Q = %g)", q);
+    w->md_q = q;
+    return DSU_OK;
+}
+
+extern "C" int dsu_walker_set_multidet(dsu_walker *w, int32_t m, const double *virt_host, int32_t ndet,
+                                       const int32_t *order, const int32_t *occ, const int32_t *virt,
+                                       const double *coef) {
+    if (!w) return fail(DSU_EINVAL, "walker is NULL");
+    if (w->prec != DSU_FP64) return fail(DSU_EINVAL, "multideterminant expansions need an FP64 walker");
+    if (m < 1 || m > 4096) return fail(DSU_EINVAL, "m = %d out of range [1, 4096]", m);
+    if (ndet < 1 || ndet > (1 << 20)) return fail(DSU_EINVAL, "ndet = %d out of range", ndet);
+    if (!virt_host || !order || !occ || !virt || !coef) return fail(DSU_EINVAL, "NULL argument");
+    for (int d = 0; d < ndet; ++d) {
+        const int o = order[d];
+        if (o < 0 || o > 4) return fail(DSU_EINVAL, "determinant %d: order %d outside [0, 4]", d, o);
+        for (int a = 0; a < o; ++a) {
+            const int j = occ[4 * d + a], v = virt[4 * d + a];
+            if (j < 0 || j >= w->n || v < 0 || v >= m) return fail(DSU_EINVAL, "determinant %d: index out of range", d);
+            for (int b = 0; b < a; ++b)
+                if (occ[4 * d + b] == j || virt[4 * d + b] == v)
+                    return fail(DSU_EINVAL, "determinant %d: repeated orbital", d);
+        }
+    }
+    walker_md_free(w);
+    CHK(walker_do_flush(w));
+    w->has_prop = false;
+    const size_t np = w->np;
+    int rc = DSU_OK;
+#define MDTRY(x)                  \
+    do {                          \
+        rc = (x);                 \
+        if (rc != DSU_OK) {       \
+            walker_md_free(w);    \
+            return rc;            \
+        }                         \
+    } while (0)
+    MDTRY(dalloc(&w->md.v, np * m));
+    MDTRY(dalloc(&w->md.t, np * m));
+    MDTRY(dalloc(&w->md.c, np));
+    MDTRY(dalloc(&w->md.vphi, (size_t)m));
+    MDTRY(dalloc(&w->md.x, (size_t)m));
+    MDTRY(dalloc(&w->md.order, (size_t)ndet));
+    MDTRY(dalloc(&w->md.occ, 4 * (size_t)ndet));
+    MDTRY(dalloc(&w->md.virt, 4 * (size_t)ndet));
+    MDTRY(dalloc(&w->md.coef, (size_t)ndet));
+    MDTRY(dalloc(&w->md.q, 2));
+    if (hipHostMalloc((void **)&w->vphi_stage, sizeof(double) * m, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+        MDTRY(fail(DSU_ENOMEM, "hipHostMalloc failed"));
+    {
+        void *dptr = nullptr;
+        if (hipHostGetDevicePointer(&dptr, w->vphi_stage, 0) != hipSuccess)
+            MDTRY(fail(DSU_EDEVICE, "hipHostGetDevicePointer failed"));
+        w->vphi_stage_dev = static_cast<const double *>(dptr);
+    }
+    w->md.m = m;
+    w->md.ndet = ndet;
+    if (hipMemcpy(w->md.v, virt_host, sizeof(double) * w->n * m, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(w->md.order, order, sizeof(int) * ndet, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(w->md.occ, occ, sizeof(int) * 4 * ndet, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(w->md.virt, virt, sizeof(int) * 4 * ndet, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(w->md.coef, coef, sizeof(double) * ndet, hipMemcpyHostToDevice) != hipSuccess)
+        MDTRY(fail(DSU_EDEVICE, "expansion upload failed"));
+    MDTRY(walker_md_refresh(w));
+#undef MDTRY
+    w->md_on = true;
+    return DSU_OK;
+}
+
+extern "C" int dsu_propose_ratio_md(dsu_walker *w, int32_t electron, const double *phi_host, const double *vphi_host,
+                                    double *ratio_out, double *ratio_ref_out) {
+    if (!w) return fail(DSU_EINVAL, "walker is NULL");
+    if (!w->md_on) return fail(DSU_ESTATE, "no multideterminant expansion set");
+    if (electron < 0 || electron >= w->n) return fail(DSU_EINVAL, "electron %d out of range", electron);
+    if (!phi_host || !vphi_host) return fail(DSU_EINVAL, "row is NULL");
+    CHK(walker_stage_rows(w, 0, 1, &phi_host));
+    std::memcpy(w->vphi_stage, vphi_host, sizeof(double) * w->md.m);
+    HIPCHK(launch_rows_from_host(w->vphi_stage_dev, w->md.vphi, nullptr, w->md.m, w->stream));
+    // an electron may hold at most one pending move: apply the window first
+    for (int j = 0; j < w->k; ++j)
+        if (w->idx[j] == electron) {
+            CHK(walker_do_flush(w));
+            break;
+        }
+    const unsigned t1 = ++w->tag;
+    HIPCHK(launch_walker_propose<double>(&w->wd, w->n, w->np, w->k, electron, 0, -1, t1, w->stream));
+    const unsigned t2 = ++w->tag;
+    HIPCHK(launch_md_propose(&w->wd, &w->md, w->n, w->np, w->k, electron, t2, w->stream));
+    CHK(walker_wait(w, t2));
+    const volatile double *h = w->ratio_h;
+    const double total = h[0], r = h[1], q = h[2];
+    w->has_prop = true;
+    w->prop_e = electron;
+    w->prop_r = r;
+    w->prop_md = true;
+    w->md_q_pending = q;
+    if (ratio_out) *ratio_out = total;
+    if (ratio_ref_out) *ratio_ref_out = r;
+    return DSU_OK;
+}
+
+extern "C" int dsu_walker_md_value(dsu_walker *w, double *logabs, int32_t *sign) {
+    if (!w) return fail(DSU_EINVAL, "walker is NULL");
+    if (!w->md_on) return fail(DSU_ESTATE, "no multideterminant expansion set");
+    if (logabs) *logabs = w->logdet + std::log(std::fabs(w->md_q));
+    if (sign) *sign = w->md_q < 0 ? -w->sign : w->sign;
+    return DSU_OK;
+}

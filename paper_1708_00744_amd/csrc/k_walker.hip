@@ -191,6 +191,134 @@ template hipError_t launch_walker_propose<double>(WalkerDev *, int, int, int, in
 template hipError_t launch_walker_accept<float>(WalkerDev *, int, int, int, int, int, hipStream_t);
 template hipError_t launch_walker_accept<double>(WalkerDev *, int, int, int, int, int, hipStream_t);
 
+// ------------------------------------------------------------------------
+// Multideterminant expansion on a single reference (FP64 walker).
+// Psi = sum_I c_I det(A_I): A_I is A with occupied columns J_I replaced by
+// virtual columns V_I, and det(A_I) / det(A) = det S_I, S_I = T[J_I][V_I]
+// with the table T = A^{-1} V.  Moving electron e (rows phi, vphi) changes T
+// by a rank-1 term: T' = T + c x^T, c = A^{-1}[:, e] (the delayed inverse's
+// column, i.e. BT[e] corrected by the pending moves as in the look-ahead),
+// x = (vphi - phi T) / R with R the reference ratio.
+// ------------------------------------------------------------------------
+
+// T[j][v] = sum_i BT[i][j] V[i][v], j < n (rows past n stay zero).
+__global__ void k_md_table(const double *bt, MdDev md, int n, int np) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, v = blockIdx.y;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += bt[(size_t)i * np + j] * md.v[(size_t)i * md.m + v];
+    md.t[(size_t)j * md.m + v] = s;
+}
+
+// c[j] = BT[e][j] - sum_l t_l Vg[l][j]  (t from the look-ahead kernel).
+__global__ void k_md_c(WalkerDev w, MdDev md, int np, int k, int e) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= np) return;
+    const double *bt = static_cast<const double *>(w.bt), *vg = static_cast<const double *>(w.vg);
+    double s = bt[(size_t)e * np + j];
+    for (int l = 0; l < k; ++l) s -= w.t[l] * vg[(size_t)l * np + j];
+    md.c[j] = s;
+}
+
+// x[v] = (vphi[v] - sum_j phi_j T[j][v]) / R, one workgroup per v.
+__global__ __launch_bounds__(kThreads) void k_md_x(WalkerDev w, MdDev md, int n) {
+    __shared__ double sbuf[1][kThreads / 64];
+    const int v = blockIdx.x;
+    double acc[1] = {0.0};
+    for (int j = threadIdx.x; j < n; j += kThreads) acc[0] += w.phi64[j] * md.t[(size_t)j * md.m + v];
+    block_sum_n<double, 1>(acc, sbuf);
+    if (threadIdx.x == 0) md.x[v] = (md.vphi[v] - acc[0]) / w.ratio[0];
+}
+
+// det of the order x order matrix S[a][b] = T[J_a][V_b] + (with_x ? c[J_a] x[V_b] : 0),
+// Gaussian elimination with partial pivoting.
+__device__ double md_det(const MdDev &md, int d, bool with_x) {
+    const int o = md.order[d];
+    double s[4][4];
+    for (int a = 0; a < o; ++a)
+        for (int b = 0; b < o; ++b) {
+            const int j = md.occ[4 * d + a], v = md.virt[4 * d + b];
+            s[a][b] = md.t[(size_t)j * md.m + v] + (with_x ? md.c[j] * md.x[v] : 0.0);
+        }
+    double det = 1.0;
+    for (int p = 0; p < o; ++p) {
+        int r = p;
+        for (int a = p + 1; a < o; ++a)
+            if (fabs(s[a][p]) > fabs(s[r][p])) r = a;
+        if (s[r][p] == 0.0) return 0.0;
+        if (r != p) {
+            for (int b = 0; b < o; ++b) {
+                const double tmp = s[p][b];
+                s[p][b] = s[r][b];
+                s[r][b] = tmp;
+            }
+            det = -det;
+        }
+        det *= s[p][p];
+        for (int a = p + 1; a < o; ++a) {
+            const double f = s[a][p] / s[p][p];
+            for (int b = p + 1; b < o; ++b) s[a][b] -= f * s[p][b];
+        }
+    }
+    return det;
+}
+
+// One workgroup: Q = sum_I c_I det S_I (mode 0: the proposal, with the
+// rank-1 term; mode 1: the present table).
+__global__ __launch_bounds__(kThreads) void k_md_sum(WalkerDev w, MdDev md, int mode, unsigned tag) {
+    __shared__ double sbuf[1][kThreads / 64];
+    double acc[1] = {0.0};
+    for (int d = threadIdx.x; d < md.ndet; d += kThreads) acc[0] += md.coef[d] * md_det(md, d, mode == 0);
+    block_sum_n<double, 1>(acc, sbuf);
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            const double r = w.ratio[0];
+            md.q[0] = acc[0];
+            w.ratio_host[0] = r * acc[0] / md.q[1];
+            w.ratio_host[1] = r;
+        } else {
+            md.q[1] = acc[0];
+        }
+        w.ratio_host[2] = acc[0];
+        __threadfence_system();
+        w.ratio_host[4] = (double)tag;
+    }
+}
+
+// T += c x^T; V[e] = vphi; Q = Q'.
+__global__ void k_md_accept(MdDev md, int n, int e) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, v = blockIdx.y;
+    if (j < n) md.t[(size_t)j * md.m + v] += md.c[j] * md.x[v];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        md.v[(size_t)e * md.m + v] = md.vphi[v];
+        if (v == 0) md.q[1] = md.q[0];
+    }
+}
+
+hipError_t launch_md_table(const WalkerDev *wd, const MdDev *md, int n, int np, hipStream_t s) {
+    hipLaunchKernelGGL(k_md_table, dim3((n + 255) / 256, md->m), dim3(256), 0, s, (const double *)wd->bt, *md, n, np);
+    return hipGetLastError();
+}
+
+hipError_t launch_md_propose(const WalkerDev *wd, const MdDev *md, int n, int np, int k, int e, unsigned tag,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_md_c, dim3((np + 255) / 256), dim3(256), 0, s, *wd, *md, np, k, e);
+    hipLaunchKernelGGL(k_md_x, dim3(md->m), dim3(kThreads), 0, s, *wd, *md, n);
+    hipLaunchKernelGGL(k_md_sum, dim3(1), dim3(kThreads), 0, s, *wd, *md, 0, tag);
+    return hipGetLastError();
+}
+
+hipError_t launch_md_init(const WalkerDev *wd, const MdDev *md, unsigned tag, hipStream_t s) {
+    hipLaunchKernelGGL(k_md_sum, dim3(1), dim3(kThreads), 0, s, *wd, *md, 1, tag);
+    return hipGetLastError();
+}
+
+hipError_t launch_md_accept(const MdDev *md, int n, int np, int e, hipStream_t s) {
+    (void)np;
+    hipLaunchKernelGGL(k_md_accept, dim3((n + 255) / 256, md->m), dim3(256), 0, s, *md, n, e);
+    return hipGetLastError();
+}
+
 // Row conversion: FP64 -> T (is_float = 1: float, else copy) into dst,
 // zero padded to np; or, with is_float = 2, float src -> FP64 dst.
 __global__ void k_row_convert(const void *src, void *dst, int mode, int n, int np) {

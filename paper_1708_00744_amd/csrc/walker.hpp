@@ -25,6 +25,21 @@ struct WalkerDev {
     int ldc;           // kp + 1
 };
 
+// Multideterminant state of an FP64 walker (single-reference expansion).
+struct MdDev {
+    double *v;      // np x m: virtual orbitals, row i = electron i (zero rows past n)
+    double *t;      // np x m: table T = A^{-1} V (row j = occupied orbital j)
+    double *c;      // np: column e of the current inverse (look-ahead corrected)
+    double *vphi;   // m: virtual row of the proposal
+    double *x;      // m: (vphi - phi T) / R
+    int *order;     // ndet: substitutions per determinant (0..4)
+    int *occ;       // ndet x 4: occupied orbitals replaced
+    int *virt;      // ndet x 4: virtual orbitals put in their place
+    double *coef;   // ndet
+    double *q;      // [0]: sum_I c_I det S_I of the pending proposal; [1]: of the present state
+    int m, ndet;
+};
+
 // Single-walker look-ahead ratio and accept (bordering).
 // grad_mode 0: ratio; 1: ratio and its gradient; 2: gradient of the present
 // row only (m = pending slot held by e, or -1).  The results are written to
@@ -40,5 +55,16 @@ hipError_t launch_row_to(const double *src, void *dst, int mode, int n, int np, 
 // count FP64 values from mapped pinned host memory (device address) into
 // dst64 and, if dst32 is not NULL, their float casts into dst32.
 hipError_t launch_rows_from_host(const double *src_mapped, double *dst64, float *dst32, int count, hipStream_t s);
+// Multideterminant steps (FP64).  table: T = BT^T V.  propose: after the
+// look-ahead kernel (ratio R and t in *wd), c = BT[e] - sum_j t_j Vg[j], x =
+// (vphi - phi T) / R, Q' = sum_I c_I det(S_I + c_J x_V) -> ratio_host[0..2] =
+// (R Q' / Q, R, Q'), then `tag` to ratio_host[4].  init: Q = sum_I c_I det S_I
+// of the present table -> q[1] and ratio_host[2], then the tag.  accept:
+// T += c x, V[e] = vphi, Q = Q'.
+hipError_t launch_md_table(const WalkerDev *wd, const MdDev *md, int n, int np, hipStream_t s);
+hipError_t launch_md_propose(const WalkerDev *wd, const MdDev *md, int n, int np, int k, int e, unsigned tag,
+                             hipStream_t s);
+hipError_t launch_md_init(const WalkerDev *wd, const MdDev *md, unsigned tag, hipStream_t s);
+hipError_t launch_md_accept(const MdDev *md, int n, int np, int e, hipStream_t s);
 
 }  // namespace dsu

@@ -70,6 +70,9 @@ SIGNATURES = {
     "dsu_get_logdet": (C.c_int, [_vp, _pd, _pi32]),
     "dsu_walker_pending": (C.c_int, [_vp, _pi32]),
     "dsu_walker_set_flush_kernel": (C.c_int, [_vp, _i32]),
+    "dsu_walker_set_multidet": (C.c_int, [_vp, _i32, _pd, _i32, _pi32, _pi32, _pi32, _pd]),
+    "dsu_propose_ratio_md": (C.c_int, [_vp, _i32, _pd, _pd, _pd, _pd]),
+    "dsu_walker_md_value": (C.c_int, [_vp, _pd, _pi32]),
     "dsu_zwalker_create": (C.c_int, [_i32, _i32, _i32, _pd, _vp, _pvp]),
     "dsu_zwalker_destroy": (C.c_int, [_vp]),
     "dsu_zpropose_ratio": (C.c_int, [_vp, _i32, _pd, _pd]),
@@ -213,6 +216,36 @@ class Walker:
         g = np.zeros(3)
         _check(lib().dsu_eval_grad(self._h, int(electron), _dp(_f64(drows, (3, self.n))), _dp(g)))
         return g
+
+    def set_multidet(self, virt, dets):
+        """virt: (n, m) virtual orbitals at every electron; dets: list of
+        (coef, [(occ, virt), ...]) with up to 4 substitutions each."""
+        v = _f64(virt)
+        nd = len(dets)
+        order = np.zeros(nd, np.int32)
+        occ = np.zeros((nd, 4), np.int32)
+        vir = np.zeros((nd, 4), np.int32)
+        coef = np.zeros(nd)
+        for d, (c, subs) in enumerate(dets):
+            if len(subs) > 4:
+                raise ValueError("at most 4 substitutions per determinant")
+            order[d], coef[d] = len(subs), c
+            for q, (j, vv) in enumerate(subs):
+                occ[d, q], vir[d, q] = j, vv
+        _check(lib().dsu_walker_set_multidet(self._h, v.shape[1], _dp(v), nd, order.ctypes.data_as(_pi32),
+                                             occ.ctypes.data_as(_pi32), vir.ctypes.data_as(_pi32), _dp(coef)))
+
+    def propose_md(self, electron, row, vrow):
+        """(Psi ratio, reference ratio) for moving `electron`; stays pending."""
+        r, r0 = C.c_double(), C.c_double()
+        _check(lib().dsu_propose_ratio_md(self._h, int(electron), _dp(_f64(row)), _dp(_f64(vrow)), C.byref(r),
+                                          C.byref(r0)))
+        return r.value, r0.value
+
+    def md_value(self):
+        la, sg = C.c_double(), C.c_int32()
+        _check(lib().dsu_walker_md_value(self._h, C.byref(la), C.byref(sg)))
+        return sg.value, la.value
 
     def accept(self):
         _check(lib().dsu_accept(self._h))
