@@ -459,9 +459,22 @@ def cpu_baseline(n=4096, sigma=0.002, target_s=15.0):
     _, used = oracle.walkers_moves(n, BOX_L, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, 0, 4, m,
                                    pos, a, ainv)
     dt = time.perf_counter() - t0
+    # one thread, one walker: the next 24 moves of walker 0
+    t1 = time.perf_counter()
+    e1 = min(4 + m, n - 24)
+    oracle.walkers_moves(n, BOX_L, [1000], [0], sigma, 0, e1, 24, pos[:1].copy(), a[:1].copy(), ainv[:1].copy())
+    single = 24 / (time.perf_counter() - t1)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": walkers * m / dt, "unit": "moves/s", "cores": int(used), "kind": "oracle",
             "sample": f"{walkers} walkers x {m} moves of sweep 0 at N={n} (FP64 Sherman-Morrison, one OpenMP thread "
                       f"per walker, set-up by LAPACK inverse not timed)",
+            "single_thread_moves_per_s": single,
+            "host": {"nproc": os.cpu_count(), "cpu": model},
             "walker_forms": cpu_baseline_walkers()}
 
 
