@@ -56,9 +56,23 @@ __global__ __launch_bounds__(kThreads) void k_flush_stream(const DetDesc<T> *__r
     DSU_GLOBAL T *y = gmem(dd.y);
 
     // W = (y - E) C^{-T} for this block's 64 rows
-    for (int v = tid; v < 64 * KP; v += kThreads) {
-        const int i = v / KP, j = v % KP;
-        lds[i * LDY + j] = y[(size_t)(r0 + i) * kp + j];
+    {
+        // loads in batches of 8 before their stores
+        constexpr int NYL = 64 * KP / kThreads, NB = NYL < 8 ? NYL : 8;
+#pragma unroll
+        for (int q0 = 0; q0 < NYL; q0 += NB) {
+            T yv[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int v = tid + (q0 + q) * kThreads, i = v / KP, j = v % KP;
+                yv[q] = y[(size_t)(r0 + i) * kp + j];
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int v = tid + (q0 + q) * kThreads, i = v / KP, j = v % KP;
+                lds[i * LDY + j] = yv[q];
+            }
+        }
     }
     __syncthreads();
     for (int j = tid; j < kslots; j += kThreads) {
@@ -244,6 +258,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_flush_stream32(const DetDesc<fl
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         const int h0 = 64 * half;
+        // (element by element: batching these loads as well pushes the K = 128
+        // kernel past its register budget and costs more in the main loop)
         for (int v = tid; v < 64 * KP; v += kThreads) {
             const int i = v / KP, j = v % KP;
             lds[i * LDY + j] = h0 + i < rows ? y[(size_t)(r0 + h0 + i) * kp + j] : 0.0f;

@@ -176,9 +176,25 @@ __global__ __launch_bounds__(kThreads, X6Cfg<KP>::occ) void k_flush_stream_x6(
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         const int h0 = 64 * half;
-        for (int v = tid; v < 64 * KP; v += kThreads) {
-            const int i = v / KP, j = v % KP;
-            lds[i * LDY + j] = h0 + i < rows ? y[(size_t)(r0 + h0 + i) * kp + j] : 0.0f;
+        {
+            // loads in batches of 8 before their stores; rows past the block read row r0
+            constexpr int NYL = 64 * KP / kThreads, NB = NYL < 8 ? NYL : 8;
+#pragma unroll
+            for (int q0 = 0; q0 < NYL; q0 += NB) {
+                float yv[NB];
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    const int v = tid + (q0 + q) * kThreads, i = v / KP, j = v % KP;
+                    const bool in = h0 + i < rows;
+                    yv[q] = y[(size_t)(r0 + (in ? h0 + i : 0)) * kp + j];
+                    if (!in) yv[q] = 0.0f;
+                }
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    const int v = tid + (q0 + q) * kThreads, i = v / KP, j = v % KP;
+                    lds[i * LDY + j] = yv[q];
+                }
+            }
         }
         __syncthreads();
         for (int j = tid; j < kslots; j += kThreads) {

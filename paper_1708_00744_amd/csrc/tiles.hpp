@@ -150,10 +150,26 @@ __device__ __forceinline__ void w_from_y(const T *ylds, int ldy, const double *_
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int t = 0; t < KP / 16; ++t) wacc[t] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    // loads issued in batches of up to 8 before their stores (not one wait per element)
+    constexpr int NL = (KP * JC + kThreads - 1) / kThreads;
+    constexpr int NB = NL < 8 ? NL : 8;
+    DSU_GLOBAL const double *cg = (DSU_GLOBAL const double *)cinv;
     for (int j0 = 0; j0 < KP; j0 += JC) {
-        for (int v = tid; v < KP * JC; v += kThreads) {
-            const int l = v / JC, jj = v % JC, j = j0 + jj;
-            cbuf[l * LDC + jj] = (l < kslots && j < kslots) ? T(cinv[(size_t)l * ldc + j]) : T(0);
+#pragma unroll
+        for (int q0 = 0; q0 < NL; q0 += NB) {
+            double cv[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int v = tid + (q0 + q) * kThreads, l = v / JC, jj = v % JC, j = j0 + jj;
+                const bool in = v < KP * JC && l < kslots && j < kslots;
+                cv[q] = cg[in ? (size_t)l * ldc + j : 0];
+                if (!in) cv[q] = 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int v = tid + (q0 + q) * kThreads, l = v / JC, jj = v % JC;
+                if (v < KP * JC) cbuf[l * LDC + jj] = T(cv[q]);
+            }
         }
         __syncthreads();
 #pragma unroll
