@@ -274,6 +274,13 @@ int dsu_batch_recompute(dsu_batch *b, double *drift_out);
 /* Per determinant d = w*spins + s: running log|det|, sign, accepted moves,
  * completed sweeps.  Any pointer may be NULL.  Synchronises. */
 int dsu_batch_stats(dsu_batch *b, double *logdet, int32_t *sign, int64_t *accepted, int64_t *sweeps_done);
+/* Resume: set every determinant's completed-sweep count, which keys the
+ * random stream of its next sweep (Philox counter word 0).  A checkpoint is
+ * {positions (dsu_batch_get_positions), seeds, walker ids, sweeps done}; a
+ * batch created from it (fresh FP64 inverses) and set to the same count
+ * proposes and draws exactly what the uninterrupted batch would.  Takes
+ * effect at the next sweep.  DSU_EINVAL for a negative count. */
+int dsu_batch_set_sweep(dsu_batch *b, int64_t sweeps_done);
 /* Current positions of determinant d (n*3 FP64). */
 int dsu_batch_get_positions(dsu_batch *b, int32_t det, double *out_host);
 /* A^{-1} of determinant d, natural layout (n*n FP64, from the device copy). */

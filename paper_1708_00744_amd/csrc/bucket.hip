@@ -12,6 +12,7 @@
 #include "bucket.hpp"
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 
@@ -672,6 +673,18 @@ extern "C" int dsu_batch_stats(dsu_batch *b, double *logdet, int32_t *sign, int6
         if (sign) sign[i] = st.sign;
         if (accepted) accepted[i] = st.accepted;
         if (sweeps_done) sweeps_done[i] = st.sweep;
+    }
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_set_sweep(dsu_batch *b, int64_t sweeps_done) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (sweeps_done < 0) return fail(DSU_EINVAL, "sweeps_done %lld < 0", (long long)sweeps_done);
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    for (int i = 0; i < b->ndet; ++i) {
+        const long long v = sweeps_done;
+        HIPCHK(hipMemcpy(reinterpret_cast<char *>(b->bk.dets[i].st) + offsetof(DetState, sweep), &v, sizeof(v),
+                         hipMemcpyHostToDevice));
     }
     return DSU_OK;
 }

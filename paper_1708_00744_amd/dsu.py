@@ -90,6 +90,7 @@ SIGNATURES = {
     "dsu_batch_recompute": (C.c_int, [_vp, _pd]),
     "dsu_batch_stats": (C.c_int, [_vp, _pd, _pi32, _pi64, _pi64]),
     "dsu_batch_get_positions": (C.c_int, [_vp, _i32, _pd]),
+    "dsu_batch_set_sweep": (C.c_int, [_vp, _i64]),
     "dsu_batch_get_inverse": (C.c_int, [_vp, _i32, _pd]),
     "dsu_batch_set_trace": (C.c_int, [_vp, _i32]),
     "dsu_batch_get_trace": (C.c_int, [_vp, _i32, _pd, _pu8]),
@@ -406,6 +407,10 @@ class Batch:
         _check(lib().dsu_batch_stats(self._h, _dp(ld), sg.ctypes.data_as(_pi32), acc.ctypes.data_as(_pi64),
                                      sw.ctypes.data_as(_pi64)))
         return {"logdet": ld, "sign": sg, "accepted": acc, "sweeps": sw}
+
+    def set_sweep(self, sweeps_done):
+        """Resume a checkpoint: the next sweep draws as sweep `sweeps_done`."""
+        _check(lib().dsu_batch_set_sweep(self._h, int(sweeps_done)))
 
     def positions(self, det):
         out = np.zeros((self.n, 3))

@@ -319,3 +319,40 @@ def test_two_window_schedules_agree(prec, n, K):
             assert rel_err(r0[:m], r1[:m], FP64_FLOOR).max() < 1e-11
         else:
             assert_fp32_ratio_stats(rel_err(r0[:m], r1[:m]))
+
+
+@pytest.mark.parametrize("prec", [dsu.FP64, dsu.FP32_MIXED])
+def test_checkpoint_resume(prec):
+    """Stop after 2 sweeps, keep {positions, seeds, walker ids, sweeps done},
+    start a new batch from it (fresh inverses) and run 2 more: the same
+    proposals and decisions as 4 uninterrupted sweeps (ratios to rounding)."""
+    require_gpu()
+    n, walkers, K, sigma = 96, 2, 16, 0.2
+    p0 = burned_in(n, walkers, 1, 61)
+    b, _ = make_batch(n, walkers, 1, K, prec, sigma, seed=61, pos=p0)
+    b.set_trace(4)
+    b.sweep(4)
+    full = [b.trace(w) for w in range(walkers)]
+    end = np.stack([b.positions(w) for w in range(walkers)])
+    b.close()
+    b, _ = make_batch(n, walkers, 1, K, prec, sigma, seed=61, pos=p0)
+    b.sweep(2)
+    ck = np.stack([b.positions(w) for w in range(walkers)])
+    b.close()
+    b2, _ = make_batch(n, walkers, 1, K, prec, sigma, seed=61, pos=ck.reshape(walkers, 1, n, 3))
+    b2.set_sweep(2)
+    b2.set_trace(2)
+    b2.sweep(2)
+    assert list(b2.stats()["sweeps"]) == [4] * walkers
+    for w in range(walkers):
+        r, a = full[w]
+        r2, a2 = b2.trace(w)
+        r, a = r[2 * n:], a[2 * n:]
+        m = len(a) if np.array_equal(a, a2) else int(np.nonzero(a != a2)[0][0])
+        if prec == dsu.FP64:
+            assert m == len(a) and rel_err(r2, r, FP64_FLOOR).max() < 1e-10
+            np.testing.assert_allclose(b2.positions(w), end[w], rtol=0, atol=0)
+        else:
+            assert m > n
+            assert_fp32_ratio_stats(rel_err(r2[:m], r[:m]))
+    b2.close()
