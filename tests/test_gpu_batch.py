@@ -356,3 +356,24 @@ def test_checkpoint_resume(prec):
             assert m > n
             assert_fp32_ratio_stats(rel_err(r2[:m], r[:m]))
     b2.close()
+
+
+@pytest.mark.parametrize("prec,K", [(dsu.FP64, 32), (dsu.FP32_MIXED, 64), (dsu.FP32_MIXED, 128)])
+def test_runs_are_bitwise_deterministic(prec, K):
+    """Two eager runs of the same inputs give bit-identical ratios, decisions,
+    positions and log-determinants (no order-dependent reductions or races
+    between workgroups, streams or the side-stream proposals)."""
+    require_gpu()
+    n, walkers = 192, 3
+    outs = []
+    for _ in range(2):
+        b, _ = make_batch(n, walkers, 1, K, prec, 0.2, seed=71)
+        b.set_trace(2)
+        b.sweep(2)
+        outs.append(([b.trace(w) for w in range(walkers)], [b.positions(w) for w in range(walkers)], b.stats()))
+        b.close()
+    (t0, p0, s0), (t1, p1, s1) = outs
+    for w in range(walkers):
+        assert np.array_equal(t0[w][0], t1[w][0]) and np.array_equal(t0[w][1], t1[w][1])
+        assert np.array_equal(p0[w], p1[w])
+    assert np.array_equal(s0["logdet"], s1["logdet"]) and np.array_equal(s0["accepted"], s1["accepted"])
