@@ -281,6 +281,16 @@ int dsu_batch_stats(dsu_batch *b, double *logdet, int32_t *sign, int64_t *accept
  * proposes and draws exactly what the uninterrupted batch would.  Takes
  * effect at the next sweep.  DSU_EINVAL for a negative count. */
 int dsu_batch_set_sweep(dsu_batch *b, int64_t sweeps_done);
+/* Watchdog (enable = 1): after every sweep, determinants that met a zero or
+ * non-finite ratio during it get a fresh FP64 inverse from their positions
+ * (dsu_batch_recompute of those members only); the others are untouched.
+ * Costs one synchronisation per sweep.  dsu_batch_watchdog_count reports the
+ * number of such recomputes so far. */
+int dsu_batch_set_watchdog(dsu_batch *b, int32_t enable);
+int dsu_batch_watchdog_count(dsu_batch *b, int64_t *recomputes);
+/* Fault injection for tests of the failure handling: overwrite row `row` of
+ * determinant `det`'s device inverse with NaN.  Synchronises. */
+int dsu_batch_poison_row(dsu_batch *b, int32_t det, int32_t row);
 /* Current positions of determinant d (n*3 FP64). */
 int dsu_batch_get_positions(dsu_batch *b, int32_t det, double *out_host);
 /* A^{-1} of determinant d, natural layout (n*n FP64, from the device copy). */

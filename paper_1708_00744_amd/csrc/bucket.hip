@@ -544,7 +544,21 @@ struct dsu_batch {
     long long trace_cap = 0;
     double *inv_tmp = nullptr;
     long long sweeps_done = 0;
+    // watchdog: recompute members whose count of zero / non-finite ratios grew
+    bool watchdog = false;
+    std::vector<int> bad_seen;
+    long long watchdog_recomputes = 0;
 };
+
+static int batch_read_bad(dsu_batch *b, std::vector<int> *bad) {
+    bad->resize(b->ndet);
+    for (int i = 0; i < b->ndet; ++i) {
+        DetState st;
+        HIPCHK(hipMemcpy(&st, b->bk.dets[i].st, sizeof(st), hipMemcpyDeviceToHost));
+        (*bad)[i] = st.bad;
+    }
+    return DSU_OK;
+}
 
 static void batch_free(dsu_batch *b) {
     b->bk.release();
@@ -642,7 +656,44 @@ extern "C" int dsu_batch_sweep(dsu_batch *b, int32_t sweeps, int32_t force_accep
             CHK(b->bk.recompute(all_indices(b->ndet), nullptr));
         CHK(b->bk.sweep(force_accept ? 1 : 0));
         ++b->sweeps_done;
+        if (b->watchdog) {
+            HIPCHK(hipStreamSynchronize(b->bk.stream));
+            std::vector<int> bad, which;
+            CHK(batch_read_bad(b, &bad));
+            for (int i = 0; i < b->ndet; ++i)
+                if (bad[i] > b->bad_seen[i]) which.push_back(i);
+            if (!which.empty()) {
+                CHK(b->bk.recompute(which, nullptr));
+                b->watchdog_recomputes += (long long)which.size();
+            }
+            b->bad_seen = bad;
+        }
     }
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_set_watchdog(dsu_batch *b, int32_t enable) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    b->watchdog = enable != 0;
+    if (b->watchdog) CHK(batch_read_bad(b, &b->bad_seen));
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_watchdog_count(dsu_batch *b, int64_t *recomputes) {
+    if (!b || !recomputes) return fail(DSU_EINVAL, "NULL argument");
+    *recomputes = b->watchdog_recomputes;
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_poison_row(dsu_batch *b, int32_t det, int32_t row) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (det < 0 || det >= b->ndet) return fail(DSU_EINVAL, "det %d out of range", det);
+    if (row < 0 || row >= b->bk.sh.n) return fail(DSU_EINVAL, "row %d out of range", row);
+    const size_t es = elem_size(b->bk.sh.prec), np = b->bk.sh.np;
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    // all-ones bytes: a NaN in either precision
+    HIPCHK(hipMemset(static_cast<char *>(b->bk.dets[det].bt) + (size_t)row * np * es, 0xff, np * es));
     return DSU_OK;
 }
 

@@ -91,6 +91,9 @@ SIGNATURES = {
     "dsu_batch_stats": (C.c_int, [_vp, _pd, _pi32, _pi64, _pi64]),
     "dsu_batch_get_positions": (C.c_int, [_vp, _i32, _pd]),
     "dsu_batch_set_sweep": (C.c_int, [_vp, _i64]),
+    "dsu_batch_set_watchdog": (C.c_int, [_vp, _i32]),
+    "dsu_batch_watchdog_count": (C.c_int, [_vp, _pi64]),
+    "dsu_batch_poison_row": (C.c_int, [_vp, _i32, _i32]),
     "dsu_batch_get_inverse": (C.c_int, [_vp, _i32, _pd]),
     "dsu_batch_set_trace": (C.c_int, [_vp, _i32]),
     "dsu_batch_get_trace": (C.c_int, [_vp, _i32, _pd, _pu8]),
@@ -407,6 +410,18 @@ class Batch:
         _check(lib().dsu_batch_stats(self._h, _dp(ld), sg.ctypes.data_as(_pi32), acc.ctypes.data_as(_pi64),
                                      sw.ctypes.data_as(_pi64)))
         return {"logdet": ld, "sign": sg, "accepted": acc, "sweeps": sw}
+
+    def set_watchdog(self, enable):
+        _check(lib().dsu_batch_set_watchdog(self._h, int(bool(enable))))
+
+    def watchdog_count(self):
+        c = C.c_int64()
+        _check(lib().dsu_batch_watchdog_count(self._h, C.byref(c)))
+        return c.value
+
+    def poison_row(self, det, row):
+        """Test aid: NaN into one row of a determinant's device inverse."""
+        _check(lib().dsu_batch_poison_row(self._h, int(det), int(row)))
 
     def set_sweep(self, sweeps_done):
         """Resume a checkpoint: the next sweep draws as sweep `sweeps_done`."""

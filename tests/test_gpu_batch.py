@@ -377,3 +377,39 @@ def test_runs_are_bitwise_deterministic(prec, K):
         assert np.array_equal(t0[w][0], t1[w][0]) and np.array_equal(t0[w][1], t1[w][1])
         assert np.array_equal(p0[w], p1[w])
     assert np.array_equal(s0["logdet"], s1["logdet"]) and np.array_equal(s0["accepted"], s1["accepted"])
+
+
+def test_watchdog_recovers_poisoned_determinant():
+    """A NaN row injected into one determinant's inverse: its ratios turn
+    non-finite and are refused, the watchdog gives it a fresh inverse from its
+    positions after that sweep, and its neighbours run exactly as without the
+    fault (the failure forced from the host, the kernels run normally)."""
+    require_gpu()
+    n, walkers, K = 128, 3, 16
+    p0 = burned_in(n, walkers, 1, 81)
+    ref, _ = make_batch(n, walkers, 1, K, dsu.FP64, 0.2, seed=81, pos=p0)
+    ref.set_trace(3)
+    ref.sweep(3)
+    rt = [ref.trace(w) for w in range(walkers)]
+    ref.close()
+    b, _ = make_batch(n, walkers, 1, K, dsu.FP64, 0.2, seed=81, pos=p0)
+    b.set_trace(3)
+    b.set_watchdog(True)
+    b.sweep(1)
+    assert b.watchdog_count() == 0
+    b.poison_row(1, 5)
+    b.sweep(2)
+    assert b.watchdog_count() >= 1
+    st = b.stats()
+    assert np.all(np.isfinite(st["logdet"]))
+    for w in (0, 2):
+        t = b.trace(w)
+        assert np.array_equal(t[0], rt[w][0]) and np.array_equal(t[1], rt[w][1])
+    a_end = oracle.pw_matrix(oracle.pw_kvectors(n), L, b.positions(1))
+    assert np.abs(b.inverse(1) @ a_end - np.eye(n)).max() < 1e-9
+    s_np, l_np = np.linalg.slogdet(a_end)
+    assert st["sign"][1] == s_np and abs(st["logdet"][1] - l_np) < 1e-8
+    with pytest.raises(dsu.DsuError) as ex:
+        b.poison_row(walkers, 0)
+    assert ex.value.code == dsu.EINVAL
+    b.close()
