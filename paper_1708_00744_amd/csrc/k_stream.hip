@@ -258,11 +258,24 @@ __global__ __launch_bounds__(kThreads, 2) void k_flush_stream32(const DetDesc<fl
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         const int h0 = 64 * half;
-        // (element by element: batching these loads as well pushes the K = 128
-        // kernel past its register budget and costs more in the main loop)
-        for (int v = tid; v < 64 * KP; v += kThreads) {
-            const int i = v / KP, j = v % KP;
-            lds[i * LDY + j] = h0 + i < rows ? y[(size_t)(r0 + h0 + i) * kp + j] : 0.0f;
+        {
+            // 16-byte loads, all in flight before their stores (scalar loads
+            // batched the same way cost the K = 128 kernel registers it has not
+            // got); rows past the block read row r0 and are zeroed
+            constexpr int NQ = 16 * KP / kThreads;
+            f32x4 yv[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int v = tid + q * kThreads, i = v / (KP / 4), jq = v % (KP / 4);
+                const bool in = h0 + i < rows;
+                yv[q] = *(DSU_GLOBAL const f32x4 *)(y + (size_t)(r0 + (in ? h0 + i : 0)) * kp + 4 * jq);
+                if (!in) yv[q] = f32x4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int v = tid + q * kThreads, i = v / (KP / 4), jq = v % (KP / 4);
+                *reinterpret_cast<f32x4 *>(lds + i * LDY + 4 * jq) = yv[q];
+            }
         }
         __syncthreads();
         for (int j = tid; j < kslots; j += kThreads) {
