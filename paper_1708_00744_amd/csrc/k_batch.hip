@@ -16,6 +16,9 @@
 #include "dsu_internal.hpp"
 #include "tiles.hpp"
 
+#include <type_traits>
+#include <utility>
+
 namespace dsu {
 
 // ------------------------------------------------------------ random stream
@@ -462,11 +465,18 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
 // at K = 128), in registers (the loop over slots is unrolled, so every
 // register index is fixed).  A step is one LDS exchange of the pivot row and
 // one barrier; the pivot column comes from one lane of each wave.
+// Calls f(integral_constant<int, I>) for I = 0, 1, ... in order.
+template <int... I, typename F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &&f) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__restrict__ descs, int kp, int e0,
                                                           int kw, int nsplit, int force_accept, int last_window,
                                                           int g_from_y, int pbuf) {
     constexpr int RW = KP / 4, CPL = KP > 64 ? KP / 64 : 1, NC = 64 * CPL;
+    static_assert(KP >= 16 && KP <= 128 && RW % 2 == 0, "window tile");
     __shared__ double s_row[2][NC];
     __shared__ double s_u[KP], s_ratio[KP];
     __shared__ int s_ok[KP];
@@ -492,59 +502,82 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
         s_u[a] = a < kw ? (pbuf ? d.prop2 : d.prop)[4 * a + 3] : 0.0;
         s_ok[a] = 0;
     }
+    __syncthreads();
     // |prod R| kept as mantissa * 2^exponent; one log at the end
     int m = 0, sgn = 1, bad = 0, pexp = 0;
     double pman = 1.0;
-#pragma unroll 1
-    for (int jb = 0; jb < 4; ++jb) {
-#pragma clang loop unroll(full)
-        for (int jj = 0; jj < RW; ++jj) {
-            const int j = jb * RW + jj;
-            if (j < kw) {
-                double *row = s_row[j & 1];
-                if (wave == jb)
+    // One step: slot j = jb * RW + JJ, whose pivot column lies in column half
+    // JH.  Both are compile-time constants, so every register index is fixed
+    // and each row needs one select (clearing the pivot column's entry in lane
+    // j & 63 before the update) and one FMA per column half.
+    auto step = [&](auto jh_c, auto jj_c, int jb) __attribute__((always_inline)) {
+        constexpr int JH = decltype(jh_c)::value, JJ = decltype(jj_c)::value;
+        const int j = jb * RW + JJ;
+        if (j >= kw) return;
+        double *row = s_row[JJ & 1];  // RW is even, so j & 1 == JJ & 1
+        const double uj = s_u[j];     // read-only after the set-up barrier
+        if (wave == jb)
 #pragma unroll
-                    for (int h = 0; h < CPL; ++h) row[lane + 64 * h] = g[jj][h];
-                __syncthreads();
-                const double r = row[j];
-                const bool finite_nz = fabs(r) > RatioFloor<T>::value && fabs(r) <= 1.7976931348623157e308;
-                const bool ok = finite_nz && (force_accept || s_u[j] < r * r);
-                if (!finite_nz) ++bad;
-                if (tid == 0) {
-                    s_ratio[j] = r;
-                    s_ok[j] = ok;
-                }
-                if (ok) {
-                    const double dinv = 1.0 / r;
-                    const int jl = j & 63, jh = j >> 6;  // lane and column half holding column j
-                    double rj[CPL];
+            for (int h = 0; h < CPL; ++h) row[lane + 64 * h] = g[JJ][h];
+        __syncthreads();
+        // the whole pivot row in one LDS round trip
+        double rv[CPL];
 #pragma unroll
-                    for (int h = 0; h < CPL; ++h) rj[h] = lane + 64 * h == j ? dinv : row[lane + 64 * h] * dinv;
+        for (int h = 0; h < CPL; ++h) rv[h] = row[lane + 64 * h];
+        const double r = row[j];
+        const bool finite_nz = fabs(r) > RatioFloor<T>::value && fabs(r) <= 1.7976931348623157e308;
+        const bool ok = finite_nz && (force_accept || uj < r * r);
+        if (!finite_nz) ++bad;
+        if (tid == 0) {
+            s_ratio[j] = r;
+            s_ok[j] = ok;
+        }
+        if (!ok) return;
+        const double dinv = 1.0 / r;
+        const int jl = j & 63;
+        const bool pl = lane == jl, prow = wave == jb;
+        // Scaled pivot row (its own column becomes 1/r) and, for the other
+        // rows, new = a * g - f * c: in lane j & 63 of half JH a = -1/r and
+        // c = 0 (the pivot column's entry g = f becomes -f/r), elsewhere a = 1
+        // and c = row / r.  Both forms round exactly as -f/r and g - f * row/r.
+        double rj[CPL], c[CPL];
 #pragma unroll
-                    for (int q = 0; q < RW; ++q) {
-                        double gq = g[q][0];
+        for (int h = 0; h < CPL; ++h) {
+            rj[h] = (h == JH && pl) ? dinv : rv[h] * dinv;
+            c[h] = (h == JH && pl) ? 0.0 : rj[h];
+        }
+        const double a = pl ? -dinv : 1.0;
 #pragma unroll
-                        for (int h = 1; h < CPL; ++h) gq = jh == h ? g[q][h] : gq;
-                        const int lo = __builtin_amdgcn_readlane(__double2loint(gq), jl);
-                        const int hi = __builtin_amdgcn_readlane(__double2hiint(gq), jl);
-                        const double f = __hiloint2double(hi, lo);
-                        const bool pivot_row = wave * RW + q == j;
+        for (int q = 0; q < RW; ++q) {
+            const int lo = __builtin_amdgcn_readlane(__double2loint(g[q][JH]), jl);
+            const int hi = __builtin_amdgcn_readlane(__double2hiint(g[q][JH]), jl);
+            const double f = __hiloint2double(hi, lo);
 #pragma unroll
-                        for (int h = 0; h < CPL; ++h) {
-                            if (pivot_row) g[q][h] = rj[h];
-                            else g[q][h] = lane + 64 * h == j ? -f * dinv : g[q][h] - f * rj[h];
-                        }
-                    }
-                    int e;
-                    pman *= frexp(fabs(r), &e);
-                    pexp += e;
-                    pman = frexp(pman, &e);
-                    pexp += e;
-                    if (r < 0.0) sgn = -sgn;
-                    ++m;
-                }
+            for (int h = 0; h < CPL; ++h) {
+                const double t = h == JH ? a * g[q][h] : g[q][h];
+                const double u = __builtin_fma(-f, c[h], t);
+                g[q][h] = (q == JJ && prow) ? rj[h] : u;
             }
         }
+        int e;
+        pman *= frexp(fabs(r), &e);
+        pexp += e;
+        pman = frexp(pman, &e);
+        pexp += e;
+        if (r < 0.0) sgn = -sgn;
+        ++m;
+    };
+    // blocks of RW slots whose pivot columns lie in column half 0, then half 1
+    constexpr int NJB0 = CPL > 1 ? 2 : 4;
+#pragma unroll 1
+    for (int jb = 0; jb < NJB0; ++jb)
+        static_for(std::make_integer_sequence<int, RW>{},
+                   [&](auto jj) __attribute__((always_inline)) { step(std::integral_constant<int, 0>{}, jj, jb); });
+    if constexpr (CPL > 1) {
+#pragma unroll 1
+        for (int jb = NJB0; jb < 4; ++jb)
+            static_for(std::make_integer_sequence<int, RW>{},
+                       [&](auto jj) __attribute__((always_inline)) { step(std::integral_constant<int, 1>{}, jj, jb); });
     }
     const double logdet = log(pman) + (double)pexp * 0.69314718055994530942;
     __syncthreads();
