@@ -547,16 +547,26 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
             c[h] = (h == JH && pl) ? 0.0 : rj[h];
         }
         const double a = pl ? -dinv : 1.0;
+        // pivot-column entries of QB rows at a time, read before their updates
+        constexpr int QB = RW < 8 ? RW : 8;
 #pragma unroll
-        for (int q = 0; q < RW; ++q) {
-            const int lo = __builtin_amdgcn_readlane(__double2loint(g[q][JH]), jl);
-            const int hi = __builtin_amdgcn_readlane(__double2hiint(g[q][JH]), jl);
-            const double f = __hiloint2double(hi, lo);
+        for (int q0 = 0; q0 < RW; q0 += QB) {
+            double f[QB];
 #pragma unroll
-            for (int h = 0; h < CPL; ++h) {
-                const double t = h == JH ? a * g[q][h] : g[q][h];
-                const double u = __builtin_fma(-f, c[h], t);
-                g[q][h] = (q == JJ && prow) ? rj[h] : u;
+            for (int i = 0; i < QB; ++i) {
+                const int lo = __builtin_amdgcn_readlane(__double2loint(g[q0 + i][JH]), jl);
+                const int hi = __builtin_amdgcn_readlane(__double2hiint(g[q0 + i][JH]), jl);
+                f[i] = __hiloint2double(hi, lo);
+            }
+#pragma unroll
+            for (int i = 0; i < QB; ++i) {
+                const int q = q0 + i;
+#pragma unroll
+                for (int h = 0; h < CPL; ++h) {
+                    const double t = h == JH ? a * g[q][h] : g[q][h];
+                    const double u = __builtin_fma(-f[i], c[h], t);
+                    g[q][h] = (q == JJ && prow) ? rj[h] : u;
+                }
             }
         }
         int e;
