@@ -456,6 +456,12 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
     }
 }
 
+// Calls f(integral_constant<int, I>) for I = 0, 1, ... in order.
+template <int... I, typename F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &&f) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
 // The same decisions for windows of up to 128 slots as an in-place
 // Gauss-Jordan sweep over G in slot order, pivoting only on accepted slots:
 // before slot a is decided, G[a][a] has had every earlier accepted slot
@@ -465,12 +471,6 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
 // at K = 128), in registers (the loop over slots is unrolled, so every
 // register index is fixed).  A step is one LDS exchange of the pivot row and
 // one barrier; the pivot column comes from one lane of each wave.
-// Calls f(integral_constant<int, I>) for I = 0, 1, ... in order.
-template <int... I, typename F>
-__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &&f) {
-    (f(std::integral_constant<int, I>{}), ...);
-}
-
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__restrict__ descs, int kp, int e0,
                                                           int kw, int nsplit, int force_accept, int last_window,
