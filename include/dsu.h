@@ -300,10 +300,13 @@ int dsu_batch_get_inverse(dsu_batch *b, int32_t det, double *out_host);
  * ratio[sweeps*n] (FP64) and accepted[sweeps*n]. */
 int dsu_batch_set_trace(dsu_batch *b, int32_t sweeps);
 int dsu_batch_get_trace(dsu_batch *b, int32_t det, double *ratio_host, uint8_t *accepted_host);
-/* Kernel timing: when enabled, HIP events bracket every launch on the
- * batch's stream; dsu_batch_kernel_time returns (count, total ms) for one
- * phase: 0 proposals, 1 look-ahead products, 2 decisions, 3 flush,
- * 4 recompute. */
+/* Kernel timing: enable = 1 brackets every launch with HIP events on the
+ * stream it runs on, 2 only the flush launches (phase 3: fewer events
+ * between kernels, so the rest of the sweep runs as untimed), 0 none (and
+ * sweeps may replay a captured graph again); any other value is DSU_EINVAL.
+ * Each call clears the totals.  dsu_batch_kernel_time returns (count,
+ * total ms) for one phase: 0 proposals, 1 look-ahead products, 2 decisions,
+ * 3 flush, 4 recompute. */
 int dsu_batch_set_timing(dsu_batch *b, int32_t enable);
 int dsu_batch_kernel_time(dsu_batch *b, int32_t phase, int64_t *launches, double *total_ms);
 /* Capture one sweep into a hipGraph and replay it for dsu_batch_sweep

@@ -251,7 +251,8 @@ void Bucket::drop_graph() {
 template <typename F> int Bucket::timed(int phase, F fn, hipStream_t on) {
     if (!on) on = stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timing) {
+    const bool ev = timing == 1 || (timing == 2 && phase == PH_FLUSH);
+    if (ev) {
         for (hipEvent_t *e : {&e0, &e1}) {
             if (!ev_free_.empty()) {
                 *e = ev_free_.back();
@@ -263,7 +264,7 @@ template <typename F> int Bucket::timed(int phase, F fn, hipStream_t on) {
         HIPCHK(hipEventRecord(e0, on));
     }
     HIPCHK(fn());
-    if (timing) {
+    if (ev) {
         HIPCHK(hipEventRecord(e1, on));
         ev_used_.push_back({phase, {e0, e1}});
     }
@@ -361,8 +362,8 @@ int Bucket::enqueue_sweep(int force) {
 int Bucket::build_graph(int force) {
     drop_graph();
     HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    const bool tm = timing;
-    timing = false;
+    const int tm = timing;
+    timing = 0;
     int rc = enqueue_sweep(force);
     timing = tm;
     hipGraph_t g = nullptr;
@@ -805,8 +806,9 @@ extern "C" int dsu_batch_get_trace(dsu_batch *b, int32_t det, double *ratio_host
 
 extern "C" int dsu_batch_set_timing(dsu_batch *b, int32_t enable) {
     if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (enable < 0 || enable > 2) return fail(DSU_EINVAL, "timing level %d (0, 1 or 2)", enable);
     CHK(b->bk.harvest_events());
-    b->bk.timing = enable != 0;
+    b->bk.timing = enable;
     for (int p = 0; p < PH_COUNT; ++p) {
         b->bk.t_ms[p] = 0;
         b->bk.t_count[p] = 0;

@@ -48,7 +48,7 @@ class Bucket {
     int kmax_comp = 0;  // largest |component| of the plane-wave integer vectors
     std::vector<DetSlot> dets;
     bool use_graph = false;
-    bool timing = false;
+    int timing = 0;  // 0 off, 1 events around every launch, 2 around flush launches only
     // 0: four launches per window; 1: one-pass flush with the next window's
     // products, FP32 matrix-core products; 2: the same pass with split-bf16
     // products (FP32 determinants only; FP64 buckets take 1)

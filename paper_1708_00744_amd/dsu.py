@@ -19,6 +19,7 @@ FLUSH_K_ACCEPTED, FLUSH_K_PROPOSED = 0, 1
 FLUSH_AUTO, FLUSH_VALU, FLUSH_MFMA = 0, 1, 2
 PATH_WINDOWS, PATH_STREAM, PATH_STREAM_X6 = 0, 1, 2
 PHASE_ROWS, PHASE_G, PHASE_DECIDE, PHASE_FLUSH, PHASE_RECOMPUTE = 0, 1, 2, 3, 4
+TIMING_ALL, TIMING_FLUSH = 1, 2
 MAX_K = 256
 
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESINGULAR: "ESINGULAR", ESTATE: "ESTATE", EDEVICE: "EDEVICE",
@@ -449,7 +450,8 @@ class Batch:
         return r, a
 
     def set_timing(self, enable):
-        _check(lib().dsu_batch_set_timing(self._h, int(bool(enable))))
+        """enable: False/0 off, True/TIMING_ALL every launch, TIMING_FLUSH flush launches only."""
+        _check(lib().dsu_batch_set_timing(self._h, int(enable)))
 
     def kernel_time(self, phase):
         cnt, ms = C.c_int64(), C.c_double()

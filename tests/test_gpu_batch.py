@@ -413,3 +413,30 @@ def test_watchdog_recovers_poisoned_determinant():
         b.poison_row(walkers, 0)
     assert ex.value.code == dsu.EINVAL
     b.close()
+
+
+def test_timing_levels():
+    """Events around every launch (1), around flush launches only (2), none (0);
+    any other level is rejected."""
+    require_gpu()
+    b, _ = make_batch(128, 2, 1, 32, dsu.FP32_MIXED, 0.2, seed=9)
+    b.set_timing(dsu.TIMING_FLUSH)
+    b.sweep(1)
+    b.sync()
+    nf, msf = b.kernel_time(dsu.PHASE_FLUSH)
+    assert nf > 0 and msf > 0
+    assert b.kernel_time(dsu.PHASE_DECIDE)[0] == 0 and b.kernel_time(dsu.PHASE_ROWS)[0] == 0
+    b.set_timing(dsu.TIMING_ALL)
+    b.sweep(1)
+    b.sync()
+    assert b.kernel_time(dsu.PHASE_FLUSH)[0] == nf
+    assert b.kernel_time(dsu.PHASE_DECIDE)[0] > 0 and b.kernel_time(dsu.PHASE_ROWS)[0] > 0
+    for bad in (-1, 3):
+        with pytest.raises(dsu.DsuError) as ex:
+            b.set_timing(bad)
+        assert ex.value.code == dsu.EINVAL
+    b.set_timing(False)
+    b.sweep(1)
+    b.sync()
+    assert b.kernel_time(dsu.PHASE_FLUSH)[0] == 0
+    b.close()
