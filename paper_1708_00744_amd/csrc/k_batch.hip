@@ -476,8 +476,8 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
                                                           int kw, int nsplit, int force_accept, int last_window,
                                                           int g_from_y, int pbuf) {
     constexpr int RW = KP / 4, CPL = KP > 64 ? KP / 64 : 1, NC = 64 * CPL;
-    static_assert(KP >= 16 && KP <= 128 && RW % 2 == 0, "window tile");
-    __shared__ double s_row[2][NC];
+    static_assert(KP >= 16 && KP <= 128 && RW % 4 == 0, "window tile");
+    __shared__ double s_row[2][2][NC];
     __shared__ double s_u[KP], s_ratio[KP];
     __shared__ int s_ok[KP];
     const DetDesc<T> d = descs[blockIdx.x];
@@ -506,25 +506,16 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
     // |prod R| kept as mantissa * 2^exponent; one log at the end
     int m = 0, sgn = 1, bad = 0, pexp = 0;
     double pman = 1.0;
-    // One step: slot j = jb * RW + JJ, whose pivot column lies in column half
-    // JH.  Both are compile-time constants, so every register index is fixed
-    // and each row needs one select (clearing the pivot column's entry in lane
-    // j & 63 before the update) and one FMA per column half.
-    auto step = [&](auto jh_c, auto jj_c, int jb) __attribute__((always_inline)) {
+    // Decision and elimination step of slot j = jb * RW + JJ, whose pivot
+    // column lies in column half JH; rv holds this lane's entries of the pivot
+    // row and r = its entry in column j.  Both JJ and JH are compile-time
+    // constants, so every register index is fixed and each row costs one FMA
+    // per column half.  If nx is given, the step is also applied to that copy
+    // of another row whose column-j entry is fx.
+    auto slot = [&](auto jh_c, auto jj_c, int jb, const double *rv, double r, double uj, double *nx, double fx)
+        __attribute__((always_inline)) {
         constexpr int JH = decltype(jh_c)::value, JJ = decltype(jj_c)::value;
         const int j = jb * RW + JJ;
-        if (j >= kw) return;
-        double *row = s_row[JJ & 1];  // RW is even, so j & 1 == JJ & 1
-        const double uj = s_u[j];     // read-only after the set-up barrier
-        if (wave == jb)
-#pragma unroll
-            for (int h = 0; h < CPL; ++h) row[lane + 64 * h] = g[JJ][h];
-        __syncthreads();
-        // the whole pivot row in one LDS round trip
-        double rv[CPL];
-#pragma unroll
-        for (int h = 0; h < CPL; ++h) rv[h] = row[lane + 64 * h];
-        const double r = row[j];
         const bool finite_nz = fabs(r) > RatioFloor<T>::value && fabs(r) <= 1.7976931348623157e308;
         const bool ok = finite_nz && (force_accept || uj < r * r);
         if (!finite_nz) ++bad;
@@ -547,6 +538,9 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
             c[h] = (h == JH && pl) ? 0.0 : rj[h];
         }
         const double a = pl ? -dinv : 1.0;
+        if (nx)
+#pragma unroll
+            for (int h = 0; h < CPL; ++h) nx[h] = __builtin_fma(-fx, c[h], h == JH ? a * nx[h] : nx[h]);
         // pivot-column entries of QB rows at a time, read before their updates
         constexpr int QB = RW < 8 ? RW : 8;
 #pragma unroll
@@ -577,17 +571,49 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
         if (r < 0.0) sgn = -sgn;
         ++m;
     };
+    // Slots j and j + 1 (j = jb * RW + 2P; both rows in wave jb, both pivot
+    // columns in half JH) with one LDS exchange and one barrier: the owner
+    // publishes both rows, every wave applies slot j's step to its copy of
+    // row j + 1 -- the same operations on the same values as the owner's own
+    // update of that row -- and decides slot j + 1 from it.
+    auto pair = [&](auto jh_c, auto p_c, int jb) __attribute__((always_inline)) {
+        constexpr int P = decltype(p_c)::value, JJ = 2 * P, JH = decltype(jh_c)::value;
+        const int j = jb * RW + JJ;
+        if (j >= kw) return;
+        double *row0 = s_row[P & 1][0], *row1 = s_row[P & 1][1];  // RW / 2 is even: buffers alternate
+        const double u0 = s_u[j], u1 = s_u[j + 1];                 // read-only after the set-up barrier
+        if (wave == jb)
+#pragma unroll
+            for (int h = 0; h < CPL; ++h) {
+                row0[lane + 64 * h] = g[JJ][h];
+                row1[lane + 64 * h] = g[JJ + 1][h];
+            }
+        __syncthreads();
+        double v0[CPL], v1[CPL];
+#pragma unroll
+        for (int h = 0; h < CPL; ++h) {
+            v0[h] = row0[lane + 64 * h];
+            v1[h] = row1[lane + 64 * h];
+        }
+        const double r0 = row0[j], f1 = row1[j];
+        slot(jh_c, std::integral_constant<int, JJ>{}, jb, v0, r0, u0, v1, f1);
+        if (j + 1 >= kw) return;
+        const int jl1 = (j + 1) & 63;
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v1[JH]), jl1);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v1[JH]), jl1);
+        slot(jh_c, std::integral_constant<int, JJ + 1>{}, jb, v1, __hiloint2double(hi, lo), u1, nullptr, 0.0);
+    };
     // blocks of RW slots whose pivot columns lie in column half 0, then half 1
     constexpr int NJB0 = CPL > 1 ? 2 : 4;
 #pragma unroll 1
     for (int jb = 0; jb < NJB0; ++jb)
-        static_for(std::make_integer_sequence<int, RW>{},
-                   [&](auto jj) __attribute__((always_inline)) { step(std::integral_constant<int, 0>{}, jj, jb); });
+        static_for(std::make_integer_sequence<int, RW / 2>{},
+                   [&](auto pp) __attribute__((always_inline)) { pair(std::integral_constant<int, 0>{}, pp, jb); });
     if constexpr (CPL > 1) {
 #pragma unroll 1
         for (int jb = NJB0; jb < 4; ++jb)
-            static_for(std::make_integer_sequence<int, RW>{},
-                       [&](auto jj) __attribute__((always_inline)) { step(std::integral_constant<int, 1>{}, jj, jb); });
+            static_for(std::make_integer_sequence<int, RW / 2>{},
+                       [&](auto pp) __attribute__((always_inline)) { pair(std::integral_constant<int, 1>{}, pp, jb); });
     }
     const double logdet = log(pman) + (double)pexp * 0.69314718055994530942;
     __syncthreads();
