@@ -25,7 +25,10 @@
  * Parity pins live in tests/test_oracle_*.py (exact rational determinants,
  * numpy LU, numpy Philox, lattice shell counts, orthogonality).
  *
- * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (oracle/build.py).
+ * Build: gcc -O3 -march=x86-64-v3 -ffp-contract=off -fno-fast-math -fopenmp
+ * -shared -fPIC (oracle/build.py).  Without contraction and without
+ * reassociation the compiler keeps every sum in its source order, so the
+ * optimisation level does not change a single result bit.
  */
 #include <math.h>
 #include <stdint.h>
@@ -331,10 +334,14 @@ double orc_sm_ratio_grad(int n, const double *ainv, int e, const double *phi, co
 void orc_sm_accept(int n, double *ainv, double *a, int e, const double *phi, double r, double *work)
 {
     double *w = work, *c = work + n;
-    for (int k = 0; k < n; ++k) {
-        double s = 0.0;
-        for (int j = 0; j < n; ++j) s += phi[j] * ainv[(size_t)j * n + k];
-        w[k] = s;
+    /* w[k] = sum_j phi[j] Ainv[j][k], accumulated row by row of Ainv so the
+     * matrix is read in storage order; every w[k] still adds its terms in
+     * ascending j from 0.0, exactly as a dot product over j would. */
+    for (int k = 0; k < n; ++k) w[k] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double pj = phi[j];
+        const double *arow = ainv + (size_t)j * n;
+        for (int k = 0; k < n; ++k) w[k] += pj * arow[k];
     }
     w[e] -= 1.0;
     for (int i = 0; i < n; ++i) c[i] = ainv[(size_t)i * n + e];

@@ -334,6 +334,73 @@ def test_walkers_run_matches_single():
     assert threads >= 1
 
 
+def test_walker_moves_equals_walker_run():
+    """orc_walker_moves (the routine the CPU baseline times, started from a
+    supplied state) and orc_walker_run (pinned above) are the same Metropolis
+    loop: from the inverse orc_walker_run starts with, two full sweeps give
+    the same ratios, accepted count, positions and inverse, bit for bit; so
+    does a sweep split at an arbitrary electron, and the OpenMP form over
+    several walkers."""
+    n, L, sigma, seed, wid, spin = 48, 10.0, 0.4, 12, 3, 1
+    pos = inputs.positions(seed, wid, n, L)
+    full = oracle.walker_run(n, L, seed, wid, spin, sigma, pos, sweeps=2, residual=False, fresh=False)
+    kv = oracle.pw_kvectors(n)
+    a = oracle.pw_matrix(kv, L, pos)
+    ainv, _, _ = oracle.inverse(a)
+    p = pos.copy()
+    r0, n0 = oracle.walker_moves(n, L, seed, wid, spin, sigma, 0, 0, 29, p, a, ainv)
+    r1, n1 = oracle.walker_moves(n, L, seed, wid, spin, sigma, 0, 29, n - 29, p, a, ainv)
+    r2, n2 = oracle.walker_moves(n, L, seed, wid, spin, sigma, 1, 0, n, p, a, ainv)
+    np.testing.assert_array_equal(np.concatenate([r0, r1, r2]), full.ratio)
+    assert n0 + n1 + n2 == full.n_accepted[0]
+    np.testing.assert_array_equal(p, full.pos)
+    np.testing.assert_array_equal(ainv, full.ainv)
+    np.testing.assert_array_equal(a, oracle.pw_matrix(kv, L, full.pos))
+    # the multi-walker form (spin 0, one thread per walker) against one walker at a time
+    nw = 3
+    pw = np.stack([inputs.positions(seed, w, n, L) for w in range(nw)])
+    aw = np.stack([oracle.pw_matrix(kv, L, pw[w]) for w in range(nw)])
+    iw = np.stack([oracle.inverse(aw[w])[0] for w in range(nw)])
+    nacc, _ = oracle.walkers_moves(n, L, [seed] * nw, list(range(nw)), sigma, 0, 5, n, pw, aw, iw)
+    for w in range(nw):
+        p1 = inputs.positions(seed, w, n, L)
+        a1 = oracle.pw_matrix(kv, L, p1)
+        i1 = oracle.inverse(a1)[0]
+        _, c1 = oracle.walker_moves(n, L, seed, w, 0, sigma, 0, 5, n, p1, a1, i1)
+        assert nacc[w] == c1 and c1 > 0
+        np.testing.assert_array_equal(pw[w], p1)
+        np.testing.assert_array_equal(iw[w], i1)
+
+
+def unimodular_integer_matrix(seed, n):
+    """L U with unit triangular integer factors: determinant 1, so the inverse
+    is an integer matrix, exactly representable, and A^-1 A - I evaluates
+    without rounding."""
+    lo = np.tril(inputs.integer_matrix(seed, n, -2, 2), -1) + np.eye(n)
+    up = np.triu(inputs.integer_matrix(seed + 1, n, -2, 2), 1) + np.eye(n)
+    return lo @ up
+
+
+def test_residual_exact_on_constructed_inverse():
+    """orc_residual = max |Ainv A - I| exactly: with the exact (integer)
+    inverse it is 0, and with Ainv = A^-1 + d e_i e_j^T the residual matrix is
+    d e_i A[j,:], so the reported value must be |d| max_k |A[j,k]| for every
+    (i, j) -- a dropped diagonal term, a transposed product or a partial max
+    gives another number."""
+    n = 5
+    a = unimodular_integer_matrix(91, n)
+    exact = np.array([[float(x) for x in row] for row in frac_inverse(a.astype(int).tolist())])
+    assert np.all(exact == np.round(exact))
+    assert oracle.residual(exact, a) == 0.0
+    for i in range(n):
+        for j in range(n):
+            d = -(2.0 ** -10) * (1 + (i + 2 * j) % 3)
+            x = exact.copy()
+            x[i, j] += d
+            assert oracle.residual(x, a) == abs(d) * np.abs(a[j]).max(), (i, j)
+    # a transposed inverse of a non-symmetric matrix is not an inverse
+    assert oracle.residual(np.ascontiguousarray(exact.T), a) >= 1.0
+
 # ------------------------------------- gradient rows and ratio gradients
 def test_plane_wave_gradient_values_and_differences():
     # Closed form at the point of test_plane_wave_values (phases pi, pi/2,
