@@ -89,40 +89,88 @@ def time_sweeps(b, steps, warmup, force=False):
     return time.perf_counter() - t0
 
 
+# Starts: seeded uniform positions equilibrated by FP64 sweeps with a large
+# step (set-up, not timed).  Uniform-random placement puts electrons close
+# together (cond(A) ~1e5 at N = 4096) where |Psi|^2 sampling keeps them
+# apart; from such starts FP32 inverses drift past 1e-2 in a sweep.
+BURN_SWEEPS, BURN_SIGMA = 10, 0.4
+RECOMPUTE_EVERY = 20
+# residual watchdog of the timed run: rows per side and determinant per sweep
+RESID_SAMPLES, RESID_THRESHOLD = 16, 1e-3
+DIAG_WALKERS = 16
+
+
+def burn_in(n, pos, seeds, wids, sweeps=BURN_SWEEPS, sigma=BURN_SIGMA, K=128):
+    """FP64 batched sweeps at step sigma from `pos`; returns the positions
+    (walkers, 1, n, 3) and the acceptance."""
+    from paper_1708_00744_amd import dsu
+    with dsu.Batch(n, pos, seeds, wids, sigma, K, precision=dsu.FP64, box_l=BOX_L) as b:
+        b.sweep(sweeps)
+        acc = float(b.stats()["accepted"].sum()) / (len(seeds) * n * sweeps)
+        out = np.stack([b.positions(d).reshape(1, n, 3) for d in range(len(seeds))])
+    return out, acc
+
+
 def headline(args, cache):
     from paper_1708_00744_amd import dsu, tune
     n, walkers = 4096, 32
     sigma = sigma_or_default(n, 0.99, cache)
     dkey = tune.delay_key(n, walkers, dsu.FP32_MIXED)
     K = int(cache["delay"].get(dkey, {}).get("best", 64))
-    pos = batch_positions(n, walkers)
+    seeds, wids = [1000 + w for w in range(walkers)], list(range(walkers))
     t0 = time.perf_counter()
-    b = dsu.Batch(n, pos, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, 256,
-                  precision=dsu.FP32_MIXED, box_l=BOX_L, recompute_every=20)
+    pos, acc_burn = burn_in(n, batch_positions(n, walkers), seeds, wids)
+    burn_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b = dsu.Batch(n, pos, seeds, wids, sigma, 256, precision=dsu.FP32_MIXED, box_l=BOX_L,
+                  recompute_every=RECOMPUTE_EVERY)
     setup_s = time.perf_counter() - t0
+    b.set_sweep(BURN_SWEEPS)  # the random stream continues after the burn-in sweeps
     b.set_delay(K)
+    b.set_residual_watchdog(RESID_SAMPLES, RESID_THRESHOLD)
     b.sweep(args.warmup)
     b.sync()
     # timed region: the K sweeps, each followed by a wait so that its own
     # duration is known (median and spread across the K sweeps); HIP events
-    # bracket the flush launches only, the kernel the roofline is quoted for
+    # bracket the flush launches only, the kernel the roofline is quoted for.
+    # Every sweep includes the residual watchdog (sampled residuals of every
+    # inverse, FP64 recompute of any above the threshold) and every 20th the
+    # periodic FP64 recompute of all inverses.
     b.set_timing(dsu.TIMING_FLUSH)
     import torch
     b.sync()
     torch.cuda.synchronize()
-    per = []
+    acc_before = float(b.stats()["accepted"].sum())
+    wd_before = b.accuracy()["recomputes"]
+    per, right, drift = [], [], []
+    last_drift = b.accuracy()["drift"]
     t0 = time.perf_counter()
     for _ in range(args.steps):
         t1 = time.perf_counter()
         b.sweep(1)
         b.sync()
         per.append(time.perf_counter() - t1)
+        a = b.accuracy()
+        right.append(float(a["residual"].max()))
+        if not np.array_equal(a["drift"], last_drift):
+            drift.append(float(np.abs(a["drift"]).max()))
+            last_drift = a["drift"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = b.stats()
     cnt, ms = b.kernel_time(dsu.PHASE_FLUSH)
     moves = walkers * n * args.steps
-    acc = float(st["accepted"].sum()) / (walkers * n * (args.steps + args.warmup))
+    acc = (float(st["accepted"].sum()) - acc_before) / moves
+    accuracy = {
+        "residual_right_max": max(right), "residual_right_per_sweep": right,
+        "residual_rows_per_sweep": RESID_SAMPLES, "watchdog_threshold": RESID_THRESHOLD,
+        "watchdog_recomputes": int(b.accuracy()["recomputes"] - wd_before),
+        "logdet_drift_at_recompute": max(drift) if drift else None,
+        "measured": "right residual max |A A^-1 - I| after every timed sweep (residual watchdog, %d rotating rows of "
+                    "every determinant, A rebuilt in FP64 from the positions, before any recompute it triggers; it "
+                    "bounds the relative ratio error of a small move); log|det| drift = max over determinants of "
+                    "running minus fresh at the FP64 recompute(s) in the timed region" % RESID_SAMPLES,
+    }
     # per-phase split from one more sweep after the timed region, with events
     # around every launch
     b.set_timing(dsu.TIMING_ALL)
@@ -151,14 +199,40 @@ def headline(args, cache):
     roof["flops_per_launch"] = flops
     roof["bytes_per_launch"] = bytes_
     per_ms = sorted(1e3 * x for x in per)
+    # ratio accuracy against the FP64 oracle at the end of a recompute interval:
+    # run to the last sweep before the next periodic recompute and record that
+    # sweep's ratios and decisions for the first walkers (the oracle replays
+    # them from the same positions with a fresh FP64 inverse, cpu_baseline)
+    done = int(b.stats()["sweeps"][0]) - BURN_SWEEPS
+    to_last = (RECOMPUTE_EVERY - 1 - done % RECOMPUTE_EVERY) % RECOMPUTE_EVERY
+    b.sweep(to_last)
+    b.sync()
+    diag = {"sweep": int(b.stats()["sweeps"][0]), "seeds": seeds[:DIAG_WALKERS], "wids": wids[:DIAG_WALKERS],
+            "pos": np.stack([b.positions(d) for d in range(DIAG_WALKERS)]),
+            "sweeps_since_recompute": RECOMPUTE_EVERY - 1}
+    b.set_trace(1)
+    b.sweep(1)
+    tr = [b.trace(d) for d in range(DIAG_WALKERS)]
+    b.set_trace(0)
+    # both residuals of every determinant at that point (the end of the
+    # interval, the largest they get before the recompute), 64 rows each
+    rr, rl = b.residual(64)
+    accuracy["end_of_interval"] = {"residual_right_max": float(rr.max()), "residual_left_max": float(rl.max()),
+                                   "residual_left_median": float(np.median(rl)),
+                                   "walkers_left_above_1e-3": int((rl > 1e-3).sum()), "rows_per_side": 64,
+                                   "sweeps_since_recompute": RECOMPUTE_EVERY}
+    diag["ratio"] = np.stack([x[0] for x in tr])
+    diag["accepted"] = np.stack([x[1] for x in tr])
     out = {
         "moves_per_s": moves / dt, "ms_per_step": 1e3 * dt / args.steps, "K": K, "sigma": sigma,
         "sweep_ms": {"median": per_ms[len(per_ms) // 2], "min": per_ms[0], "max": per_ms[-1]},
         "accepted_moves_per_s": None,
         "acceptance": acc, "setup_s": setup_s,
+        "burn_in": {"sweeps": BURN_SWEEPS, "sigma": BURN_SIGMA, "precision": "fp64", "acceptance": acc_burn,
+                    "seconds": burn_s},
         "phase_ms_per_sweep": {k: v[1] for k, v in phases.items()},
         "phase_split_from": "one sweep after the timed region, events around every launch",
-        "roofline": roof, "batch": b,
+        "roofline": roof, "accuracy": accuracy, "diag": diag, "batch": b,
     }
     out["accepted_moves_per_s"] = out["moves_per_s"] * acc
     return out
@@ -443,33 +517,64 @@ def serving(cache, count=40, seed=7):
             "queue_wait_s_p50": float(np.percentile(wait, 50)), "end_to_end_s_p99": float(np.percentile(e2e, 99))}
 
 
-def cpu_baseline(n=4096, sigma=0.002, target_s=15.0):
+def ratio_accuracy(diag, r_or, upto, sigma):
+    """FP32 device ratios against the oracle's FP64 ones for the first `upto`
+    moves of each walker's traced sweep, up to and including the first move
+    whose decision differs (after it the two trajectories part)."""
+    import oracle
+    errs, flips, compared = [], 0, 0
+    for w in range(r_or.shape[0]):
+        rg, ag = diag["ratio"][w][:upto], diag["accepted"][w][:upto].astype(bool)
+        stop = upto
+        for e in range(upto):
+            _, u = oracle.move_randoms(diag["seeds"][w], diag["wids"][w], diag["sweep"], e)
+            if (u < r_or[w, e] ** 2) != ag[e]:
+                stop = e + 1
+                flips += 1
+                break
+        ro = r_or[w, :stop]
+        errs.append(np.abs(rg[:stop] - ro) / np.maximum(np.abs(ro), 1e-3))
+        compared += stop
+    e = np.concatenate(errs)
+    return {"moves_compared": int(compared), "median": float(np.median(e)), "p99": float(np.percentile(e, 99)),
+            "max": float(e.max()), "decision_flips": flips,
+            "measured": "relative error |R - R_fp64| / max(|R_fp64|, 1e-3) of the device's FP32 ratios against the "
+                        "oracle's (FP64 Sherman-Morrison from a fresh inverse at the same positions) on the last sweep "
+                        "before a periodic recompute (%d sweeps since the last), each walker compared up to its first "
+                        "differing decision" % diag["sweeps_since_recompute"]}
+
+
+def cpu_baseline(diag, sigma, n=4096, target_s=15.0):
     """The oracle (plain FP64 Sherman-Morrison in C) on the host cores: a
     bounded sample of the headline workload -- one thread per walker, each
-    running the first moves of sweep 0 from a fresh inverse (set-up not timed)."""
+    running the first moves of the sweep the headline traced, from the same
+    positions with a fresh inverse (set-up by LAPACK, not timed).  Its ratios
+    double as the FP64 reference of the device's FP32 ones."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    threads = max(1, min(threads, 16))
+    threads = max(1, min(threads, len(diag["seeds"])))
     walkers = threads
+    seeds, wids, sweep = diag["seeds"][:walkers], diag["wids"][:walkers], diag["sweep"]
     kv = oracle.pw_kvectors(n)
-    pos = batch_positions(n, walkers)[:, 0]
-    pos = np.ascontiguousarray(pos)
+    pos = np.ascontiguousarray(diag["pos"][:walkers])
     a = np.stack([oracle.pw_matrix(kv, BOX_L, pos[w]) for w in range(walkers)])
     ainv = np.ascontiguousarray(np.stack([np.linalg.inv(a[w]) for w in range(walkers)]))
     # calibrate the sample size with 4 moves
+    r0 = np.zeros((walkers, 4))
     t0 = time.perf_counter()
-    oracle.walkers_moves(n, BOX_L, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, 0, 0, 4,
-                         pos, a, ainv)
+    oracle.walkers_moves(n, BOX_L, seeds, wids, sigma, sweep, 0, 4, pos, a, ainv, ratios=r0)
     per = (time.perf_counter() - t0) / 4
-    m = max(8, int(target_s / max(per, 1e-6)))
+    m = min(max(8, int(target_s / max(per, 1e-6))), n - 4 - 24)
+    r1 = np.zeros((walkers, m))
     t0 = time.perf_counter()
-    _, used = oracle.walkers_moves(n, BOX_L, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, 0, 4, m,
-                                   pos, a, ainv)
+    _, used = oracle.walkers_moves(n, BOX_L, seeds, wids, sigma, sweep, 4, m, pos, a, ainv, ratios=r1)
     dt = time.perf_counter() - t0
+    ratio_acc = ratio_accuracy(diag, np.concatenate([r0, r1], axis=1), 4 + m, sigma)
     # one thread, one walker: the next 24 moves of walker 0
     t1 = time.perf_counter()
-    e1 = min(4 + m, n - 24)
-    oracle.walkers_moves(n, BOX_L, [1000], [0], sigma, 0, e1, 24, pos[:1].copy(), a[:1].copy(), ainv[:1].copy())
+    e1 = 4 + m
+    oracle.walkers_moves(n, BOX_L, seeds[:1], wids[:1], sigma, sweep, e1, 24, pos[:1].copy(), a[:1].copy(),
+                         ainv[:1].copy())
     single = 24 / (time.perf_counter() - t1)
     model = ""
     try:
@@ -478,11 +583,11 @@ def cpu_baseline(n=4096, sigma=0.002, target_s=15.0):
     except OSError:
         pass
     return {"value": walkers * m / dt, "unit": "moves/s", "cores": int(used), "kind": "oracle",
-            "sample": f"{walkers} walkers x {m} moves of sweep 0 at N={n} (FP64 Sherman-Morrison, one OpenMP thread "
-                      f"per walker, set-up by LAPACK inverse not timed)",
+            "sample": f"{walkers} walkers x {m} moves of one sweep at N={n} from the headline's positions (FP64 "
+                      f"Sherman-Morrison, one OpenMP thread per walker, set-up by LAPACK inverse not timed)",
             "single_thread_moves_per_s": single,
             "host": {"nproc": os.cpu_count(), "cpu": model},
-            "walker_forms": cpu_baseline_walkers()}
+            "walker_forms": cpu_baseline_walkers()}, ratio_acc
 
 
 def cpu_baseline_walkers(n=1024, moves=100):
@@ -560,7 +665,7 @@ EXTRA_LEGS = {
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true")
@@ -623,9 +728,11 @@ def main():
         log("serving")
         extras["serving"] = serving(cache)
     cpu = None
+    diag = h.pop("diag")
+    accuracy = h.pop("accuracy")
     if not args.no_cpu:
-        log("cpu baseline (oracle)")
-        cpu = cpu_baseline(sigma=h["sigma"])
+        log("cpu baseline (oracle), ratio accuracy against it")
+        cpu, accuracy["ratio_vs_fp64_oracle"] = cpu_baseline(diag, h["sigma"])
     roof = h.pop("roofline")
     line = {
         "metric": "electron moves/sec/GPU (FP32-batched delayed update, N=4096)",
@@ -639,11 +746,15 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (FP64 recompute and log-det)",
-        "data": "synthetic: seeded uniform positions, plane-wave orbitals, device Philox4x64-10 moves",
-        "config": {"workload": "32 walkers x N=4096 Slater matrices, K=%d, acceptance %.3f, FP64 recompute every 20 "
-                               "sweeps; step = one sweep of every walker" % (h["K"], h["acceptance"]),
-                   "walkers": 32, "n": 4096, "K": h["K"], "sigma": h["sigma"], "precision": "fp32_mixed"},
+        "data": "synthetic: seeded uniform positions equilibrated by %d FP64 sweeps at sigma %.1f (set-up, not "
+                "timed), plane-wave orbitals, device Philox4x64-10 moves" % (BURN_SWEEPS, BURN_SIGMA),
+        "config": {"workload": "32 walkers x N=4096 Slater matrices, K=%d, acceptance %.3f, FP64 recompute every %d "
+                               "sweeps, residual watchdog every sweep; step = one sweep of every walker"
+                               % (h["K"], h["acceptance"], RECOMPUTE_EVERY),
+                   "walkers": 32, "n": 4096, "K": h["K"], "sigma": h["sigma"], "precision": "fp32_mixed",
+                   "recompute_every": RECOMPUTE_EVERY},
         "roofline": roof,
+        "accuracy": accuracy,
         "cpu_baseline": cpu,
         "detail": {k: v for k, v in h.items() if k not in ("moves_per_s", "ms_per_step")},
         "extras": extras,

@@ -288,6 +288,43 @@ int dsu_batch_set_sweep(dsu_batch *b, int64_t sweeps_done);
  * number of such recomputes so far. */
 int dsu_batch_set_watchdog(dsu_batch *b, int32_t enable);
 int dsu_batch_watchdog_count(dsu_batch *b, int64_t *recomputes);
+/* Sampled residuals of every determinant's device inverse X against its
+ * Slater matrix A (Sec. III checks the delayed updates against a direct
+ * calculation), A rebuilt in FP64 from the current positions, X converted
+ * exactly to FP64, products on FP64 matrix cores.  With S = samples and
+ * t = sweeps_done mod (n / S):
+ *   right_host[d] = max |(A X - I)[r][j]| over the S rows r = s * (n / S) + t
+ *                   (s < S) and every column j;
+ *   left_host[d]  = max |(X A - I)[i][j]| over the S consecutive rows
+ *                   i = t * S + s (s < S) and every column j;
+ * +inf if an entry is not finite.  The rows visited rotate with the completed
+ * sweeps, so n / S consecutive sweeps cover every row below S * (n / S).
+ * For a proposal close to the present position the ratio error is about the
+ * right residual's diagonal entry; the left residual is the norm
+ * ||A^{-1} A - I|| of the FP32 form's accuracy statement.  Either output may
+ * be NULL (its kernel is skipped), not both.  samples in [1, min(64, n)],
+ * else DSU_EINVAL.  Synchronises. */
+int dsu_batch_residual(dsu_batch *b, int32_t samples, double *right_host, double *left_host);
+/* Residual watchdog (the adaptive recompute of the FP32 form): after every
+ * sweep, the sampled right residual above for every determinant; a
+ * determinant whose right residual exceeds `threshold` (or is not finite)
+ * gets a fresh FP64 inverse at once, from its positions.  The right residual
+ * is the one that bounds the ratios: a proposal phi~ = A[e, :] + delta has
+ * R_computed - R = F[e][e] + delta A^{-1} F[:, e] with F = A X - I, so for the
+ * small moves of a high-acceptance run the relative ratio error is about
+ * F[e][e].  samples = 0 turns it off; otherwise samples as for
+ * dsu_batch_residual and threshold > 0, else DSU_EINVAL.  Costs the right
+ * residual's kernels (one pass over every inverse) and one synchronisation
+ * per sweep. */
+int dsu_batch_set_residual_watchdog(dsu_batch *b, int32_t samples, double threshold);
+/* Accuracy record, per determinant d (any pointer may be NULL):
+ * residual_out[d] = the sampled right residual after the latest sweep run
+ * with the residual watchdog on (before any recompute it triggered; 0 before
+ * the first); drift_out[d] = running-minus-fresh log|det| found by the latest
+ * FP64 recompute of d (periodic, either watchdog, or dsu_batch_recompute; 0
+ * before the first after creation); *residual_recomputes = recomputes the
+ * residual watchdog has made. */
+int dsu_batch_accuracy(dsu_batch *b, double *residual_out, double *drift_out, int64_t *residual_recomputes);
 /* Fault injection for tests of the failure handling: overwrite row `row` of
  * determinant `det`'s device inverse with NaN.  Synchronises. */
 int dsu_batch_poison_row(dsu_batch *b, int32_t det, int32_t row);

@@ -301,6 +301,45 @@ double orc_residual(int n, const double *ainv, const double *a)
     return worst;
 }
 
+/* Rows of the right residual A Ainv - I: the largest |sum_k a[r][k] ainv[k][j]
+ * - [r == j]| over the listed rows r = rows[0..m) and every column j (the
+ * check of an inverse against the matrix itself, Sec. III, restricted to a
+ * sample of electrons).  Rows outside [0, n) are skipped. */
+double orc_residual_rows(int n, const double *ainv, const double *a, int m, const int *rows)
+{
+    double worst = 0.0;
+    for (int q = 0; q < m; ++q) {
+        const int r = rows[q];
+        if (r < 0 || r >= n) continue;
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += a[(size_t)r * n + k] * ainv[(size_t)k * n + j];
+            if (r == j) s -= 1.0;
+            if (fabs(s) > worst) worst = fabs(s);
+        }
+    }
+    return worst;
+}
+
+/* Rows of the left residual Ainv A - I: the largest |sum_k ainv[r][k] a[k][j]
+ * - [r == j]| over the listed rows r and every column j.  Rows outside
+ * [0, n) are skipped. */
+double orc_residual_left_rows(int n, const double *ainv, const double *a, int m, const int *rows)
+{
+    double worst = 0.0;
+    for (int q = 0; q < m; ++q) {
+        const int r = rows[q];
+        if (r < 0 || r >= n) continue;
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += ainv[(size_t)r * n + k] * a[(size_t)k * n + j];
+            if (r == j) s -= 1.0;
+            if (fabs(s) > worst) worst = fabs(s);
+        }
+    }
+    return worst;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Eq. (1): ratio det(A_new)/det(A) when row e of A becomes phi.             */
 /* ------------------------------------------------------------------------ */
@@ -486,10 +525,11 @@ int64_t orc_walker_moves(int n, double L, uint64_t seed, uint64_t walker, int sp
 }
 
 /* orc_walker_moves for nw walkers at once, one OpenMP thread each; arrays are
- * per-walker blocks.  Returns the number of threads used. */
+ * per-walker blocks (ratios, if not NULL: nmoves per walker).  Returns the
+ * number of threads used. */
 int orc_walkers_moves(int nw, int n, double L, const uint64_t *seeds, const uint64_t *walker_ids, double sigma,
                       int sweep, int e_first, int nmoves, int force_accept, double *pos, double *a, double *ainv,
-                      int64_t *n_accepted)
+                      int64_t *n_accepted, double *ratios)
 {
     int threads = 1;
 #ifdef _OPENMP
@@ -500,7 +540,7 @@ int orc_walkers_moves(int nw, int n, double L, const uint64_t *seeds, const uint
     for (int w = 0; w < nw; ++w)
         n_accepted[w] = orc_walker_moves(n, L, seeds[w], walker_ids[w], 0, sigma, sweep, e_first, nmoves, force_accept,
                                          pos + (size_t)w * 3 * n, a + (size_t)w * n * n, ainv + (size_t)w * n * n,
-                                         NULL);
+                                         ratios ? ratios + (size_t)w * nmoves : NULL);
     return threads;
 }
 

@@ -56,6 +56,10 @@ def _declare(L):
     L.orc_inverse.restype = C.c_int
     L.orc_residual.argtypes = [C.c_int, _dp, _dp]
     L.orc_residual.restype = C.c_double
+    L.orc_residual_rows.argtypes = [C.c_int, _dp, _dp, C.c_int, _ip]
+    L.orc_residual_rows.restype = C.c_double
+    L.orc_residual_left_rows.argtypes = [C.c_int, _dp, _dp, C.c_int, _ip]
+    L.orc_residual_left_rows.restype = C.c_double
     L.orc_sm_ratio.argtypes = [C.c_int, _dp, C.c_int, _dp]
     L.orc_sm_ratio.restype = C.c_double
     L.orc_sm_ratio_grad.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp, _dp]
@@ -88,7 +92,7 @@ def _declare(L):
                                    C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, vp]
     L.orc_walker_moves.restype = C.c_int64
     L.orc_walkers_moves.argtypes = [C.c_int, C.c_int, C.c_double, _u64p, _u64p, C.c_double, C.c_int, C.c_int,
-                                    C.c_int, C.c_int, _dp, _dp, _dp, _i64p]
+                                    C.c_int, C.c_int, _dp, _dp, _dp, _i64p, C.c_void_p]
     L.orc_walkers_moves.restype = C.c_int
 
 
@@ -166,6 +170,19 @@ def inverse(a):
 
 def residual(ainv, a):
     return lib().orc_residual(a.shape[0], np.ascontiguousarray(ainv), np.ascontiguousarray(a))
+
+
+def residual_rows(ainv, a, rows):
+    """max |(A Ainv - I)[r, j]| over the listed rows r and all columns j."""
+    rows = np.ascontiguousarray(rows, np.int32)
+    return lib().orc_residual_rows(a.shape[0], np.ascontiguousarray(ainv), np.ascontiguousarray(a), len(rows), rows)
+
+
+def residual_left_rows(ainv, a, rows):
+    """max |(Ainv A - I)[r, j]| over the listed rows r and all columns j."""
+    rows = np.ascontiguousarray(rows, np.int32)
+    return lib().orc_residual_left_rows(a.shape[0], np.ascontiguousarray(ainv), np.ascontiguousarray(a), len(rows),
+                                        rows)
 
 
 def sm_ratio(ainv, e, phi):
@@ -256,16 +273,21 @@ def walker_moves(n, L, seed, walker, spin, sigma, sweep, e_first, nmoves, pos, a
     return ratios, nacc
 
 
-def walkers_moves(n, L, seeds, walker_ids, sigma, sweep, e_first, nmoves, pos, a, ainv, force_accept=False):
-    """Many walkers (OpenMP): pos (w, n, 3), a and ainv (w, n, n), all in place.
+def walkers_moves(n, L, seeds, walker_ids, sigma, sweep, e_first, nmoves, pos, a, ainv, force_accept=False,
+                  ratios=None):
+    """Many walkers (OpenMP): pos (w, n, 3), a and ainv (w, n, n), all in place;
+    ratios (optional, (w, nmoves) FP64) receives every move's ratio.
     Returns (accepted per walker, threads used)."""
     nw = len(seeds)
-    for x in (pos, a, ainv):
+    for x in (pos, a, ainv) + ((ratios,) if ratios is not None else ()):
         assert x.flags.c_contiguous and x.dtype == np.float64
+    if ratios is not None:
+        assert ratios.shape == (nw, nmoves)
     nacc = np.zeros(nw, np.int64)
     threads = lib().orc_walkers_moves(nw, n, float(L), np.ascontiguousarray(seeds, np.uint64),
                                       np.ascontiguousarray(walker_ids, np.uint64), float(sigma), int(sweep),
-                                      int(e_first), int(nmoves), int(bool(force_accept)), pos, a, ainv, nacc)
+                                      int(e_first), int(nmoves), int(bool(force_accept)), pos, a, ainv, nacc,
+                                      ratios.ctypes.data_as(C.c_void_p) if ratios is not None else None)
     return nacc, threads
 
 

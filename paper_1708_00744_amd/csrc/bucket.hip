@@ -121,8 +121,15 @@ void Bucket::release() {
     if (stream) (void)hipStreamSynchronize(stream);
     if (side) (void)hipStreamSynchronize(side);
     drop_graph();
-    for (void *p : {(void *)kvec, ddesc_, fdesc_, sub_ddesc_, (void *)sub_pos_, (void *)sub_bt_, (void *)drift_})
+    for (void *p : {(void *)kvec, ddesc_, fdesc_, sub_ddesc_, (void *)sub_pos_, (void *)sub_bt_, (void *)drift_,
+                    (void *)res_rows_, (void *)res_eidx_, (void *)res_bits_})
         dfree(p);
+    if (res_host_) (void)hipHostFree(res_host_);
+    res_rows_ = nullptr;
+    res_eidx_ = nullptr;
+    res_bits_ = nullptr;
+    res_host_ = nullptr;
+    res_cap_ = 0;
     if (status_h_) (void)hipHostFree(status_h_);
     if (stage_h_) (void)hipHostFree(stage_h_);
     status_h_ = nullptr;
@@ -235,12 +242,20 @@ int Bucket::set_dets(const std::vector<DetSlot> &d) {
 
 int Bucket::set_delay(int k) {
     if (k < 1 || k > sh.kmax) return fail(DSU_EINVAL, "delay %d outside [1, %d] of this batch", k, sh.kmax);
+    HIPCHK(hipStreamSynchronize(stream));
+    HIPCHK(hipStreamSynchronize(side));
     K = k;
     drop_graph();
     return DSU_OK;
 }
 
 void Bucket::drop_graph() {
+    // a launched graph may still be running on either stream: destroy it only
+    // once both have drained
+    if (gexec_ || graph_) {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (side) (void)hipStreamSynchronize(side);
+    }
     if (gexec_) (void)hipGraphExecDestroy(gexec_);
     if (graph_) (void)hipGraphDestroy(graph_);
     gexec_ = nullptr;
@@ -436,6 +451,57 @@ void Bucket::check_recompute(std::vector<int> *singular) {
     pending_.clear();
 }
 
+int Bucket::residual(int samples, std::vector<double> *right, std::vector<double> *left) {
+    const int nd = (int)dets.size();
+    if (right) right->assign(nd, 0.0);
+    if (left) left->assign(nd, 0.0);
+    if (nd == 0 || (!right && !left)) return DSU_OK;
+    if (samples < 1 || samples > 64 || samples > sh.n)
+        return fail(DSU_EINVAL, "residual samples %d outside [1, min(64, n = %d)]", samples, sh.n);
+    HIPCHK(hipStreamSynchronize(stream));
+    if (nd > res_cap_) {
+        for (void *p : {(void *)res_rows_, (void *)res_eidx_, (void *)res_bits_}) dfree(p);
+        if (res_host_) (void)hipHostFree(res_host_);
+        res_rows_ = nullptr;
+        res_eidx_ = nullptr;
+        res_bits_ = nullptr;
+        res_host_ = nullptr;
+        res_cap_ = 0;
+        CHK(dalloc(&res_rows_, (size_t)nd * 64 * sh.np));
+        CHK(dalloc(&res_eidx_, (size_t)nd * 64));
+        CHK(dalloc(&res_bits_, (size_t)2 * nd));
+        HIPCHK(hipHostMalloc((void **)&res_host_, sizeof(unsigned long long) * 2 * nd));
+        res_cap_ = nd;
+    }
+    const bool f64 = sh.prec == DSU_FP64;
+    if (right) {
+        HIPCHK(f64 ? launch_resid<double>((const DetDesc<double> *)ddesc_, nd, sh.n, sh.np, samples, kvec, twopi_l,
+                                          res_rows_, res_eidx_, res_bits_, stream)
+                   : launch_resid<float>((const DetDesc<float> *)ddesc_, nd, sh.n, sh.np, samples, kvec, twopi_l,
+                                         res_rows_, res_eidx_, res_bits_, stream));
+    }
+    if (left) {
+        HIPCHK(f64 ? launch_resid_left<double>((const DetDesc<double> *)ddesc_, nd, sh.n, sh.np, samples, kvec,
+                                               twopi_l, kmax_comp, res_bits_ + nd, stream)
+                   : launch_resid_left<float>((const DetDesc<float> *)ddesc_, nd, sh.n, sh.np, samples, kvec,
+                                              twopi_l, kmax_comp, res_bits_ + nd, stream));
+    }
+    HIPCHK(hipMemcpyAsync(res_host_, res_bits_, sizeof(unsigned long long) * 2 * nd, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int i = 0; i < nd; ++i) {
+        double v;
+        if (right) {
+            std::memcpy(&v, &res_host_[i], sizeof(v));
+            (*right)[i] = v;
+        }
+        if (left) {
+            std::memcpy(&v, &res_host_[nd + i], sizeof(v));
+            (*left)[i] = v;
+        }
+    }
+    return DSU_OK;
+}
+
 int Bucket::recompute(const std::vector<int> &which, double *drift_host) {
     if (which.empty()) return DSU_OK;
     HIPCHK(hipStreamSynchronize(stream));
@@ -549,7 +615,21 @@ struct dsu_batch {
     bool watchdog = false;
     std::vector<int> bad_seen;
     long long watchdog_recomputes = 0;
+    // residual watchdog: sampled residual after every sweep, recompute above threshold
+    int resid_samples = 0;
+    double resid_threshold = 0.0;
+    long long resid_recomputes = 0;
+    std::vector<double> last_right, last_drift;
 };
+
+// Recompute the listed members, keeping each one's running-minus-fresh log|det|.
+static int batch_recompute_some(dsu_batch *b, const std::vector<int> &which) {
+    if (which.empty()) return DSU_OK;
+    std::vector<double> drift(which.size());
+    CHK(b->bk.recompute(which, drift.data()));
+    for (size_t i = 0; i < which.size(); ++i) b->last_drift[which[i]] = drift[i];
+    return DSU_OK;
+}
 
 static int batch_read_bad(dsu_batch *b, std::vector<int> *bad) {
     bad->resize(b->ndet);
@@ -601,6 +681,8 @@ extern "C" int dsu_batch_create(int32_t walkers, int32_t n, int32_t spins, int32
     b->spins = spins;
     b->ndet = walkers * spins;
     b->recompute_every = recompute_every;
+    b->last_right.assign(b->ndet, 0.0);
+    b->last_drift.assign(b->ndet, 0.0);
     const BucketShape sh = BucketShape::make(n, k_delay, precision);
     // recompute as many determinants at once as fit in ~8 GiB of workspace
     const size_t per = GjWork::bytes_per(sh.np, n);
@@ -654,9 +736,17 @@ extern "C" int dsu_batch_sweep(dsu_batch *b, int32_t sweeps, int32_t force_accep
     if (sweeps < 0) return fail(DSU_EINVAL, "sweeps < 0");
     for (int s = 0; s < sweeps; ++s) {
         if (b->recompute_every > 0 && b->sweeps_done > 0 && b->sweeps_done % b->recompute_every == 0)
-            CHK(b->bk.recompute(all_indices(b->ndet), nullptr));
+            CHK(batch_recompute_some(b, all_indices(b->ndet)));
         CHK(b->bk.sweep(force_accept ? 1 : 0));
         ++b->sweeps_done;
+        if (b->resid_samples > 0) {
+            CHK(b->bk.residual(b->resid_samples, &b->last_right, nullptr));
+            std::vector<int> which;
+            for (int i = 0; i < b->ndet; ++i)
+                if (!(b->last_right[i] <= b->resid_threshold)) which.push_back(i);
+            CHK(batch_recompute_some(b, which));
+            b->resid_recomputes += (long long)which.size();
+        }
         if (b->watchdog) {
             HIPCHK(hipStreamSynchronize(b->bk.stream));
             std::vector<int> bad, which;
@@ -664,7 +754,7 @@ extern "C" int dsu_batch_sweep(dsu_batch *b, int32_t sweeps, int32_t force_accep
             for (int i = 0; i < b->ndet; ++i)
                 if (bad[i] > b->bad_seen[i]) which.push_back(i);
             if (!which.empty()) {
-                CHK(b->bk.recompute(which, nullptr));
+                CHK(batch_recompute_some(b, which));
                 b->watchdog_recomputes += (long long)which.size();
             }
             b->bad_seen = bad;
@@ -678,6 +768,35 @@ extern "C" int dsu_batch_set_watchdog(dsu_batch *b, int32_t enable) {
     HIPCHK(hipStreamSynchronize(b->bk.stream));
     b->watchdog = enable != 0;
     if (b->watchdog) CHK(batch_read_bad(b, &b->bad_seen));
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_residual(dsu_batch *b, int32_t samples, double *right_host, double *left_host) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (!right_host && !left_host) return fail(DSU_EINVAL, "both outputs are NULL");
+    std::vector<double> r, l;
+    CHK(b->bk.residual(samples, right_host ? &r : nullptr, left_host ? &l : nullptr));
+    if (right_host) std::copy(r.begin(), r.end(), right_host);
+    if (left_host) std::copy(l.begin(), l.end(), left_host);
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_set_residual_watchdog(dsu_batch *b, int32_t samples, double threshold) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (samples < 0 || samples > 64 || samples > b->bk.sh.n)
+        return fail(DSU_EINVAL, "residual samples %d outside [0, min(64, n = %d)]", samples, b->bk.sh.n);
+    if (samples > 0 && !(threshold > 0.0)) return fail(DSU_EINVAL, "residual threshold must be positive");
+    b->resid_samples = samples;
+    b->resid_threshold = threshold;
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_accuracy(dsu_batch *b, double *residual_out, double *drift_out,
+                                  int64_t *residual_recomputes) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (residual_out) std::copy(b->last_right.begin(), b->last_right.end(), residual_out);
+    if (drift_out) std::copy(b->last_drift.begin(), b->last_drift.end(), drift_out);
+    if (residual_recomputes) *residual_recomputes = b->resid_recomputes;
     return DSU_OK;
 }
 
@@ -706,7 +825,9 @@ extern "C" int dsu_batch_sync(dsu_batch *b) {
 
 extern "C" int dsu_batch_recompute(dsu_batch *b, double *drift_out) {
     if (!b) return fail(DSU_EINVAL, "batch is NULL");
-    return b->bk.recompute(all_indices(b->ndet), drift_out);
+    CHK(batch_recompute_some(b, all_indices(b->ndet)));
+    if (drift_out) std::copy(b->last_drift.begin(), b->last_drift.end(), drift_out);
+    return DSU_OK;
 }
 
 extern "C" int dsu_batch_set_delay(dsu_batch *b, int32_t k_delay) {

@@ -72,6 +72,10 @@ class Bucket {
     // until they are checked.
     int recompute_async(const std::vector<int> &which);
     void check_recompute(std::vector<int> *singular);
+    // Sampled residuals of every member, A rebuilt from the positions: right =
+    // max over `samples` rows of |A A^{-1} - I| (launch_resid), left = the same
+    // for A^{-1} A - I (launch_resid_left); either may be NULL.  Waits.
+    int residual(int samples, std::vector<double> *right, std::vector<double> *left);
     // Pre-size the descriptor arrays for n members.
     int reserve(int n) { return ensure_capacity(n); }
     int harvest_events();
@@ -88,6 +92,11 @@ class Bucket {
     int *status_h_ = nullptr;      // pinned: one status word per pending recompute
     char *stage_h_ = nullptr;      // pinned: descriptor staging of pending recomputes
     std::vector<int> pending_;
+    double *res_rows_ = nullptr;              // residual scratch, sized for res_cap_ members
+    int *res_eidx_ = nullptr;
+    unsigned long long *res_bits_ = nullptr;
+    unsigned long long *res_host_ = nullptr;  // pinned
+    int res_cap_ = 0;
     GjWork gj_;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t gexec_ = nullptr;

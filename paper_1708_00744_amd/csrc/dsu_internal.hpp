@@ -190,6 +190,22 @@ hipError_t launch_flush_stream_x6(const DetDesc<float> *d, int ndesc, int np, in
 template <typename T>
 hipError_t launch_reset_state(const DetDesc<T> *d, const GjDesc *gj, double *drift, int ndesc, hipStream_t s);
 
+// Sampled residual of the inverse: out_bits[d] = bit pattern of
+// max_{s, j} |phi(r_{e_s}) . BT[j, :] - delta(j, e_s)| over `samples` (1..64,
+// <= n) electrons e_s = s * (n / samples) + (sweep mod (n / samples)).
+// Scratch: rows (ndesc x 64 x np FP64), eidx (ndesc x 64).
+template <typename T>
+hipError_t launch_resid(const DetDesc<T> *d, int ndesc, int n, int np, int samples, const int4 *kvec,
+                        double twopi_over_l, double *rows, int *eidx, unsigned long long *out_bits, hipStream_t s);
+
+// Left residual: out_bits[d] = bit pattern of max_{i, j} |(A^{-1} A - I)[i0 + i][j]|
+// over i < samples (1..64, <= n), i0 = (sweep mod (n / samples)) * samples,
+// with A rebuilt from the positions (no scratch); nmax = largest |component|
+// of the plane-wave integer vectors.
+template <typename T>
+hipError_t launch_resid_left(const DetDesc<T> *d, int ndesc, int n, int np, int samples, const int4 *kvec,
+                             double twopi_over_l, int nmax, unsigned long long *out_bits, hipStream_t s);
+
 // rows[c][j] = phi_j(pos_c): plane-wave orbital rows at `count` positions.
 hipError_t launch_pw_rows(const double *pos_dev, double *rows_dev, int n, int count, const int4 *kvec,
                           double twopi_over_l, hipStream_t s);

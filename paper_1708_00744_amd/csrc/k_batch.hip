@@ -773,4 +773,311 @@ hipError_t launch_reset_state(const DetDesc<T> *d, const GjDesc *gj, double *dri
 template hipError_t launch_reset_state<float>(const DetDesc<float> *, const GjDesc *, double *, int, hipStream_t);
 template hipError_t launch_reset_state<double>(const DetDesc<double> *, const GjDesc *, double *, int, hipStream_t);
 
+// ------------------------------------------------- sampled inverse residual
+// Sec. III checks the determinants against a direct calculation; between FP64
+// recomputes the batched form checks its inverse X against the Slater matrix
+// itself (rebuilt in FP64 from the positions) on a rotating sample of rows.
+// With S samples, stride = n / S and t = sweep mod stride:
+//   right: rows e_s = s * stride + t of A X - I,
+//          res[s][j] = phi(r_{e_s}) . BT[j, :] - delta(j, e_s)
+//          (BT = X^T row-major: column j of X is row j of BT);
+//   left:  rows i = t * S + s of X A - I,
+//          res[s][j] = sum_k BT[k][i] phi_j(r_k) - delta(i, j).
+// Both are skinny products on FP64 matrix cores (X converted exactly to FP64)
+// and end in a max |res| per determinant, kept as the bit pattern of a
+// non-negative double (those order like unsigned integers; a non-finite entry
+// counts as +inf).
+//
+// Operand layout of v_mfma_f64_16x16x4f64 with the k index permuted: at step
+// s (0..3) of a 16-wide k block c0, lane l supplies A[l%16][k] and B[k][l%16]
+// for k = c0 + 4 (l/16) + s, so each lane reads 4 consecutive k of its own
+// row; every k of the block is used exactly once, which is all the product
+// needs.
+
+__device__ __forceinline__ double resid_abs(double v) {
+    const double av = fabs(v);
+    return av <= 1.79769313486231570815e308 ? av : __builtin_inf();
+}
+
+__device__ __forceinline__ void resid_store_max(double m, unsigned long long *out) {
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+// rows[d][s][c] = phi_c(r_{e_s}) for c < n, 0 for n <= c < np and for the
+// padding samples s >= S (eidx = -1 there); grid (ndesc, SP).  Also clears
+// the determinant's result word.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_resid_rows(const DetDesc<T> *__restrict__ descs, int n, int np, int S,
+                                                         int SP, const int4 *__restrict__ kvec, double twopi_l,
+                                                         double *__restrict__ rows, int *__restrict__ eidx,
+                                                         unsigned long long *__restrict__ out_bits) {
+    const DetDesc<T> d = descs[blockIdx.x];
+    const int s = blockIdx.y;
+    const int stride = n / S;
+    const int e = s < S ? s * stride + (int)(d.st->sweep % (long long)stride) : -1;
+    double *r = rows + ((size_t)blockIdx.x * SP + s) * np;
+    if (threadIdx.x == 0) {
+        eidx[blockIdx.x * SP + s] = e;
+        if (s == 0) out_bits[blockIdx.x] = 0ull;
+    }
+    const double x = e >= 0 ? d.pos[3 * e + 0] : 0.0, y = e >= 0 ? d.pos[3 * e + 1] : 0.0,
+                 z = e >= 0 ? d.pos[3 * e + 2] : 0.0;
+    for (int c = threadIdx.x; c < np; c += kThreads)
+        r[c] = (e >= 0 && c < n) ? pw_orbital(kvec[c], twopi_l, x, y, z) : 0.0;
+}
+
+// Four consecutive elements of a row, as FP64.
+template <typename T> struct Quad;
+template <> struct Quad<float> {
+    static __device__ __forceinline__ void load(const float *p, double (&v)[4]) {
+        const f32x4 x = *reinterpret_cast<const DSU_GLOBAL f32x4 *>(gmem(p));
+        v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+    }
+};
+template <> struct Quad<double> {
+    static __device__ __forceinline__ void load(const double *p, double (&v)[4]) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 a = *reinterpret_cast<const DSU_GLOBAL d2 *>(gmem(p));
+        const d2 b = *reinterpret_cast<const DSU_GLOBAL d2 *>(gmem(p + 2));
+        v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
+    }
+};
+
+// Right residual: one wave per (64 rows j of BT, determinant); the 64 x SP
+// block BT[j, :] . rows[s, :] as 4 x SP/16 tiles, operands straight from
+// global memory (BT streamed once, the sample rows from L2), the next block's
+// loads issued before the current block's products.
+template <typename T, int SP>
+__global__ __launch_bounds__(64) void k_resid_prod(const DetDesc<T> *__restrict__ descs, int n, int np, int nblk,
+                                                   const double *__restrict__ rows, const int *__restrict__ eidx,
+                                                   unsigned long long *__restrict__ out_bits) {
+    constexpr int NT = SP / 16;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int di = blk / nblk, j0 = (blk % nblk) * 64;
+    const DetDesc<T> d = descs[di];
+    const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
+    const T *bp = d.bt + (size_t)(j0 + lr) * np + 4 * lk;
+    const double *rp = rows + ((size_t)di * SP + lr) * np + 4 * lk;
+    f64x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f64x4{0, 0, 0, 0};
+    double a[4][4], b[NT][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Quad<T>::load(bp + (size_t)16 * m * np, a[m]);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) Quad<double>::load(rp + (size_t)16 * t * np, b[t]);
+    for (int c0 = 0; c0 < np; c0 += 16) {
+        double an[4][4], bn[NT][4];
+        const int cn = c0 + 16 < np ? c0 + 16 : c0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) Quad<T>::load(bp + (size_t)16 * m * np + cn, an[m]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) Quad<double>::load(rp + (size_t)16 * t * np + cn, bn[t]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[m][t] = Mma<double>::mma(a[m][s], b[t][s], acc[m][t]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[m][q] = an[m][q];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[t][q] = bn[t][q];
+    }
+    // D[i][n] of tile (m, t): i = row0 + q * row_step (rows of BT), n = lr (sample)
+    double mx = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int e = eidx[di * SP + 16 * t + lr];
+        if (e < 0) continue;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = j0 + 16 * m + Mma<double>::row0(lane) + q * Mma<double>::row_step;
+                if (j < n) mx = fmax(mx, resid_abs(acc[m][t][q] - (j == e ? 1.0 : 0.0)));
+            }
+    }
+    resid_store_max(mx, out_bits + di);
+}
+
+template <typename T>
+hipError_t launch_resid(const DetDesc<T> *d, int ndesc, int n, int np, int samples, const int4 *kvec,
+                        double twopi_over_l, double *rows, int *eidx, unsigned long long *out_bits, hipStream_t s) {
+    if (samples < 1 || samples > 64 || samples > n) return hipErrorInvalidValue;
+    const int sp = samples <= 16 ? 16 : (samples <= 32 ? 32 : 64);
+    hipLaunchKernelGGL((k_resid_rows<T>), dim3(ndesc, sp), dim3(kThreads), 0, s, d, n, np, samples, sp, kvec,
+                       twopi_over_l, rows, eidx, out_bits);
+    const int nblk = np / 64;
+    const dim3 grid(ndesc * nblk);
+    if (sp == 16)
+        hipLaunchKernelGGL((k_resid_prod<T, 16>), grid, dim3(64), 0, s, d, n, np, nblk, rows, eidx, out_bits);
+    else if (sp == 32)
+        hipLaunchKernelGGL((k_resid_prod<T, 32>), grid, dim3(64), 0, s, d, n, np, nblk, rows, eidx, out_bits);
+    else
+        hipLaunchKernelGGL((k_resid_prod<T, 64>), grid, dim3(64), 0, s, d, n, np, nblk, rows, eidx, out_bits);
+    return hipGetLastError();
+}
+template hipError_t launch_resid<float>(const DetDesc<float> *, int, int, int, int, const int4 *, double, double *,
+                                        int *, unsigned long long *, hipStream_t);
+template hipError_t launch_resid<double>(const DetDesc<double> *, int, int, int, int, const int4 *, double, double *,
+                                         int *, unsigned long long *, hipStream_t);
+
+// Left residual: one workgroup per (256 columns j, determinant), wave w on
+// columns 64w .. 64w+63, all S rows i0 .. i0+S-1 (i0 = t S) as SP/16 x 4
+// tiles per wave.  A operand X[i][k] = BT[k][i0+i] (16 consecutive elements
+// of row k per load); B operand A[k][j] = phi_j(r_k) evaluated by the lane
+// from per-electron phase tables in LDS: with q = 2 pi / L,
+// exp(i q n.r) = Ex^nx Ey^ny Ez^nz and E^-m = conj(E^m), so 16 electrons need
+// 3 (nmax + 1) sincos each for all 256 columns (the workgroup fills the table
+// together), and an orbital is two complex products.  nmax <= kPwTab (true
+// for every n the batched form takes: nmax is about (3 n / 8 pi)^(1/3)).
+template <typename T, int SP>
+__global__ __launch_bounds__(kThreads) void k_resid_left(const DetDesc<T> *__restrict__ descs, int n, int np, int S,
+                                                         int nblk, const int4 *__restrict__ kvec, double twopi_l,
+                                                         int nmax, unsigned long long *__restrict__ out_bits) {
+#pragma clang fp contract(off)
+    constexpr int NT = SP / 16;
+    constexpr int XL = (16 * SP + kThreads - 1) / kThreads;  // X elements each thread stages per step
+    __shared__ double s_c[16][3][kPwTab + 1], s_s[16][3][kPwTab + 1];
+    __shared__ double s_x[16][SP + 1];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int di = blk / nblk;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
+    const int j0 = (blk % nblk) * 256 + 64 * wave;
+    const DetDesc<T> d = descs[di];
+    DSU_GLOBAL const T *bt = gmem(d.bt);
+    DSU_GLOBAL const double *pos = gmem(d.pos);
+    const int stride = n / S;
+    const int i0 = (int)(d.st->sweep % (long long)stride) * S;
+    int4 kv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int j = j0 + 16 * u + lr;
+        kv[u] = j < n ? kvec[j] : int4{0, 0, 0, 3};
+    }
+    f64x4 acc[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[t][u] = f64x4{0, 0, 0, 0};
+    // X[i][k] = BT[k][i0 + i] for the 16 electrons of a step: element v of the
+    // step is (e = v / SP, i = v % SP); loads of the next step are in flight
+    // while the current one is computed
+    T xr[XL];
+    auto load_x = [&](int c) {
+#pragma unroll
+        for (int q = 0; q < XL; ++q) {
+            const int v = tid + q * kThreads, e = v / SP, i = v % SP, k = c + e;
+            const bool in = v < 16 * SP && k < n && i < S;
+            xr[q] = bt[in ? (size_t)k * np + i0 + i : 0];
+            if (!in) xr[q] = T(0);
+        }
+    };
+    load_x(0);
+#pragma unroll 1
+    for (int c0 = 0; c0 < n; c0 += 16) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < XL; ++q) {
+            const int v = tid + q * kThreads;
+            if (v < 16 * SP) s_x[v / SP][v % SP] = (double)xr[q];
+        }
+        if (c0 + 16 < n) load_x(c0 + 16);
+        for (int v = tid; v < 16 * 3 * (nmax + 1); v += kThreads) {
+            const int e = v / (3 * (nmax + 1)), r = v % (3 * (nmax + 1)), ax = r / (nmax + 1), m = r % (nmax + 1);
+            const int k = c0 + e < n ? c0 + e : 0;
+            double sn, cs;
+            sincos(twopi_l * ((double)m * pos[3 * k + ax]), &sn, &cs);
+            s_c[e][ax][m] = cs;
+            s_s[e][ax][m] = sn;
+        }
+        __syncthreads();
+        // one electron of the lane's four at a time: its four orbitals, then
+        // the step's products (keeps the live registers to one step's operands)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int e = 4 * lk + s;
+            const bool kin = c0 + e < n;
+            double bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                double o;
+                if (kv[u].w == 0) {
+                    o = 1.0;
+                } else if (kv[u].w == 3) {
+                    o = 0.0;
+                } else {
+                    const int ax_n[3] = {kv[u].x, kv[u].y, kv[u].z};
+                    double re = 1.0, im = 0.0;
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const int m = ax_n[ax] < 0 ? -ax_n[ax] : ax_n[ax];
+                        const double fc = s_c[e][ax][m];
+                        const double fs = ax_n[ax] < 0 ? -s_s[e][ax][m] : s_s[e][ax][m];
+                        const double tt = re * fc - im * fs;
+                        im = re * fs + im * fc;
+                        re = tt;
+                    }
+                    o = kv[u].w == 1 ? re : im;
+                }
+                bv[u] = kin ? o : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const double a = s_x[e][16 * t + lr];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[t][u] = Mma<double>::mma(a, bv[u], acc[t][u]);
+            }
+        }
+    }
+    double mx = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int j = j0 + 16 * u + lr;
+        if (j >= n) continue;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * t + Mma<double>::row0(lane) + q * Mma<double>::row_step;
+                if (i < S) mx = fmax(mx, resid_abs(acc[t][u][q] - (i0 + i == j ? 1.0 : 0.0)));
+            }
+    }
+    resid_store_max(mx, out_bits + di);
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0ull;
+}
+
+template <typename T>
+hipError_t launch_resid_left(const DetDesc<T> *d, int ndesc, int n, int np, int samples, const int4 *kvec,
+                             double twopi_over_l, int nmax, unsigned long long *out_bits, hipStream_t s) {
+    if (samples < 1 || samples > 64 || samples > n || nmax > kPwTab) return hipErrorInvalidValue;
+    const int sp = samples <= 16 ? 16 : (samples <= 32 ? 32 : 64);
+    hipLaunchKernelGGL(k_zero_u64, dim3((ndesc + 255) / 256), dim3(256), 0, s, out_bits, ndesc);
+    const int nblk = (np + 255) / 256;
+    const dim3 grid(ndesc * nblk);
+#define DSU_L(SPV)                                                                                              \
+    if (sp == SPV)                                                                                              \
+        hipLaunchKernelGGL((k_resid_left<T, SPV>), grid, dim3(kThreads), 0, s, d, n, np, samples, nblk, kvec,   \
+                           twopi_over_l, nmax, out_bits);
+    DSU_L(16) DSU_L(32) DSU_L(64)
+#undef DSU_L
+    return hipGetLastError();
+}
+template hipError_t launch_resid_left<float>(const DetDesc<float> *, int, int, int, int, const int4 *, double, int,
+                                             unsigned long long *, hipStream_t);
+template hipError_t launch_resid_left<double>(const DetDesc<double> *, int, int, int, int, const int4 *, double, int,
+                                              unsigned long long *, hipStream_t);
+
 }  // namespace dsu

@@ -95,6 +95,9 @@ SIGNATURES = {
     "dsu_batch_set_watchdog": (C.c_int, [_vp, _i32]),
     "dsu_batch_watchdog_count": (C.c_int, [_vp, _pi64]),
     "dsu_batch_poison_row": (C.c_int, [_vp, _i32, _i32]),
+    "dsu_batch_residual": (C.c_int, [_vp, _i32, _pd, _pd]),
+    "dsu_batch_set_residual_watchdog": (C.c_int, [_vp, _i32, _dbl]),
+    "dsu_batch_accuracy": (C.c_int, [_vp, _pd, _pd, _pi64]),
     "dsu_batch_get_inverse": (C.c_int, [_vp, _i32, _pd]),
     "dsu_batch_set_trace": (C.c_int, [_vp, _i32]),
     "dsu_batch_get_trace": (C.c_int, [_vp, _i32, _pd, _pu8]),
@@ -419,6 +422,26 @@ class Batch:
         c = C.c_int64()
         _check(lib().dsu_batch_watchdog_count(self._h, C.byref(c)))
         return c.value
+
+    def residual(self, samples=32, right=True, left=True):
+        """Sampled (right, left) residuals per determinant: max |A A^-1 - I| and
+        max |A^-1 A - I| over `samples` rows each (dsu_batch_residual); a side
+        not asked for is None."""
+        r = np.zeros(self.ndet) if right else None
+        lf = np.zeros(self.ndet) if left else None
+        _check(lib().dsu_batch_residual(self._h, int(samples), _dp(r) if right else None, _dp(lf) if left else None))
+        return r, lf
+
+    def set_residual_watchdog(self, samples, threshold=1e-3):
+        _check(lib().dsu_batch_set_residual_watchdog(self._h, int(samples), float(threshold)))
+
+    def accuracy(self):
+        """Latest sampled right residual of the residual watchdog, drift of the
+        latest recompute, and the residual watchdog's recompute count."""
+        res, drift = np.zeros(self.ndet), np.zeros(self.ndet)
+        cnt = C.c_int64()
+        _check(lib().dsu_batch_accuracy(self._h, _dp(res), _dp(drift), C.byref(cnt)))
+        return {"residual": res, "drift": drift, "recomputes": cnt.value}
 
     def poison_row(self, det, row):
         """Test aid: NaN into one row of a determinant's device inverse."""

@@ -361,13 +361,15 @@ def test_walker_moves_equals_walker_run():
     pw = np.stack([inputs.positions(seed, w, n, L) for w in range(nw)])
     aw = np.stack([oracle.pw_matrix(kv, L, pw[w]) for w in range(nw)])
     iw = np.stack([oracle.inverse(aw[w])[0] for w in range(nw)])
-    nacc, _ = oracle.walkers_moves(n, L, [seed] * nw, list(range(nw)), sigma, 0, 5, n, pw, aw, iw)
+    rw = np.zeros((nw, n))
+    nacc, _ = oracle.walkers_moves(n, L, [seed] * nw, list(range(nw)), sigma, 0, 5, n, pw, aw, iw, ratios=rw)
     for w in range(nw):
         p1 = inputs.positions(seed, w, n, L)
         a1 = oracle.pw_matrix(kv, L, p1)
         i1 = oracle.inverse(a1)[0]
-        _, c1 = oracle.walker_moves(n, L, seed, w, 0, sigma, 0, 5, n, p1, a1, i1)
+        r1, c1 = oracle.walker_moves(n, L, seed, w, 0, sigma, 0, 5, n, p1, a1, i1)
         assert nacc[w] == c1 and c1 > 0
+        np.testing.assert_array_equal(rw[w], r1)
         np.testing.assert_array_equal(pw[w], p1)
         np.testing.assert_array_equal(iw[w], i1)
 
@@ -400,6 +402,46 @@ def test_residual_exact_on_constructed_inverse():
             assert oracle.residual(x, a) == abs(d) * np.abs(a[j]).max(), (i, j)
     # a transposed inverse of a non-symmetric matrix is not an inverse
     assert oracle.residual(np.ascontiguousarray(exact.T), a) >= 1.0
+
+def test_residual_rows_exact_on_constructed_inverse():
+    """orc_residual_rows = max |(A Ainv - I)[r, :]| over the listed rows (and
+    orc_residual_left_rows the same for Ainv A - I):
+    with Ainv = A^-1 + d e_i e_j^T the right residual is d A[:, i] e_j^T, so
+    over rows S the value is |d| max_{r in S} |A[r, i]| -- exactly, on a
+    unimodular integer matrix.  A left residual, a transposed product, a
+    missing diagonal term or rows taken from the wrong operand give another
+    number; every row listed gives the full right residual, and rows outside
+    [0, n) are skipped."""
+    n = 6
+    a = unimodular_integer_matrix(93, n)
+    exact = np.array([[float(x) for x in row] for row in frac_inverse(a.astype(int).tolist())])
+    assert oracle.residual_rows(exact, a, list(range(n))) == 0.0
+    for rows in ([0, 3], [5], [1, 2, 4], [2, -1, n]):
+        valid = [r for r in rows if 0 <= r < n]
+        for i in range(n):
+            for j in range(n):
+                d = (2.0 ** -9) * (1 + (2 * i + j) % 4)
+                x = exact.copy()
+                x[i, j] += d
+                want = abs(d) * np.abs(a[valid, i]).max()
+                assert oracle.residual_rows(x, a, rows) == want, (rows, i, j)
+    # the left residual of the same perturbation is d e_i A[j, :]: nonzero only
+    # on row i, where it is |d| max |A[j, :]|
+    for rows in ([0, 3], [1], [1, 2, 4], [2, -1, n, 1]):
+        for i in range(n):
+            for j in range(n):
+                d = (2.0 ** -9) * (1 + (2 * i + j) % 4)
+                x = exact.copy()
+                x[i, j] += d
+                want = abs(d) * np.abs(a[j]).max() if i in rows else 0.0
+                assert oracle.residual_left_rows(x, a, rows) == want, (rows, i, j)
+    # on one perturbed inverse the right residual sees column i of A and the
+    # left one row j of A: each function returns its own
+    x = exact.copy()
+    x[1, 4] += 2.0 ** -8
+    assert oracle.residual_rows(x, a, list(range(n))) == 2.0 ** -8 * np.abs(a[:, 1]).max()
+    assert oracle.residual(x, a) == 2.0 ** -8 * np.abs(a[4]).max()
+
 
 # ------------------------------------- gradient rows and ratio gradients
 def test_plane_wave_gradient_values_and_differences():
