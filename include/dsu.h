@@ -305,6 +305,21 @@ int dsu_batch_watchdog_count(dsu_batch *b, int64_t *recomputes);
  * be NULL (its kernel is skipped), not both.  samples in [1, min(64, n)],
  * else DSU_EINVAL.  Synchronises. */
 int dsu_batch_residual(dsu_batch *b, int32_t samples, double *right_host, double *left_host);
+/* dsu_batch_residual for callers that cannot allocate device memory (code
+ * under HIP graph capture nearby, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, with every device buffer
+ * (sample rows, sample indices, result words) carved from one static 32 MiB
+ * array per GPU that the library holds until the process ends; nothing is
+ * allocated, on the device or the host.  Needed: 16 * ndet and
+ * 4 * ndet * S' bytes, each rounded up to 256, plus ndet * S' * np * 8
+ * (S' = samples rounded up to 16, 32 or 64; np = n rounded up to 64;
+ * ndet = walkers * spins), at most 32 MiB: e.g. 32 determinants of
+ * n = 4096 with up to 32 samples; a batch that needs more gets DSU_EINVAL
+ * with the figure, and nothing runs.  Call with the batch's device current.  Every call on one GPU
+ * shares that GPU's array, whose contents the next call overwrites (the
+ * kernels clear what must start at zero): calls that overlap on one GPU, from
+ * threads or streams, race.  Synchronises the batch's stream. */
+int dsu_batch_residual_noalloc(dsu_batch *b, int32_t samples, double *right_host, double *left_host);
 /* Residual watchdog (the adaptive recompute of the FP32 form): after every
  * sweep, the sampled right residual above for every determinant; a
  * determinant whose right residual exceeds `threshold` (or is not finite)

@@ -15,6 +15,7 @@
 #include <cstddef>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 namespace dsu {
 
@@ -502,6 +503,51 @@ int Bucket::residual(int samples, std::vector<double> *right, std::vector<double
     return DSU_OK;
 }
 
+static int resid_pad(int samples) { return samples <= 16 ? 16 : (samples <= 32 ? 32 : 64); }
+
+size_t Bucket::residual_scratch_bytes(int samples) const {
+    const size_t nd = dets.size(), sp = (size_t)resid_pad(samples);
+    return align256(2 * nd * sizeof(unsigned long long)) + align256(nd * sp * sizeof(int)) +
+           nd * sp * (size_t)sh.np * sizeof(double);
+}
+
+int Bucket::residual_into(int samples, double *right_host, double *left_host, void *scratch, size_t scratch_bytes) {
+    const int nd = (int)dets.size();
+    if (nd == 0 || (!right_host && !left_host)) return DSU_OK;
+    if (samples < 1 || samples > 64 || samples > sh.n)
+        return fail(DSU_EINVAL, "residual samples %d outside [1, min(64, n = %d)]", samples, sh.n);
+    const size_t need = residual_scratch_bytes(samples);
+    if (need > scratch_bytes)
+        return fail(DSU_EINVAL,
+                    "%d determinants of n = %d with %d samples need %zu bytes of residual scratch; the "
+                    "allocation-free entry point has %zu (use dsu_batch_residual)",
+                    nd, sh.n, samples, need, scratch_bytes);
+    // layout: result words (right, then left), sample indices, sample rows
+    char *base = static_cast<char *>(scratch);
+    unsigned long long *bits = reinterpret_cast<unsigned long long *>(base);
+    const size_t sp = (size_t)resid_pad(samples);
+    int *eidx = reinterpret_cast<int *>(base + align256(2 * (size_t)nd * sizeof(unsigned long long)));
+    double *rows = reinterpret_cast<double *>(reinterpret_cast<char *>(eidx) + align256((size_t)nd * sp * sizeof(int)));
+    const bool f64 = sh.prec == DSU_FP64;
+    if (right_host) {
+        HIPCHK(f64 ? launch_resid<double>((const DetDesc<double> *)ddesc_, nd, sh.n, sh.np, samples, kvec, twopi_l,
+                                          rows, eidx, bits, stream)
+                   : launch_resid<float>((const DetDesc<float> *)ddesc_, nd, sh.n, sh.np, samples, kvec, twopi_l, rows,
+                                         eidx, bits, stream));
+        HIPCHK(hipMemcpyAsync(right_host, bits, sizeof(double) * nd, hipMemcpyDeviceToHost, stream));
+    }
+    if (left_host) {
+        HIPCHK(f64 ? launch_resid_left<double>((const DetDesc<double> *)ddesc_, nd, sh.n, sh.np, samples, kvec,
+                                               twopi_l, kmax_comp, bits + nd, stream)
+                   : launch_resid_left<float>((const DetDesc<float> *)ddesc_, nd, sh.n, sh.np, samples, kvec,
+                                              twopi_l, kmax_comp, bits + nd, stream));
+        HIPCHK(hipMemcpyAsync(left_host, bits + nd, sizeof(double) * nd, hipMemcpyDeviceToHost, stream));
+    }
+    // the words are the bit patterns of the doubles: copied as they are
+    HIPCHK(hipStreamSynchronize(stream));
+    return DSU_OK;
+}
+
 int Bucket::recompute(const std::vector<int> &which, double *drift_host) {
     if (which.empty()) return DSU_OK;
     HIPCHK(hipStreamSynchronize(stream));
@@ -779,6 +825,42 @@ extern "C" int dsu_batch_residual(dsu_batch *b, int32_t samples, double *right_h
     if (right_host) std::copy(r.begin(), r.end(), right_host);
     if (left_host) std::copy(l.begin(), l.end(), left_host);
     return DSU_OK;
+}
+
+// --------------------------------------------------------------------------
+// Allocation-free residual: the device buffers of dsu_batch_residual carved
+// from one file-scope array.  Each GPU holds its own copy of the array, so its
+// address is looked up once per device (hipGetSymbolAddress, with that device
+// current) and only that address is handed to kernels and copies: in host code
+// the array's name is a host-side stand-in, not a device address.
+static constexpr size_t kResidScratchBytes = (size_t)32 << 20;  // 32 MiB per device
+static __device__ __align__(256) unsigned char scratch[kResidScratchBytes];
+static std::mutex g_scratch_mu;
+static constexpr int kMaxDevices = 64;
+static void *g_scratch_dev[kMaxDevices] = {};
+
+static int resid_scratch(void **out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DSU_EDEVICE, "device %d outside the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(DSU_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_residual_noalloc(dsu_batch *b, int32_t samples, double *right_host, double *left_host) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    if (!right_host && !left_host) return fail(DSU_EINVAL, "both outputs are NULL");
+    void *p = nullptr;
+    CHK(resid_scratch(&p));
+    return b->bk.residual_into(samples, right_host, left_host, p, kResidScratchBytes);
 }
 
 extern "C" int dsu_batch_set_residual_watchdog(dsu_batch *b, int32_t samples, double threshold) {

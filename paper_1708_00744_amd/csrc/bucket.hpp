@@ -76,6 +76,12 @@ class Bucket {
     // max over `samples` rows of |A A^{-1} - I| (launch_resid), left = the same
     // for A^{-1} A - I (launch_resid_left); either may be NULL.  Waits.
     int residual(int samples, std::vector<double> *right, std::vector<double> *left);
+    // The same into caller memory, with every device buffer carved from
+    // `scratch` (scratch_bytes long): nothing allocated.  right_host and
+    // left_host receive one double per member (either may be NULL).
+    int residual_into(int samples, double *right_host, double *left_host, void *scratch, size_t scratch_bytes);
+    // Scratch residual_into needs for the present members.
+    size_t residual_scratch_bytes(int samples) const;
     // Pre-size the descriptor arrays for n members.
     int reserve(int n) { return ensure_capacity(n); }
     int harvest_events();

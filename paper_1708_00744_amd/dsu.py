@@ -96,6 +96,7 @@ SIGNATURES = {
     "dsu_batch_watchdog_count": (C.c_int, [_vp, _pi64]),
     "dsu_batch_poison_row": (C.c_int, [_vp, _i32, _i32]),
     "dsu_batch_residual": (C.c_int, [_vp, _i32, _pd, _pd]),
+    "dsu_batch_residual_noalloc": (C.c_int, [_vp, _i32, _pd, _pd]),
     "dsu_batch_set_residual_watchdog": (C.c_int, [_vp, _i32, _dbl]),
     "dsu_batch_accuracy": (C.c_int, [_vp, _pd, _pd, _pi64]),
     "dsu_batch_get_inverse": (C.c_int, [_vp, _i32, _pd]),
@@ -430,6 +431,15 @@ class Batch:
         r = np.zeros(self.ndet) if right else None
         lf = np.zeros(self.ndet) if left else None
         _check(lib().dsu_batch_residual(self._h, int(samples), _dp(r) if right else None, _dp(lf) if left else None))
+        return r, lf
+
+    def residual_noalloc(self, samples=32, right=True, left=True):
+        """dsu_batch_residual_noalloc: the same residuals, device buffers from
+        the library's static per-GPU scratch array."""
+        r = np.zeros(self.ndet) if right else None
+        lf = np.zeros(self.ndet) if left else None
+        _check(lib().dsu_batch_residual_noalloc(self._h, int(samples), _dp(r) if right else None,
+                                                _dp(lf) if left else None))
         return r, lf
 
     def set_residual_watchdog(self, samples, threshold=1e-3):
