@@ -430,11 +430,12 @@ template <typename T> int Bucket::recompute_async_t(const std::vector<int> &whic
             hipError_t e =
                 launch_build_pw_transpose(sub_pos_ + base + g0, gj_.mptr, cnt, sh.n, sh.np, kvec, twopi_l, stream);
             if (e != hipSuccess) return e;
-            e = launch_gj_invert(gj_.gdesc, gj_.rdesc, cnt, sh.n, sh.np, gj_.nb, stream);
+            const GjDesc *res = nullptr;
+            e = gj_.invert(cnt, sh.n, stream, &res);
             if (e != hipSuccess) return e;
-            e = launch_cast_perm<T>(gj_.gdesc, (T *const *)(sub_bt_ + base + g0), cnt, sh.n, sh.np, stream);
+            e = launch_cast_perm<T>(res, (T *const *)(sub_bt_ + base + g0), cnt, sh.n, sh.np, stream);
             if (e != hipSuccess) return e;
-            return launch_reset_state<T>(dd + g0, gj_.gdesc, drift_ + base + g0, cnt, stream);
+            return launch_reset_state<T>(dd + g0, res, drift_ + base + g0, cnt, stream);
         }));
         HIPCHK(hipMemcpyAsync(status_h_ + base + g0, gj_.status, sizeof(int) * cnt, hipMemcpyDeviceToHost, stream));
     }
@@ -730,9 +731,9 @@ extern "C" int dsu_batch_create(int32_t walkers, int32_t n, int32_t spins, int32
     b->last_right.assign(b->ndet, 0.0);
     b->last_drift.assign(b->ndet, 0.0);
     const BucketShape sh = BucketShape::make(n, k_delay, precision);
-    // recompute as many determinants at once as fit in ~8 GiB of workspace
+    // recompute as many determinants at once as fit in ~16 GiB of workspace
     const size_t per = GjWork::bytes_per(sh.np, n);
-    int group = (int)std::min<size_t>((size_t)b->ndet, std::max<size_t>(1, ((size_t)8 << 30) / per));
+    int group = (int)std::min<size_t>((size_t)b->ndet, std::max<size_t>(1, ((size_t)16 << 30) / per));
     int rc = b->bk.init(sh, k_delay, box_L, hip_stream, group);
     if (rc == DSU_OK) rc = dev_alloc((void **)&b->store, sh.det_bytes() * b->ndet);
     if (rc != DSU_OK) {

@@ -21,6 +21,7 @@ using dsu::dalloc;
 using dsu::dev_alloc;
 using dsu::dfree;
 using dsu::fail;
+using dsu::GjDesc;
 using dsu::GjWork;
 using dsu::kpad;
 using dsu::make_stream;
@@ -87,12 +88,13 @@ static void walker_free(dsu_walker *w) {
 
 static int walker_recompute(dsu_walker *w, double *fresh_logdet, int *fresh_sign) {
     HIPCHK(launch_load_transpose(w->a_ptr, w->gj.mptr, 1, w->n, w->np, w->np, w->stream));
-    HIPCHK(launch_gj_invert(w->gj.gdesc, w->gj.rdesc, 1, w->n, w->np, w->gj.nb, w->stream));
+    const GjDesc *res = nullptr;
+    HIPCHK(w->gj.invert(1, w->n, w->stream, &res));
     if (w->prec == DSU_FP64)
-        HIPCHK(launch_cast_perm<double>(w->gj.gdesc, reinterpret_cast<double *const *>(w->bt_ptr), 1, w->n, w->np,
+        HIPCHK(launch_cast_perm<double>(res, reinterpret_cast<double *const *>(w->bt_ptr), 1, w->n, w->np,
                                         w->stream));
     else
-        HIPCHK(launch_cast_perm<float>(w->gj.gdesc, reinterpret_cast<float *const *>(w->bt_ptr), 1, w->n, w->np,
+        HIPCHK(launch_cast_perm<float>(res, reinterpret_cast<float *const *>(w->bt_ptr), 1, w->n, w->np,
                                        w->stream));
     double ld = 0.0;
     int sg = 0, st = 0;

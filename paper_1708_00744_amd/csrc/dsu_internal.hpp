@@ -60,13 +60,6 @@ template <typename T> struct FlushDesc {
     int ldc;
 };
 
-// One explicit rank-k update M <- M - W Q  (Gauss-Jordan panel update).
-struct RankDesc {
-    double *m;        // np x np
-    const double *w;  // np x kp
-    const double *q;  // kp x np
-};
-
 // Per-determinant running state of the batched form (device memory).
 struct DetState {
     double logdet;
@@ -113,17 +106,17 @@ template <typename T> struct DetDesc {
 template <typename T>
 hipError_t launch_flush(const FlushDesc<T> *descs_dev, int ndesc, int n, int np, int kslots, int mode,
                         hipStream_t s);
-// M <- M - W Q for `ndesc` matrices, rank kslots (<= 64).
-hipError_t launch_rank_update(const RankDesc *descs_dev, int ndesc, int np, int kslots, hipStream_t s);
 
 // FP64 inversion by blocked Gauss-Jordan with partial pivoting.
 struct GjDesc {
     double *m;        // np x np work (in: A^T padded with identity; out: inverse scrambled)
+    double *m2;       // np x np: the other buffer of the ping-pong trailing update
     double *panel;    // np x nb
     double *w;        // np x nb
     double *q;        // nb x np
     int *piv;         // n pivots
     int *perm;        // np final column permutation
+    int *rowsrc;      // np: the panel's row interchanges, composed (row i <- row rowsrc[i])
     double *logdet;   // out
     int *sign;        // out
     int *status;      // out: 0 or -3 singular
@@ -136,8 +129,11 @@ struct GjDesc {
 template <typename T> struct RatioFloor;
 template <> struct RatioFloor<double> { static constexpr double value = 1e-12; };
 template <> struct RatioFloor<float> { static constexpr double value = 1e-6; };
-hipError_t launch_gj_invert(const GjDesc *descs_dev, const RankDesc *rank_dev, int ndesc, int n, int np,
-                            int nb, hipStream_t s);
+// Two descriptor sets of the same matrices with m and m2 exchanged: panel p
+// reads set (p mod 2)'s m and writes its m2.  *final_set receives the set
+// whose m holds the result (for launch_cast_perm).
+hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc, int n, int np, int nb,
+                            hipStream_t s, const GjDesc **final_set);
 // BT[i][j] = T(M[i][perm[j]]) for i, j < n, zero padding elsewhere.
 template <typename T>
 hipError_t launch_cast_perm(const GjDesc *gj_dev, T *const *bt_dev, int ndesc, int n, int np, hipStream_t s);

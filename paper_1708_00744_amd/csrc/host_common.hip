@@ -1,6 +1,8 @@
 // host_common.hip -- implementation of host_common.hpp.
 #include "host_common.hpp"
 
+#include <utility>
+
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -62,7 +64,7 @@ static int gj_panel_width(int n) { return n >= 512 ? 64 : (n >= 64 ? 32 : 16); }
 
 size_t GjWork::bytes_per(int np_, int n) {
     const size_t nb_ = gj_panel_width(n);
-    return (size_t)np_ * np_ * 8 + (size_t)np_ * nb_ * 8 * 3 + (size_t)np_ * 8 + 128;
+    return (size_t)np_ * np_ * 8 * 2 + (size_t)np_ * nb_ * 8 * 3 + (size_t)np_ * 12 + 128;
 }
 
 int GjWork::alloc(int groups, int np_, int n) {
@@ -71,41 +73,44 @@ int GjWork::alloc(int groups, int np_, int n) {
     nb = gj_panel_width(n);
     const size_t np2 = (size_t)np * np;
     CHK(dalloc(&m, np2 * g));
+    CHK(dalloc(&m2, np2 * g));
     CHK(dalloc(&panel, (size_t)np * nb * g));
     CHK(dalloc(&w, (size_t)np * nb * g));
     CHK(dalloc(&q, (size_t)np * nb * g));
     CHK(dalloc(&logdet, g));
     CHK(dalloc(&piv, (size_t)np * g));
     CHK(dalloc(&perm, (size_t)np * g));
+    CHK(dalloc(&rowsrc, (size_t)np * g));
     CHK(dalloc(&sign, g));
     CHK(dalloc(&status, g));
     CHK(dalloc(&pmax, g));
     CHK(dalloc(&gdesc, g));
-    CHK(dalloc(&rdesc, g));
+    CHK(dalloc(&gdesc_b, g));
     CHK(dalloc(&mptr, g));
-    std::vector<GjDesc> gd(g);
-    std::vector<RankDesc> rd(g);
+    std::vector<GjDesc> ga(g), gb(g);
     std::vector<double *> mp(g);
     for (int i = 0; i < g; ++i) {
-        gd[i] = GjDesc{m + np2 * i, panel + (size_t)np * nb * i, w + (size_t)np * nb * i, q + (size_t)np * nb * i,
-                       piv + (size_t)np * i, perm + (size_t)np * i, logdet + i, sign + i, status + i, pmax + i};
-        rd[i] = RankDesc{gd[i].m, gd[i].w, gd[i].q};
-        mp[i] = gd[i].m;
+        ga[i] = GjDesc{m + np2 * i, m2 + np2 * i, panel + (size_t)np * nb * i, w + (size_t)np * nb * i,
+                       q + (size_t)np * nb * i, piv + (size_t)np * i, perm + (size_t)np * i, rowsrc + (size_t)np * i,
+                       logdet + i, sign + i, status + i, pmax + i};
+        gb[i] = ga[i];
+        std::swap(gb[i].m, gb[i].m2);
+        mp[i] = ga[i].m;
     }
-    HIPCHK(hipMemcpy(gdesc, gd.data(), sizeof(GjDesc) * g, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(rdesc, rd.data(), sizeof(RankDesc) * g, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(gdesc, ga.data(), sizeof(GjDesc) * g, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(gdesc_b, gb.data(), sizeof(GjDesc) * g, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(mptr, mp.data(), sizeof(double *) * g, hipMemcpyHostToDevice));
     return DSU_OK;
 }
 
 void GjWork::release() {
-    for (void *p : {(void *)m, (void *)panel, (void *)w, (void *)q, (void *)logdet, (void *)piv, (void *)perm,
-                    (void *)sign, (void *)status, (void *)gdesc, (void *)rdesc, (void *)mptr, (void *)pmax})
+    for (void *p : {(void *)m, (void *)m2, (void *)panel, (void *)w, (void *)q, (void *)logdet, (void *)piv,
+                    (void *)perm, (void *)rowsrc, (void *)sign, (void *)status, (void *)gdesc, (void *)gdesc_b,
+                    (void *)mptr, (void *)pmax})
         dfree(p);
-    m = panel = w = q = logdet = pmax = nullptr;
-    piv = perm = sign = status = nullptr;
-    gdesc = nullptr;
-    rdesc = nullptr;
+    m = m2 = panel = w = q = logdet = pmax = nullptr;
+    piv = perm = rowsrc = sign = status = nullptr;
+    gdesc = gdesc_b = nullptr;
     mptr = nullptr;
 }
 

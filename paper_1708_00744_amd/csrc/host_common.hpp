@@ -42,11 +42,17 @@ inline size_t elem_size(int prec) { return prec == DSU_FP64 ? sizeof(double) : s
 // Workspace of the blocked Gauss-Jordan inversion for `g` matrices at once.
 struct GjWork {
     int g = 0, np = 0, nb = 32;
-    double *m = nullptr, *panel = nullptr, *w = nullptr, *q = nullptr, *logdet = nullptr, *pmax = nullptr;
-    int *piv = nullptr, *perm = nullptr, *sign = nullptr, *status = nullptr;
-    GjDesc *gdesc = nullptr;
-    RankDesc *rdesc = nullptr;
-    double **mptr = nullptr;
+    double *m = nullptr, *m2 = nullptr, *panel = nullptr, *w = nullptr, *q = nullptr, *logdet = nullptr,
+           *pmax = nullptr;
+    int *piv = nullptr, *perm = nullptr, *rowsrc = nullptr, *sign = nullptr, *status = nullptr;
+    GjDesc *gdesc = nullptr;   // set A: m = first buffer (the input, see mptr)
+    GjDesc *gdesc_b = nullptr; // set B: the buffers exchanged
+    double **mptr = nullptr;   // per matrix: the input buffer (set A's m)
+    // Invert the first `cnt` matrices (inputs in mptr); returns the descriptor
+    // set holding the result.
+    hipError_t invert(int cnt, int n, hipStream_t s, const GjDesc **final_set) const {
+        return launch_gj_invert(gdesc, gdesc_b, cnt, n, np, nb, s, final_set);
+    }
     int alloc(int groups, int np_, int n);
     void release();
     static size_t bytes_per(int np_, int n);

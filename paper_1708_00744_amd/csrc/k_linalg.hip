@@ -10,8 +10,8 @@
 //    owns 64 rows and does the three products back to back on matrix cores
 //    (v_mfma_*_16x16x4), reading its rows of BT twice and writing them once.
 //  * k_flush_valu: the same update with vector ALUs, one wave per row (small k).
-//  * k_rank_update: M <- M - W Q (the trailing update of the Gauss-Jordan
-//    inversion), the third product of the flush on its own.
+//  * k_gj_update: the trailing update of the Gauss-Jordan inversion,
+//    M' = (row-interchanged M) - W Q, on matrix cores.
 //  * Gauss-Jordan inversion with partial pivoting in FP64, blocked by panels of
 //    nb columns: the O(N^3) explicit route the paper uses for direct checks.
 #include "dsu_internal.hpp"
@@ -150,33 +150,6 @@ template hipError_t launch_flush<float>(const FlushDesc<float> *, int, int, int,
 template hipError_t launch_flush<double>(const FlushDesc<double> *, int, int, int, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// M <- M - W Q  (FP64), W np x KP (ld KP), Q KP x np.
-// ---------------------------------------------------------------------------
-template <int KP>
-__global__ __launch_bounds__(kThreads) void k_rank_update(const RankDesc *__restrict__ descs, int np, int nblk) {
-    __shared__ __attribute__((aligned(16))) double lds[KP * Phase3Cfg<double, KP>::LDV];
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int d = b / nblk, r0 = (b % nblk) * kRowBlock;
-    const RankDesc rd = descs[d];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double wa[KP / 4];
-    const double *wr = rd.w + (size_t)(r0 + 16 * wave + (lane & 15)) * KP + (lane >> 4);
-#pragma unroll
-    for (int s = 0; s < KP / 4; ++s) wa[s] = -wr[4 * s];
-    rowblock_plus_wv<double, KP>(rd.m + (size_t)r0 * np, np, np, rd.q, np, wa, lds);
-}
-
-hipError_t launch_rank_update(const RankDesc *descs_dev, int ndesc, int np, int kslots, hipStream_t s) {
-    const int nblk = np / kRowBlock;
-    const dim3 grid(ndesc * nblk);
-    if (kslots == 16) hipLaunchKernelGGL((k_rank_update<16>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk);
-    else if (kslots == 32) hipLaunchKernelGGL((k_rank_update<32>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk);
-    else if (kslots == 64) hipLaunchKernelGGL((k_rank_update<64>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Blocked Gauss-Jordan inversion (FP64, in place, partial pivoting).
 // For a panel of columns R = [k0, k1): factor the panel with the unblocked
 // in-place Gauss-Jordan step (pivot = largest |entry| among rows >= k, lowest
@@ -272,29 +245,120 @@ __global__ __launch_bounds__(kThreads) void k_gj_panel(const GjDesc *__restrict_
     }
 }
 
-// Apply the panel's row swaps to the non-panel columns, gather the pivot rows
-// into Q (zero in the panel columns), and store the factored panel into M.
-__global__ __launch_bounds__(kThreads) void k_gj_swap(const GjDesc *__restrict__ descs, int np, int nb, int k0,
-                                                      int k1) {
-    const GjDesc g = descs[blockIdx.y];
+// The panel's row interchanges, composed: rowsrc[i] = the row of M whose
+// contents row i holds after the swaps k <-> piv[k], k = k0 .. k1-1, in order
+// (one workgroup per determinant; rows outside the panel's reach stay i).
+// The map is built in LDS (np ints, dynamic shared memory) when it fits,
+// else in place in global memory.
+__global__ __launch_bounds__(kThreads) void k_gj_rowsrc(const GjDesc *__restrict__ descs, int np, int k0, int k1,
+                                                        int in_lds) {
+    extern __shared__ int s_rs[];
+    __shared__ int s_piv[64];
+    const GjDesc g = descs[blockIdx.x];
     const int w = k1 - k0;
-    const int c = blockIdx.x * kThreads + threadIdx.x;
-    if (c >= np) return;
-    if (c >= k0 && c < k1) {
-        for (int kk = 0; kk < nb; ++kk) g.q[(size_t)kk * np + c] = 0.0;
-        const double *col = g.panel + (size_t)(c - k0) * np;
-        for (int i = 0; i < np; ++i) g.m[(size_t)i * np + c] = col[i];
-        return;
-    }
-    for (int k = k0; k < k1; ++k) {
-        const int p = g.piv[k];
-        if (p != k) {
-            const double t = g.m[(size_t)k * np + c];
-            g.m[(size_t)k * np + c] = g.m[(size_t)p * np + c];
-            g.m[(size_t)p * np + c] = t;
+    int *rs = in_lds ? s_rs : g.rowsrc;
+    if (threadIdx.x < w) s_piv[threadIdx.x] = g.piv[k0 + threadIdx.x];
+    for (int i = threadIdx.x; i < np; i += kThreads) rs[i] = i;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int kk = 0; kk < w; ++kk) {
+            const int k = k0 + kk, p = s_piv[kk];
+            if (p != k) {
+                const int t = rs[k];
+                rs[k] = rs[p];
+                rs[p] = t;
+            }
         }
     }
-    for (int kk = 0; kk < nb; ++kk) g.q[(size_t)kk * np + c] = kk < w ? g.m[(size_t)(k0 + kk) * np + c] : 0.0;
+    __syncthreads();
+    if (in_lds)
+        for (int i = threadIdx.x; i < np; i += kThreads) g.rowsrc[i] = s_rs[i];
+}
+
+// Q[j][c] = (swapped M)[k0 + j][c] = M[rowsrc[k0 + j]][c] for the non-panel
+// columns, 0 in the panel's columns and for j >= w (nb rows).
+__global__ __launch_bounds__(kThreads) void k_gj_qgather(const GjDesc *__restrict__ descs, int np, int nb, int k0,
+                                                         int w) {
+    const GjDesc g = descs[blockIdx.y];
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= np) return;
+    const bool panel = c >= k0 && c < k0 + w;
+    for (int j = 0; j < nb; ++j)
+        g.q[(size_t)j * np + c] = (j < w && !panel) ? g.m[(size_t)g.rowsrc[k0 + j] * np + c] : 0.0;
+}
+
+// Trailing update with the row interchanges folded in, into the other buffer:
+//     m2[i][c] = m[rowsrc[i]][c] - sum_j W[i][j] Q[j][c]     (c outside the panel)
+//     m2[i][c] = T[i][c - k0]                                 (the panel's columns)
+// One workgroup per 64 rows (wave w: rows 16w..16w+15, KP/4 W fragments in
+// registers), Q staged in LDS by 64-column chunks, the next chunk's source
+// rows loaded before the current chunk's products.  FP64 16x16x4 matrix cores.
+template <int KP>
+__global__ __launch_bounds__(kThreads) void k_gj_update(const GjDesc *__restrict__ descs, int np, int nblk, int k0,
+                                                        int w) {
+    constexpr int CW = 64, LDQ = CW + 8;  // +64 B row pad
+    __shared__ __attribute__((aligned(16))) double q_lds[KP * LDQ];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int d = b / nblk, r0 = (b % nblk) * kRowBlock;
+    const GjDesc g = descs[d];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
+    DSU_GLOBAL const double *msrc = gmem(g.m);
+    DSU_GLOBAL double *mdst = gmem(g.m2);
+    DSU_GLOBAL const double *qg = gmem(g.q);
+    double wa[KP / 4];
+    {
+        DSU_GLOBAL const double *wr = gmem(g.w) + (size_t)(r0 + 16 * wave + lr) * KP + lk;
+#pragma unroll
+        for (int s = 0; s < KP / 4; ++s) wa[s] = -wr[4 * s];
+    }
+    // result rows of this lane (FP64 tile layout: row (lane / 16) + 4 i)
+    int row[4];
+    DSU_GLOBAL const double *src[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        row[i] = r0 + 16 * wave + Mma<double>::row0(lane) + i * Mma<double>::row_step;
+        src[i] = msrc + (size_t)g.rowsrc[row[i]] * np + lr;
+    }
+    double pre[CW / 16][4];
+#pragma unroll
+    for (int t = 0; t < CW / 16; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pre[t][i] = src[i][16 * t];
+    for (int c0 = 0; c0 < np; c0 += CW) {
+        for (int v = tid; v < KP * (CW / 2); v += kThreads) {
+            const int r = v / (CW / 2), cc = (v % (CW / 2)) * 2;
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            *reinterpret_cast<d2 *>(q_lds + r * LDQ + cc) =
+                *reinterpret_cast<DSU_GLOBAL const d2 *>(qg + (size_t)r * np + c0 + cc);
+        }
+        Mma<double>::acc_t acc[CW / 16];
+#pragma unroll
+        for (int t = 0; t < CW / 16; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[t][i] = pre[t][i];
+        if (c0 + CW < np) {
+#pragma unroll
+            for (int t = 0; t < CW / 16; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pre[t][i] = src[i][c0 + CW + 16 * t];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < KP / 4; ++s) {
+            const double *bp = q_lds + (4 * s + lk) * LDQ + lr;
+#pragma unroll
+            for (int t = 0; t < CW / 16; ++t) acc[t] = Mma<double>::mma(wa[s], bp[16 * t], acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < CW / 16; ++t) {
+            const int c = c0 + 16 * t + lr;
+            const bool panel = c >= k0 && c < k0 + w;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                mdst[(size_t)row[i] * np + c] = panel ? g.panel[(size_t)(c - k0) * np + row[i]] : acc[t][i];
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -329,13 +393,23 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_sub(const GjDesc *__restrict_
     __shared__ double S[WS * NPMAX];  // the group's columns, S[j * np + i]
     __shared__ double s_v[kGjThreads / 64];
     __shared__ int s_i[kGjThreads / 64];
-    __shared__ double s_row[WS];
-    __shared__ int s_p;
     const GjDesc g = descs[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double *P = g.panel + (size_t)j0 * np;
     for (int v = tid; v < ws * np; v += kGjThreads) S[v] = P[v];
-    if (k0 == 0 && j0 == 0 && tid == 0) { *g.logdet = 0.0; *g.sign = 1; *g.status = 0; *g.pmax = 0.0; }
+    // running log|det|, sign and status: thread 0's registers for the whole
+    // group, read once and written once; the largest pivot so far (the
+    // singularity threshold): every thread's register
+    double logdet = 0.0, pmax = 0.0;
+    int sign = 1, status = 0;
+    if (!(k0 == 0 && j0 == 0)) {
+        pmax = *g.pmax;
+        if (tid == 0) {
+            logdet = *g.logdet;
+            sign = *g.sign;
+            status = *g.status;
+        }
+    }
     __syncthreads();
     for (int kk = 0; kk < ws; ++kk) {
         const int k = k0 + j0 + kk;
@@ -350,44 +424,61 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_sub(const GjDesc *__restrict_
         }
         if (lane == 0) { s_v[wave] = best; s_i[wave] = bi; }
         __syncthreads();
-        if (tid == 0) {
-            double bv = s_v[0];
-            int bidx = s_i[0];
-            for (int q = 1; q < kGjThreads / 64; ++q) argmax_combine(bv, bidx, s_v[q], s_i[q]);
-            const double pm = fmax(*g.pmax, bv);
-            *g.pmax = pm;
-            if (!(bv > (double)n * 2.220446049250313e-16 * pm)) { *g.status = -3; bidx = k; }
-            s_p = bidx;
-            g.piv[k] = bidx;
+        // every thread combines the waves' candidates (same order, same result)
+        double bv = s_v[0];
+        int p = s_i[0];
+#pragma unroll
+        for (int q = 1; q < kGjThreads / 64; ++q) argmax_combine(bv, p, s_v[q], s_i[q]);
+        pmax = fmax(pmax, bv);
+        // singular when the best pivot is at rounding level of the largest one:
+        // flagged, and no interchange
+        if (!(bv > (double)n * 2.220446049250313e-16 * pmax)) {
+            status = -3;
+            p = k;
         }
-        __syncthreads();
-        const int p = s_p;
-        if (p != k && tid < ws) {
-            const double t = S[tid * np + k];
-            S[tid * np + k] = S[tid * np + p];
-            S[tid * np + p] = t;
-        }
-        __syncthreads();
-        const double d = S[kk * np + k];
-        if (tid == 0) {
-            if (d != 0.0) *g.logdet += log(fabs(d));
-            int sg = *g.sign;
-            if (p != k) sg = -sg;
-            if (d < 0.0) sg = -sg;
-            *g.sign = sg;
-        }
+        // the pivot row (old row p) in registers before anything is written
+        const double d = S[kk * np + p];
         const double dinv = d != 0.0 ? 1.0 / d : 0.0;
-        if (tid < ws) s_row[tid] = tid == kk ? dinv : S[tid * np + k] * dinv;
+        double rp[WS];
+#pragma unroll
+        for (int j = 0; j < WS; ++j) rp[j] = j < ws ? (j == kk ? dinv : S[j * np + p] * dinv) : 0.0;
+        if (tid == 0) {
+            g.piv[k] = p;
+            if (d != 0.0) logdet += log(fabs(d));
+            if (p != k) sign = -sign;
+            if (d < 0.0) sign = -sign;
+        }
         __syncthreads();
+        // rows after the interchange: row k = the scaled pivot row, row p =
+        // old row k eliminated, every other row eliminated in place; the owner
+        // of row k writes rows k and p
         for (int i = tid; i < np; i += kGjThreads) {
+            if (i == p && p != k) continue;
             if (i == k) {
-                for (int j = 0; j < ws; ++j) S[j * np + i] = s_row[j];
+                const double f = S[kk * np + k];
+#pragma unroll
+                for (int j = 0; j < WS; ++j) {
+                    if (j >= ws) continue;
+                    const double ok = S[j * np + k];
+                    S[j * np + k] = rp[j];
+                    if (p != k) S[j * np + p] = j == kk ? -f * dinv : ok - f * rp[j];
+                }
                 continue;
             }
             const double f = S[kk * np + i];
-            for (int j = 0; j < ws; ++j) S[j * np + i] = j == kk ? -f * dinv : S[j * np + i] - f * s_row[j];
+#pragma unroll
+            for (int j = 0; j < WS; ++j) {
+                if (j >= ws) continue;
+                S[j * np + i] = j == kk ? -f * dinv : S[j * np + i] - f * rp[j];
+            }
         }
         __syncthreads();
+    }
+    if (tid == 0) {
+        *g.logdet = logdet;
+        *g.pmax = pmax;
+        *g.sign = sign;
+        *g.status = status;
     }
     // the factored columns, and the group's update (E - S) column-major in w
     for (int v = tid; v < ws * np; v += kGjThreads) {
@@ -466,24 +557,36 @@ __global__ void k_gj_perm(const GjDesc *__restrict__ descs, int n, int np) {
     }
 }
 
-hipError_t launch_gj_invert(const GjDesc *descs_dev, const RankDesc *rank_dev, int ndesc, int n, int np, int nb,
-                            hipStream_t s) {
+hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc, int n, int np, int nb,
+                            hipStream_t s, const GjDesc **final_set) {
     if (nb != 16 && nb != 32 && nb != 64) return hipErrorInvalidValue;
+    const GjDesc *cur = set_a, *nxt = set_b;
+    const int nblk = np / kRowBlock;
     for (int k0 = 0; k0 < n; k0 += nb) {
         const int k1 = k0 + nb < n ? k0 + nb : n;
-        // group width: the group's np x WS columns fill at most 128 KB of LDS
-        if (np <= 512) launch_gj_panel2<16, 512>(descs_dev, ndesc, n, np, nb, k0, k1 - k0, s);
-        else if (np <= 1024) launch_gj_panel2<16, 1024>(descs_dev, ndesc, n, np, nb, k0, k1 - k0, s);
-        else if (np <= 2048) launch_gj_panel2<8, 2048>(descs_dev, ndesc, n, np, nb, k0, k1 - k0, s);
-        else if (np <= 4096) launch_gj_panel2<4, 4096>(descs_dev, ndesc, n, np, nb, k0, k1 - k0, s);
-        else if (np <= 8192) launch_gj_panel2<2, 8192>(descs_dev, ndesc, n, np, nb, k0, k1 - k0, s);
-        else hipLaunchKernelGGL(k_gj_panel, dim3(ndesc), dim3(kThreads), 0, s, descs_dev, n, np, nb, k0, k1);
-        hipLaunchKernelGGL(k_gj_swap, dim3((np + kThreads - 1) / kThreads, ndesc), dim3(kThreads), 0, s, descs_dev, np,
-                           nb, k0, k1);
-        hipError_t e = launch_rank_update(rank_dev, ndesc, np, nb, s);
-        if (e != hipSuccess) return e;
+        // factor the panel: group width such that the group's np x WS columns fill at most 128 KB of LDS
+        if (np <= 512) launch_gj_panel2<16, 512>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
+        else if (np <= 1024) launch_gj_panel2<16, 1024>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
+        else if (np <= 2048) launch_gj_panel2<8, 2048>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
+        else if (np <= 4096) launch_gj_panel2<4, 4096>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
+        else if (np <= 8192) launch_gj_panel2<2, 8192>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
+        else hipLaunchKernelGGL(k_gj_panel, dim3(ndesc), dim3(kThreads), 0, s, cur, n, np, nb, k0, k1);
+        // row interchanges, pivot rows, then the trailing update into the other buffer
+        const int in_lds = np <= 8192;  // 32 KB of dynamic LDS at most
+        hipLaunchKernelGGL(k_gj_rowsrc, dim3(ndesc), dim3(kThreads), in_lds ? np * sizeof(int) : 0, s, cur, np, k0,
+                           k1, in_lds);
+        hipLaunchKernelGGL(k_gj_qgather, dim3((np + kThreads - 1) / kThreads, ndesc), dim3(kThreads), 0, s, cur, np,
+                           nb, k0, k1 - k0);
+        const dim3 grid(ndesc * nblk);
+        if (nb == 16) hipLaunchKernelGGL((k_gj_update<16>), grid, dim3(kThreads), 0, s, cur, np, nblk, k0, k1 - k0);
+        else if (nb == 32) hipLaunchKernelGGL((k_gj_update<32>), grid, dim3(kThreads), 0, s, cur, np, nblk, k0, k1 - k0);
+        else hipLaunchKernelGGL((k_gj_update<64>), grid, dim3(kThreads), 0, s, cur, np, nblk, k0, k1 - k0);
+        const GjDesc *t = cur;
+        cur = nxt;
+        nxt = t;
     }
-    hipLaunchKernelGGL(k_gj_perm, dim3(ndesc), dim3(64), 0, s, descs_dev, n, np);
+    hipLaunchKernelGGL(k_gj_perm, dim3(ndesc), dim3(64), 0, s, cur, n, np);
+    if (final_set) *final_set = cur;
     return hipGetLastError();
 }
 
