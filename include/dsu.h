@@ -368,18 +368,6 @@ int dsu_batch_use_graph(dsu_batch *b, int32_t enable);
  * with; Sec. II: K is the tunable of the method).  Takes effect at the next
  * sweep. */
 int dsu_batch_set_delay(dsu_batch *b, int32_t k_delay);
-/* Window schedule.  path = 1 (default): three launches per window
- * (proposals, one-pass flush that also forms the next window's look-ahead
- * products while each chunk of the inverse is on chip, decisions).
- * path = 0: four launches (proposals, look-ahead products, decisions,
- * flush that reads the inverse twice).  path = 2 (DSU_FP32_MIXED batches;
- * FP64 batches run path 1): as path 1 with both products of the flush on the
- * bf16 matrix cores at FP32 accuracy (each FP32 operand split into three
- * bf16 parts, six cross products kept; error within that of FP32 products)
- * for padded delays 32, 64 and 128, other delays as path 1.  All paths
- * compute the same ratios to the precision's rounding.  DSU_EINVAL for a
- * path outside 0..2. */
-int dsu_batch_set_flush_path(dsu_batch *b, int32_t path);
 
 /* ======================================================================
  * Serving: a pool of walkers of mixed n admitted by a device-memory budget,

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdsu.so")
 
-SOURCES = ["k_linalg.hip", "k_walker.hip", "k_batch.hip", "k_stream.hip", "k_stream_x6.hip", "host_common.hip", "dsu_api.hip", "zwalker.hip", "bucket.hip",
+SOURCES = ["k_linalg.hip", "k_walker.hip", "k_batch.hip", "k_stream.hip", "host_common.hip", "dsu_api.hip", "zwalker.hip", "bucket.hip",
            "dsu_server.hip"]
 
 FLAGS = [

@@ -1,14 +1,17 @@
 // bucket.hip -- the lock-step engine of the batched form, and the dsu_batch
 // entry points built on it.
 //
-// Per sweep and window of K proposals (electrons e0..e0+kw-1), four launches
-// over every member determinant:
-//   rows   : draw the kw moves, evaluate the proposed orbital rows U and copy
-//            the stale inverse rows Vg                       (k_window_rows)
-//   G      : look-ahead products G = U BT[e0..]^T on matrix cores (k_window_g)
+// A sweep of every member determinant is a chain of windows of K proposals
+// (electrons e0..e0+kw-1), three launches per window:
+//   props  : draw the next window's kw moves and evaluate their proposed
+//            orbital rows U (k_window_rows, beside the decisions on a second
+//            stream)
 //   decide : sequential Metropolis decisions with the bordered inverse of
-//            eq. (3)'s C matrix                               (k_window_decide)
-//   flush  : en-bloc Woodbury update of BT, eq. (4)          (k_flush_mfma)
+//            eq. (3)'s C matrix (k_window_decide_gj / k_window_decide), the
+//            look-ahead products G taken from the previous pass over BT
+//   flush  : one pass over BT: the en-bloc Woodbury update of eq. (4), and,
+//            while each chunk of the new BT is on chip, the next window's
+//            look-ahead products (k_flush_stream32 / k_flush_stream)
 #include "bucket.hpp"
 
 #include <algorithm>
@@ -21,18 +24,6 @@ namespace dsu {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Column splits of the window look-ahead product: one 512-byte column range
-// per workgroup when np allows it (np is a multiple of 64 elements; 512 bytes
-// are 128 FP32 or 64 FP64 elements), else ranges of a multiple of 64 elements.
-static int choose_nsplit(int np, int prec) {
-    const int w = prec == DSU_FP64 ? 64 : 128;
-    if (np % w == 0) return np / w;
-    int s = np / 512;
-    if (s < 1) s = 1;
-    while (s > 1 && (np % s != 0 || (np / s) % 64 != 0)) --s;
-    return s;
-}
-
 BucketShape BucketShape::make(int n, int kmax, int prec) {
     BucketShape s;
     s.n = n;
@@ -40,29 +31,27 @@ BucketShape BucketShape::make(int n, int kmax, int prec) {
     s.kmax = kmax;
     s.kp = kpad(kmax);
     s.prec = prec;
-    s.nsplit = choose_nsplit(s.np, prec);
     return s;
 }
 
 // Piece sizes in carve order.
-static constexpr int kPieces = 15;
+static constexpr int kPieces = 14;
 static void pieces(const BucketShape &s, size_t out[kPieces]) {
     const size_t e = elem_size(s.prec), np = s.np, kp = s.kp;
     out[0] = np * np * e;                           // bt
     out[1] = kp * np * e;                           // u
     out[2] = kp * np * e;                           // vg
-    out[3] = (size_t)s.nsplit * kp * kp * e;        // gpart
-    out[4] = kp * kp * 8;                           // cfl
-    out[5] = kp > 128 ? kp * (kp + 1) * 8 : 0;      // cwork
-    out[6] = kp > 64 ? kp * (kp + 1) * 8 : 0;       // gwork
-    out[7] = kp * 4 * 8;                            // prop
-    out[8] = (size_t)s.n * 3 * 8;                   // pos
-    out[9] = kp * 4;                                // idx
-    out[10] = sizeof(DetState);                     // st
-    out[11] = kp * np * e;                          // u2
-    out[12] = kp * np * e;                          // vg2
-    out[13] = np * kp * e;                          // y
-    out[14] = kp * 4 * 8;                           // prop2
+    out[3] = kp * kp * 8;                           // cfl
+    out[4] = kp > 128 ? kp * (kp + 1) * 8 : 0;      // cwork
+    out[5] = kp > 64 ? kp * (kp + 1) * 8 : 0;       // gwork
+    out[6] = kp * 4 * 8;                            // prop
+    out[7] = (size_t)s.n * 3 * 8;                   // pos
+    out[8] = kp * 4;                                // idx
+    out[9] = sizeof(DetState);                      // st
+    out[10] = kp * np * e;                          // u2
+    out[11] = kp * np * e;                          // vg2
+    out[12] = np * kp * e;                          // y
+    out[13] = kp * 4 * 8;                           // prop2
 }
 
 size_t BucketShape::det_bytes() const {
@@ -85,18 +74,17 @@ DetSlot BucketShape::carve(char *base) const {
     d.bt = ptr[0];
     d.u = ptr[1];
     d.vg = ptr[2];
-    d.gpart = ptr[3];
-    d.cfl = (double *)ptr[4];
-    d.cwork = (double *)ptr[5];
-    d.gwork = (double *)ptr[6];
-    d.prop = (double *)ptr[7];
-    d.pos = (double *)ptr[8];
-    d.idx = (int *)ptr[9];
-    d.st = (DetState *)ptr[10];
-    d.u2 = ptr[11];
-    d.vg2 = ptr[12];
-    d.y = ptr[13];
-    d.prop2 = (double *)ptr[14];
+    d.cfl = (double *)ptr[3];
+    d.cwork = (double *)ptr[4];
+    d.gwork = (double *)ptr[5];
+    d.prop = (double *)ptr[6];
+    d.pos = (double *)ptr[7];
+    d.idx = (int *)ptr[8];
+    d.st = (DetState *)ptr[9];
+    d.u2 = ptr[10];
+    d.vg2 = ptr[11];
+    d.y = ptr[12];
+    d.prop2 = (double *)ptr[13];
     return d;
 }
 
@@ -196,7 +184,6 @@ template <typename T> static DetDesc<T> to_desc(const DetSlot &s) {
     d.bt = (T *)s.bt;
     d.u = (T *)s.u;
     d.vg = (T *)s.vg;
-    d.gpart = (T *)s.gpart;
     d.cfl = s.cfl;
     d.cwork = s.cwork;
     d.gwork = s.gwork;
@@ -303,26 +290,6 @@ int Bucket::harvest_events() {
     return DSU_OK;
 }
 
-template <typename T> int Bucket::enqueue_sweep_t(int force) {
-    const DetDesc<T> *dd = (const DetDesc<T> *)ddesc_;
-    const FlushDesc<T> *fd = (const FlushDesc<T> *)fdesc_;
-    const int nd = (int)dets.size();
-    const int kt = kpad(K);
-    for (int e0 = 0; e0 < sh.n; e0 += K) {
-        const int kw = std::min(K, sh.n - e0);
-        const int last = e0 + kw == sh.n;
-        CHK(timed(PH_ROWS, [&] {
-            return launch_window_rows<T>(dd, nd, sh.n, sh.np, kt, e0, kw, kvec, twopi_l, kmax_comp, stream);
-        }));
-        CHK(timed(PH_G, [&] { return launch_window_g<T>(dd, nd, sh.np, kt, sh.kp, e0, sh.nsplit, stream); }));
-        CHK(timed(PH_DECIDE, [&] {
-            return launch_window_decide<T>(dd, nd, kt, sh.kp, e0, kw, sh.nsplit, force, last, stream);
-        }));
-        CHK(timed(PH_FLUSH, [&] { return launch_flush<T>(fd, nd, sh.n, sh.np, kw, 0, stream); }));
-    }
-    return DSU_OK;
-}
-
 // Streaming sweep: prime (proposals of window 0, y = BT U^T for all rows,
 // decisions of window 0), then per window w: proposals of w+1, one-pass flush
 // of w producing y for w+1, decisions of w+1.
@@ -356,13 +323,10 @@ template <typename T> int Bucket::enqueue_sweep_stream_t(int force) {
             HIPCHK(hipEventRecord(join, side));
         }
         CHK(timed(PH_DECIDE, [&] {
-            return launch_window_decide<T>(dd, nd, kt, sh.kp, e0, kw_of(w), 1, force, w + 1 == nwin, stream, 1, cur);
+            return launch_window_decide<T>(dd, nd, kt, sh.kp, e0, kw_of(w), force, w + 1 == nwin, cur, stream);
         }));
         if (has_next) HIPCHK(hipStreamWaitEvent(stream, join, 0));
         CHK(timed(PH_FLUSH, [&] {
-            if (sizeof(T) == 4 && flush_path == 2 && (kt == 32 || kt == 64 || kt == 128))
-                return launch_flush_stream_x6((const DetDesc<float> *)dd, nd, sh.np, kt, sh.kp, kw_of(w), cur,
-                                              has_next ? 1 : 0, e0n, kwn, stream);
             return launch_flush_stream<T>(dd, nd, sh.np, kt, sh.kp, kw_of(w), cur, has_next ? 1 : 0, e0n, kwn, stream);
         }));
     }
@@ -370,9 +334,7 @@ template <typename T> int Bucket::enqueue_sweep_stream_t(int force) {
 }
 
 int Bucket::enqueue_sweep(int force) {
-    if (flush_path != 0)
-        return sh.prec == DSU_FP64 ? enqueue_sweep_stream_t<double>(force) : enqueue_sweep_stream_t<float>(force);
-    return sh.prec == DSU_FP64 ? enqueue_sweep_t<double>(force) : enqueue_sweep_t<float>(force);
+    return sh.prec == DSU_FP64 ? enqueue_sweep_stream_t<double>(force) : enqueue_sweep_stream_t<float>(force);
 }
 
 int Bucket::build_graph(int force) {
@@ -1035,10 +997,3 @@ extern "C" int dsu_batch_use_graph(dsu_batch *b, int32_t enable) {
     return DSU_OK;
 }
 
-extern "C" int dsu_batch_set_flush_path(dsu_batch *b, int32_t path) {
-    if (!b) return fail(DSU_EINVAL, "batch is NULL");
-    if (path < 0 || path > 2) return fail(DSU_EINVAL, "bad flush path %d", path);
-    HIPCHK(hipStreamSynchronize(b->bk.stream));
-    b->bk.flush_path = path;
-    return b->bk.set_dets(b->bk.dets);  // drops any captured graph
-}

@@ -14,7 +14,7 @@ namespace dsu {
 
 // Device storage of one determinant.
 struct DetSlot {
-    void *bt = nullptr, *u = nullptr, *vg = nullptr, *gpart = nullptr, *u2 = nullptr, *vg2 = nullptr, *y = nullptr;
+    void *bt = nullptr, *u = nullptr, *vg = nullptr, *u2 = nullptr, *vg2 = nullptr, *y = nullptr;
     double *cfl = nullptr, *cwork = nullptr, *gwork = nullptr, *prop = nullptr, *pos = nullptr, *prop2 = nullptr;
     int *idx = nullptr;
     DetState *st = nullptr;
@@ -28,7 +28,7 @@ struct DetSlot {
 
 // Sizes shared by every determinant of a bucket.
 struct BucketShape {
-    int n = 0, np = 0, kmax = 0, kp = 0, prec = 0, nsplit = 1;
+    int n = 0, np = 0, kmax = 0, kp = 0, prec = 0;
     static BucketShape make(int n, int kmax, int prec);
     size_t det_bytes() const;            // one determinant's storage, 256-byte aligned pieces
     DetSlot carve(char *base) const;     // split a det_bytes() block into its arrays
@@ -49,10 +49,6 @@ class Bucket {
     std::vector<DetSlot> dets;
     bool use_graph = false;
     int timing = 0;  // 0 off, 1 events around every launch, 2 around flush launches only
-    // 0: four launches per window; 1: one-pass flush with the next window's
-    // products, FP32 matrix-core products; 2: the same pass with split-bf16
-    // products (FP32 determinants only; FP64 buckets take 1)
-    int flush_path = 1;
 
     int init(const BucketShape &shape, int k_delay, double box_l, void *stream_or_null, int gj_group);
     void release();
@@ -117,7 +113,6 @@ class Bucket {
     hipEvent_t ev_ring_[8] = {};
     template <typename F> int timed(int phase, F fn, hipStream_t on = nullptr);
     template <typename T> int upload_t();
-    template <typename T> int enqueue_sweep_t(int force_accept);
     template <typename T> int enqueue_sweep_stream_t(int force_accept);
     template <typename T> int recompute_async_t(const std::vector<int> &which);
 };

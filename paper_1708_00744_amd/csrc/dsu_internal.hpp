@@ -75,7 +75,6 @@ template <typename T> struct DetDesc {
     T *bt;           // np x np
     T *u;            // kp x np
     T *vg;           // kp x np
-    T *gpart;        // nsplit x kp x kp (G^T partial sums: gpart[b][a] = BT[e0+b,:].U[a,:])
     double *cfl;     // kp x kp
     double *cwork;   // kp x (kp+1) when the bordered inverse does not fit LDS
     double *gwork;   // kp x (kp+1) when G does not fit LDS
@@ -153,15 +152,11 @@ hipError_t launch_untranspose(const T *bt, double *out, int n, int np, hipStream
 // Batched window kernels.  ktile = padded delay of the launch (template tile
 // count, 16..256), kp = padded delay the buffers were allocated for (stride),
 // nmax = largest |component| of the plane-wave integer vectors.
+// Decisions of one window: the look-ahead products G come from y (formed by
+// the previous pass over BT), proposals from prop (pbuf 0) or prop2 (1).
 template <typename T>
-hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
-                              const int4 *kvec, double twopi_over_l, int nmax, hipStream_t s);
-template <typename T>
-hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int e0, int nsplit,
-                           hipStream_t s);
-template <typename T>
-hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int nsplit,
-                                int force_accept, int last_window, hipStream_t s, int g_from_y = 0, int pbuf = 0);
+hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int force_accept,
+                                int last_window, int pbuf, hipStream_t s);
 
 // Streaming path (one pass over BT per window):
 //   props : proposals and orbital rows of a window into U buffer `buf`
@@ -178,11 +173,6 @@ hipError_t launch_window_prime(const DetDesc<T> *d, int ndesc, int np, int ktile
 template <typename T>
 hipError_t launch_flush_stream(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int kslots, int cur,
                                int has_next, int e0n, int kwn, hipStream_t s);
-// The same pass for FP32 determinants with both products on the bf16 matrix
-// cores at FP32 accuracy (operands split into three bf16 parts); ktile 32, 64
-// or 128.
-hipError_t launch_flush_stream_x6(const DetDesc<float> *d, int ndesc, int np, int ktile, int kp, int kslots, int cur,
-                                  int has_next, int e0n, int kwn, hipStream_t s);
 template <typename T>
 hipError_t launch_reset_state(const DetDesc<T> *d, const GjDesc *gj, double *drift, int ndesc, hipStream_t s);
 

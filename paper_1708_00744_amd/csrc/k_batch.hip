@@ -171,17 +171,6 @@ __global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__re
 }
 
 template <typename T>
-hipError_t launch_window_rows(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
-                              const int4 *kvec, double twopi_over_l, int nmax, hipStream_t s) {
-    int nsplit = np / 256;
-    if (nsplit < 1) nsplit = 1;
-    while (np % nsplit) --nsplit;
-    hipLaunchKernelGGL((k_window_rows<T>), dim3(ndesc, nsplit), dim3(kThreads), 0, s, d, n, np, ktile, e0, kw, kvec,
-                       twopi_over_l, 0, 1, nmax);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_window_props(const DetDesc<T> *d, int ndesc, int n, int np, int ktile, int e0, int kw,
                                const int4 *kvec, double twopi_over_l, int buf, int copy_vg, int nmax, hipStream_t s) {
     int nsplit = np / 256;
@@ -195,133 +184,6 @@ template hipError_t launch_window_props<float>(const DetDesc<float> *, int, int,
                                                double, int, int, int, hipStream_t);
 template hipError_t launch_window_props<double>(const DetDesc<double> *, int, int, int, int, int, int, const int4 *,
                                                 double, int, int, int, hipStream_t);
-template hipError_t launch_window_rows<float>(const DetDesc<float> *, int, int, int, int, int, int, const int4 *,
-                                              double, int, hipStream_t);
-template hipError_t launch_window_rows<double>(const DetDesc<double> *, int, int, int, int, int, int, const int4 *,
-                                               double, int, hipStream_t);
-
-// ---------------------------------------------- window look-ahead products
-// gpart[s][b][a] = sum over the s-th column range of BT[e0+b, c] * U[a, c]
-// (a, b < KP; row stride kp of the allocation).
-// grid: ndesc * nsplit * nrb, nrb = 64-row blocks covering KP rows.  Same
-// matrix-core tiling as the flush's first product (64 rows x KP columns).
-template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_window_g(const DetDesc<T> *__restrict__ descs, int np, int kp, int e0,
-                                                       int nsplit, int nrb) {
-    constexpr int LDU = 128 / (int)sizeof(T) + 16 / (int)sizeof(T);
-    __shared__ __attribute__((aligned(16))) T lds[KP * LDU];
-    const int b = blockIdx.x;
-    const int d = b / (nsplit * nrb), rem = b % (nsplit * nrb);
-    const int s = rem / nrb, rb = rem % nrb;
-    const DetDesc<T> dd = descs[d];
-    const int cols = np / nsplit;
-    const int row0 = e0 + rb * 64;
-    int rows_valid = np - row0;
-    rows_valid = rows_valid < 0 ? 0 : (rows_valid > 64 ? 64 : rows_valid);
-    typename Mma<T>::acc_t acc[KP / 16];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    rowblock_times_ut<T, KP>(dd.bt + (size_t)row0 * np, np, rows_valid, dd.u, np, s * cols, (s + 1) * cols, lds,
-                             acc);
-    T *out = dd.gpart + (size_t)s * kp * kp;
-#pragma unroll
-    for (int t = 0; t < KP / 16; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int br = rb * 64 + 16 * wave + Mma<T>::row0(lane) + i * Mma<T>::row_step;
-            const int ac = 16 * t + (lane & 15);
-            if (br < KP) out[(size_t)br * kp + ac] = acc[t][i];
-        }
-}
-
-// The same for K <= 64, one launch-wide burst: each workgroup takes one
-// 512-byte column range of the window's 64 stale rows and of the K orbital
-// rows and issues all of its loads at once (the product is small, so the
-// launch is bound by how many bytes are in flight).  Lane group g = lane/16
-// contracts over its own contiguous quarter of the range.
-template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_window_g_wide(const DetDesc<T> *__restrict__ descs, int np, int kp,
-                                                            int e0, int nsplit, int nrb) {
-    constexpr int CWB = 512 / (int)sizeof(T), VEC = 16 / (int)sizeof(T), LDU = CWB + VEC, Q = CWB / 4;
-    constexpr int NU = KP * (CWB / VEC) / kThreads;
-    static_assert(NU >= 1 && NU * kThreads == KP * (CWB / VEC), "staging split");
-    typedef typename Vec16<T>::type vec_t;
-    __shared__ __attribute__((aligned(16))) T lds[KP * LDU];
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int d = b / (nsplit * nrb), sp = (b / nrb) % nsplit, rb = b % nrb;
-    const DetDesc<T> dd = descs[d];
-    const int c_begin = sp * CWB;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int arow = 64 * rb + 16 * wave + (lane & 15);  // stale row of the window (G row b)
-    const bool avalid = e0 + arow < np && arow < KP;
-    DSU_GLOBAL const T *ap = gmem<const T>(dd.bt) + (size_t)(avalid ? e0 + arow : 0) * np + c_begin + Q * (lane >> 4);
-    DSU_GLOBAL const T *u = gmem<const T>(dd.u);
-    vec_t a[Q / VEC], st[NU];
-#pragma unroll
-    for (int h = 0; h < Q / VEC; ++h) a[h] = avalid ? *(DSU_GLOBAL const vec_t *)(ap + h * VEC) : vec_t{};
-#pragma unroll
-    for (int q = 0; q < NU; ++q) {
-        const int v = tid + q * kThreads, r = v / (CWB / VEC), cc = (v % (CWB / VEC)) * VEC;
-        st[q] = *(DSU_GLOBAL const vec_t *)(u + (size_t)r * np + c_begin + cc);
-    }
-#pragma unroll
-    for (int q = 0; q < NU; ++q) {
-        const int v = tid + q * kThreads, r = v / (CWB / VEC), cc = (v % (CWB / VEC)) * VEC;
-        *reinterpret_cast<vec_t *>(lds + r * LDU + cc) = st[q];
-    }
-    __syncthreads();
-    typename Mma<T>::acc_t acc[KP / 16];
-#pragma unroll
-    for (int t = 0; t < KP / 16; ++t) acc[t] = typename Mma<T>::acc_t{0, 0, 0, 0};
-#pragma unroll
-    for (int h = 0; h < Q / VEC; ++h)
-#pragma unroll
-        for (int t = 0; t < KP / 16; ++t) {
-            const vec_t bv = *reinterpret_cast<const vec_t *>(lds + (16 * t + (lane & 15)) * LDU + Q * (lane >> 4) +
-                                                              h * VEC);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[t] = Mma<T>::mma(a[h][e], bv[e], acc[t]);
-        }
-    T *out = dd.gpart + (size_t)sp * kp * kp;
-#pragma unroll
-    for (int t = 0; t < KP / 16; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int br = 64 * rb + 16 * wave + Mma<T>::row0(lane) + i * Mma<T>::row_step;
-            if (br < KP) out[(size_t)br * kp + 16 * t + (lane & 15)] = acc[t][i];
-        }
-}
-
-template <typename T>
-hipError_t launch_window_g(const DetDesc<T> *d, int ndesc, int np, int ktile, int kp, int e0, int nsplit,
-                           hipStream_t s) {
-    // (at K = 128 the 64-row blocks would each stage all 128 orbital rows and
-    // halve the occupancy; the chunked kernel below is faster there)
-    if (ktile <= 64 && np == nsplit * (512 / (int)sizeof(T))) {
-        const int nrb = ktile > 64 ? ktile / 64 : 1;
-        const dim3 grid(ndesc * nsplit * nrb);
-        if (ktile == 16)
-            hipLaunchKernelGGL((k_window_g_wide<T, 16>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);
-        else if (ktile == 32)
-            hipLaunchKernelGGL((k_window_g_wide<T, 32>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);
-        else if (ktile == 64)
-            hipLaunchKernelGGL((k_window_g_wide<T, 64>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);
-        else
-            hipLaunchKernelGGL((k_window_g_wide<T, 128>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);
-        return hipGetLastError();
-    }
-    const int nrb = ktile > 64 ? ktile / 64 : 1;
-    const dim3 grid(ndesc * nsplit * nrb);
-#define DSU_G(KPV)                                                                                          \
-    if (ktile == KPV) {                                                                                     \
-        hipLaunchKernelGGL((k_window_g<T, KPV>), grid, dim3(kThreads), 0, s, d, np, kp, e0, nsplit, nrb);    \
-        return hipGetLastError();                                                                           \
-    }
-    DSU_G(16) DSU_G(32) DSU_G(64) DSU_G(128) DSU_G(256)
-#undef DSU_G
-    return hipErrorInvalidValue;
-}
-template hipError_t launch_window_g<float>(const DetDesc<float> *, int, int, int, int, int, int, hipStream_t);
-template hipError_t launch_window_g<double>(const DetDesc<double> *, int, int, int, int, int, int, hipStream_t);
 
 // ------------------------------------------------------ window decisions
 // One workgroup (max(64, KP) threads) per determinant.  Thread i owns row i
@@ -337,9 +199,8 @@ template <int KP> struct DecideCfg {
 
 template <typename T, int KP>
 __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const DetDesc<T> *__restrict__ descs,
-                                                                          int kp, int e0, int kw, int nsplit,
-                                                                          int force_accept, int last_window,
-                                                                          int g_from_y, int pbuf) {
+                                                                          int kp, int e0, int kw, int force_accept,
+                                                                          int last_window, int pbuf) {
     typedef DecideCfg<KP> C;
     constexpr int LD = C::ld, NT = C::threads;
     __shared__ double s_g[C::lds_g];
@@ -353,14 +214,10 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
     double *G = C::g_lds ? s_g : d.gwork;
     double *Cm = C::c_lds ? s_c : d.cwork;
 
-    // G[a][b] = sum_s gpart[s][b][a]  (fixed summation order: deterministic)
+    // G[a][b] = phi_a . BT[e0 + b, :], formed by the previous flush pass
     for (int v = tid; v < kw * kw; v += NT) {
         const int a = v / kw, b = v % kw;
-        double acc = 0.0;
-        if (g_from_y) acc = (double)d.y[(size_t)(e0 + b) * kp + a];
-        else
-            for (int s = 0; s < nsplit; ++s) acc += (double)d.gpart[((size_t)s * kp + b) * kp + a];
-        G[a * LD + b] = acc;
+        G[a * LD + b] = (double)d.y[(size_t)(e0 + b) * kp + a];
     }
     for (int a = tid; a < KP; a += NT) {
         s_u[a] = a < kw ? (pbuf ? d.prop2 : d.prop)[4 * a + 3] : 0.0;
@@ -473,8 +330,7 @@ __device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &
 // one barrier; the pivot column comes from one lane of each wave.
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__restrict__ descs, int kp, int e0,
-                                                          int kw, int nsplit, int force_accept, int last_window,
-                                                          int g_from_y, int pbuf) {
+                                                          int kw, int force_accept, int last_window, int pbuf) {
     constexpr int RW = KP / 4, CPL = KP > 64 ? KP / 64 : 1, NC = 64 * CPL;
     static_assert(KP >= 16 && KP <= 128 && RW % 4 == 0, "window tile");
     __shared__ double s_row[2][2][NC];
@@ -489,13 +345,7 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
         for (int h = 0; h < CPL; ++h) {
             const int a = wave * RW + r, b = lane + 64 * h;
             double v = a == b ? 1.0 : 0.0;
-            if (a < kw && b < kw) {
-                if (g_from_y) v = (double)d.y[(size_t)(e0 + b) * kp + a];
-                else {
-                    v = 0.0;
-                    for (int q = 0; q < nsplit; ++q) v += (double)d.gpart[((size_t)q * kp + b) * kp + a];
-                }
-            }
+            if (a < kw && b < kw) v = (double)d.y[(size_t)(e0 + b) * kp + a];
             g[r][h] = v;
         }
     for (int a = tid; a < KP; a += 256) {
@@ -650,18 +500,18 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
 }
 
 template <typename T>
-hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int nsplit,
-                                int force_accept, int last_window, hipStream_t s, int g_from_y, int pbuf) {
+hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int kp, int e0, int kw, int force_accept,
+                                int last_window, int pbuf, hipStream_t s) {
 #define DSU_G(KPV)                                                                                                \
     if (ktile == KPV) {                                                                                           \
-        hipLaunchKernelGGL((k_window_decide_gj<T, KPV>), dim3(ndesc), dim3(256), 0, s, d, kp, e0, kw, nsplit,     \
-                           force_accept, last_window, g_from_y, pbuf);                                            \
+        hipLaunchKernelGGL((k_window_decide_gj<T, KPV>), dim3(ndesc), dim3(256), 0, s, d, kp, e0, kw,             \
+                           force_accept, last_window, pbuf);                                                      \
         return hipGetLastError();                                                                                 \
     }
 #define DSU_D(KPV)                                                                                                \
     if (ktile == KPV) {                                                                                           \
         hipLaunchKernelGGL((k_window_decide<T, KPV>), dim3(ndesc), dim3(DecideCfg<KPV>::threads), 0, s, d, kp,    \
-                           e0, kw, nsplit, force_accept, last_window, g_from_y, pbuf);                            \
+                           e0, kw, force_accept, last_window, pbuf);                                              \
         return hipGetLastError();                                                                                 \
     }
     DSU_G(16) DSU_G(32) DSU_G(64) DSU_G(128) DSU_D(256)
@@ -670,9 +520,9 @@ hipError_t launch_window_decide(const DetDesc<T> *d, int ndesc, int ktile, int k
     return hipErrorInvalidValue;
 }
 template hipError_t launch_window_decide<float>(const DetDesc<float> *, int, int, int, int, int, int, int, int,
-                                                hipStream_t, int, int);
+                                                hipStream_t);
 template hipError_t launch_window_decide<double>(const DetDesc<double> *, int, int, int, int, int, int, int, int,
-                                                 hipStream_t, int, int);
+                                                 hipStream_t);
 
 // ------------------------------------------------------- streaming path
 // y[i][a] = BT[i,:] . U[buf][a,:] for every row i (the look-ahead products of

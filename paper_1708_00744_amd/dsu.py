@@ -17,7 +17,6 @@ OK, EINVAL, ENOMEM, ESINGULAR, ESTATE, EDEVICE, EBUDGET = 0, -1, -2, -3, -4, -5,
 FP64, FP32_MIXED = 0, 1
 FLUSH_K_ACCEPTED, FLUSH_K_PROPOSED = 0, 1
 FLUSH_AUTO, FLUSH_VALU, FLUSH_MFMA = 0, 1, 2
-PATH_WINDOWS, PATH_STREAM, PATH_STREAM_X6 = 0, 1, 2
 PHASE_ROWS, PHASE_G, PHASE_DECIDE, PHASE_FLUSH, PHASE_RECOMPUTE = 0, 1, 2, 3, 4
 TIMING_ALL, TIMING_FLUSH = 1, 2
 MAX_K = 256
@@ -106,7 +105,6 @@ SIGNATURES = {
     "dsu_batch_kernel_time": (C.c_int, [_vp, _i32, _pi64, _pd]),
     "dsu_batch_use_graph": (C.c_int, [_vp, _i32]),
     "dsu_batch_set_delay": (C.c_int, [_vp, _i32]),
-    "dsu_batch_set_flush_path": (C.c_int, [_vp, _i32]),
     "dsu_server_create": (C.c_int, [_i32, _i32, _dbl, _sz, _i32, _pvp]),
     "dsu_server_destroy": (C.c_int, [_vp]),
     "dsu_server_run": (C.c_int, [_vp, C.POINTER(Request), _i32, C.POINTER(Result), _pd, _i64, _pi64]),
@@ -493,11 +491,6 @@ class Batch:
 
     def use_graph(self, enable):
         _check(lib().dsu_batch_use_graph(self._h, int(bool(enable))))
-
-    def set_flush_path(self, path):
-        """0: four launches per window; 1 (or True): one-pass streaming flush;
-        2: streaming flush with split-bf16 products (FP32 batches)."""
-        _check(lib().dsu_batch_set_flush_path(self._h, int(path)))
 
     def set_delay(self, k_delay):
         _check(lib().dsu_batch_set_delay(self._h, int(k_delay)))

@@ -209,11 +209,11 @@ def test_bad_arguments():
     assert ex.value.code == dsu.ESINGULAR
 
 
-@pytest.mark.parametrize("K,path", [(128, dsu.PATH_STREAM), (64, dsu.PATH_STREAM), (128, dsu.PATH_STREAM_X6)])
-def test_c4_shape_sampled(K, path):
+@pytest.mark.parametrize("K", [128, 64])
+def test_c4_shape_sampled(K):
     """N = 4096, FP32, K = 128 (and 64), sigma = 0.0015 (acceptance 0.99): the
-    bench's launch configuration on two walkers, with FP32 and with split-bf16
-    flush products.  Properties checked at full size:
+    bench's launch configuration on two walkers, from uniform-random starts
+    (cond(A) ~1e5, the worst case for FP32).  Properties checked at full size:
     after a sweep the running log-determinant against a direct (LAPACK)
     calculation and the inverse residual on sampled rows; on walker 0 the
     first window's ratios and decisions against the oracle's Sherman-Morrison
@@ -221,7 +221,6 @@ def test_c4_shape_sampled(K, path):
     require_gpu()
     n, walkers, sigma = 4096, 2, 0.0015
     b, pos = make_batch(n, walkers, 1, K, dsu.FP32_MIXED, sigma, seed=1000)
-    b.set_flush_path(path)
     b.set_trace(1)
     b.sweep(1)
     st = b.stats()
@@ -271,28 +270,37 @@ def test_c4_shape_sampled(K, path):
     b.close()
 
 
-@pytest.mark.parametrize("prec,n,K", [(dsu.FP64, 100, 16), (dsu.FP64, 200, 64), (dsu.FP32_MIXED, 256, 64),
-                                      (dsu.FP32_MIXED, 192, 128), (dsu.FP32_MIXED, 256, 128), (dsu.FP64, 256, 128)])
-def test_two_window_schedules_agree(prec, n, K):
-    """The one-pass streaming flush and the four-launch window schedule compute
-    the same ratios and decisions (to rounding)."""
+@pytest.mark.parametrize("prec,n,K", [(dsu.FP64, 200, 64), (dsu.FP64, 256, 128), (dsu.FP32_MIXED, 192, 128),
+                                      (dsu.FP32_MIXED, 256, 128), (dsu.FP32_MIXED, 300, 256),
+                                      (dsu.FP32_MIXED, 256, 256)])
+def test_wide_windows_against_oracle(prec, n, K):
+    """Windows of K = 128 and 256 (the decision kernel's register form up to
+    128, the bordered inverse in LDS/global memory at 256) on equilibrated
+    starts, two sweeps: FP64 to the oracle's ratios and decisions as
+    everywhere else; FP32 decisions identical to the oracle's until the first
+    marginal one (|u - R^2| within 1e-2 relative), the ratios before it within
+    the FP32 statistics bounds."""
     require_gpu()
-    out = []
-    p0 = burned_in(n, 2, 1, 51)
-    for streaming in (True, False):
-        b, pos = make_batch(n, 2, 1, K, prec, 0.2, seed=51, pos=p0)
-        b.set_flush_path(streaming)
-        b.set_trace(2)
-        b.sweep(2)
-        out.append((b.trace(0), b.trace(1), b.stats()))
-        b.close()
-    for (r0, a0), (r1, a1) in zip(out[0][:2], out[1][:2]):
-        m = len(a0) if np.array_equal(a0, a1) else int(np.nonzero(a0 != a1)[0][0])
-        assert m > n
-        if prec == dsu.FP64:
-            assert rel_err(r0[:m], r1[:m], FP64_FLOOR).max() < 1e-11
-        else:
-            assert_fp32_ratio_stats(rel_err(r0[:m], r1[:m]))
+    sigma, seed, walkers = 0.2, 51, 2
+    b, pos = make_batch(n, walkers, 1, K, prec, sigma, seed=seed, pos=burned_in(n, walkers, 1, seed))
+    b.set_trace(2)
+    b.sweep(2)
+    if prec == dsu.FP64:
+        check_fp64_against_oracle(b, pos, n, walkers, 1, sigma, 2, seed=seed)
+    else:
+        compared = 0
+        for w in range(walkers):
+            t = oracle_det(n, pos, w, 0, sigma, 2, seed=seed)
+            r, a = b.trace(w)
+            diff = np.nonzero(a != t.accepted)[0]
+            upto = diff[0] if len(diff) else len(a)
+            if len(diff):
+                assert marginal(t.u[upto], t.ratio[upto], 1e-2), (w, upto, r[upto], t.ratio[upto], t.u[upto])
+            print(f"walker {w}: identical decisions over {upto} of {len(a)} moves; ratio error median/p99/max",
+                  assert_fp32_ratio_stats(rel_err(r[:upto], t.ratio[:upto])), flush=True)
+            compared += upto
+        assert compared > walkers * n
+    b.close()
 
 
 @pytest.mark.parametrize("prec", [dsu.FP64, dsu.FP32_MIXED])
