@@ -152,8 +152,9 @@ def headline(args, cache):
         per.append(time.perf_counter() - t1)
         a = b.accuracy()
         right.append(float(a["residual"].max()))
-        if not np.array_equal(a["drift"], last_drift):
-            drift.append(float(np.abs(a["drift"]).max()))
+        changed = a["drift"] != last_drift
+        if changed.any():  # the determinants recomputed during this step
+            drift.append(float(np.abs(a["drift"][changed]).max()))
             last_drift = a["drift"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -268,6 +269,77 @@ def batched_at(n, walkers, cache, steps=2, precision=None, k_curve_ks=()):
                 b.set_delay(k)
                 curve[str(k)] = walkers * n / time_sweeps(b, 1, 1)
             out["k_curve_moves_per_s"] = curve
+    return out
+
+
+def c3_batched(cache, burn, n=512, walkers=512, K=32, sweeps=100, recompute_every=50, diag_walkers=16):
+    """512 walkers x N = 512 in one batch, K = 32, FP32 with FP64 recompute
+    every 50 sweeps, acceptance ~0.99, 100 sweeps, from the seeded uniform
+    starts or after 2 FP64 burn-in sweeps (set-up).  Per sweep: the residual
+    watchdog's sampled right residual (16 rows of every determinant); at each
+    recompute the log|det| drift; at the end of each interval both residuals
+    on 64 rows; and the FP32 ratios of the last sweep before the first
+    recompute against the oracle's FP64 ones on the first 16 walkers."""
+    import oracle
+    from paper_1708_00744_amd import dsu
+    sigma = sigma_or_default(n, 0.99, cache)
+    seeds, wids = [1000 + w for w in range(walkers)], list(range(walkers))
+    pos = batch_positions(n, walkers)
+    if burn:
+        pos, _ = burn_in(n, pos, seeds, wids, sweeps=2)
+    out = {"walkers": walkers, "n": n, "K": K, "sweeps": sweeps, "recompute_every": recompute_every,
+           "burn_in_sweeps": 2 if burn else 0, "sigma": sigma}
+    with dsu.Batch(n, pos, seeds, wids, sigma, K, precision=dsu.FP32_MIXED, box_l=BOX_L,
+                   recompute_every=recompute_every) as b:
+        if burn:
+            b.set_sweep(2)
+        b.set_residual_watchdog(16, 1e-3)
+        per, right, drift, left_end = [], [], [], []
+        last = b.accuracy()["drift"]
+        ratio_acc = None
+        for sw in range(sweeps):
+            trace = sw == recompute_every - 1
+            if trace:
+                p_diag = np.stack([b.positions(d) for d in range(diag_walkers)])
+                sweep_idx = int(b.stats()["sweeps"][0])
+                b.set_trace(1)
+            t1 = time.perf_counter()
+            b.sweep(1)
+            b.sync()
+            per.append(time.perf_counter() - t1)
+            a = b.accuracy()
+            right.append(float(a["residual"].max()))
+            changed = a["drift"] != last
+            if changed.any():  # the determinants recomputed before or after this sweep
+                drift.append(float(np.abs(a["drift"][changed]).max()))
+                last = a["drift"]
+            if sw % recompute_every == recompute_every - 1:
+                rr, rl = b.residual(64)
+                left_end.append({"after_sweep": sw + 1, "right_max": float(rr.max()), "left_max": float(rl.max()),
+                                 "left_median": float(np.median(rl))})
+            if trace:
+                tr = [b.trace(d) for d in range(diag_walkers)]
+                b.set_trace(0)
+                kv = oracle.pw_kvectors(n)
+                a_or = np.stack([oracle.pw_matrix(kv, BOX_L, p_diag[w]) for w in range(diag_walkers)])
+                i_or = np.ascontiguousarray(np.stack([np.linalg.inv(x) for x in a_or]))
+                r_or = np.zeros((diag_walkers, n))
+                oracle.walkers_moves(n, BOX_L, seeds[:diag_walkers], wids[:diag_walkers], sigma, sweep_idx, 0, n,
+                                     np.ascontiguousarray(p_diag), a_or, i_or, ratios=r_or)
+                diag = {"seeds": seeds[:diag_walkers], "wids": wids[:diag_walkers], "sweep": sweep_idx,
+                        "ratio": np.stack([x[0] for x in tr]), "accepted": np.stack([x[1] for x in tr]),
+                        "sweeps_since_recompute": recompute_every - 1}
+                ratio_acc = ratio_accuracy(diag, r_or, n, sigma)
+                ratio_acc.pop("measured")
+        st = b.stats()
+        wd = b.accuracy()["recomputes"]
+    t = sum(per)
+    out.update({"moves_per_s": walkers * n * sweeps / t,
+                "acceptance": float(st["accepted"].sum()) / (walkers * n * sweeps),
+                "sweep_ms_median": 1e3 * sorted(per)[len(per) // 2],
+                "residual_right_max_per_sweep": right, "logdet_drift_at_recompute": drift,
+                "end_of_interval": left_end, "watchdog_recomputes": int(wd),
+                "ratio_vs_fp64_oracle_last_sweep_before_recompute": ratio_acc})
     return out
 
 
@@ -673,6 +745,8 @@ def _cache():
 
 EXTRA_LEGS = {
     "walker_propose_n4096": lambda: walker_propose(),
+    "c3_n512_w512": lambda: c3_batched(_cache(), burn=False),
+    "c3_n512_w512_burn_in": lambda: c3_batched(_cache(), burn=True),
     "fp64_single_walker_n1024": lambda: fp64_single_walker(_cache()),
     "complex_single_walker_n1024": lambda: complex_single_walker(),
     "multidet_single_walker_n1024": lambda: multidet_single_walker(),
@@ -730,6 +804,9 @@ def main():
         extras["walker_propose_n4096"] = walker_propose()
     b.close()
     if not args.quick:
+        log("512 walkers x N=512, 100 sweeps, with and without FP64 burn-in")
+        extras["c3_n512_w512"] = c3_batched(cache, burn=False)
+        extras["c3_n512_w512_burn_in"] = c3_batched(cache, burn=True)
         log("batched N=1024 / 2048, FP32 and FP64")
         extras["fp32_batched_n1024"] = batched_at(1024, 256, cache, k_curve_ks=(16, 32, 128))
         extras["fp32_batched_n2048"] = batched_at(2048, 64, cache, k_curve_ks=(16, 32, 128))

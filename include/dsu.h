@@ -397,10 +397,15 @@ typedef struct {
     int64_t accepted;       /* accepted moves over all spins and sweeps           */
 } dsu_result;
 
-/* budget_bytes: device memory the pool may use for walker state (one arena,
- * allocated here); requests wait until enough is free.  Each size n also
- * gets a small recompute workspace outside the budget.  recompute_every as
- * in dsu_batch_create. */
+/* budget_bytes: device memory the pool may use (one arena, allocated here)
+ * for walker state and, for every size n with a resident walker, that size's
+ * FP64 recompute workspace (four determinants per pass; released when the
+ * size's last walker leaves); requests wait until enough is free.  Beyond the
+ * arena the pool holds only descriptor arrays, the orbital table and
+ * streams (under 1 MB per size).  recompute_every as in dsu_batch_create. */
+/* Bytes of the budget a pool charges for the recompute workspace of size n
+ * while walkers of that size are resident (0 on a bad n). */
+size_t dsu_server_workspace_bytes(int32_t n);
 int dsu_server_create(int32_t k_delay, int32_t precision, double box_L, size_t budget_bytes,
                       int32_t recompute_every, dsu_server **out);
 int dsu_server_destroy(dsu_server *s);

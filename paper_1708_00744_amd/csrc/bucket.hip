@@ -88,7 +88,8 @@ DetSlot BucketShape::carve(char *base) const {
     return d;
 }
 
-int Bucket::init(const BucketShape &shape, int k_delay, double box_l, void *stream_or_null, int gj_group) {
+int Bucket::init(const BucketShape &shape, int k_delay, double box_l, void *stream_or_null, int gj_group,
+                 void *gj_block) {
     sh = shape;
     K = k_delay;
     L = box_l;
@@ -102,7 +103,7 @@ int Bucket::init(const BucketShape &shape, int k_delay, double box_l, void *stre
     HIPCHK(hipMemcpy(kvec, kv.data(), sizeof(int4) * sh.n, hipMemcpyHostToDevice));
     kmax_comp = 0;
     for (const int4 &k : kv) kmax_comp = std::max({kmax_comp, std::abs(k.x), std::abs(k.y), std::abs(k.z)});
-    CHK(gj_.alloc(std::max(1, gj_group), sh.np, sh.n));
+    CHK(gj_.alloc(std::max(1, gj_group), sh.np, sh.n, gj_block));
     return DSU_OK;
 }
 

@@ -50,7 +50,10 @@ class Bucket {
     bool use_graph = false;
     int timing = 0;  // 0 off, 1 events around every launch, 2 around flush launches only
 
-    int init(const BucketShape &shape, int k_delay, double box_l, void *stream_or_null, int gj_group);
+    // gj_block (optional): GjWork::block_bytes(gj_group, np, n) bytes of the
+    // caller's device memory for the recompute workspace (else allocated here).
+    int init(const BucketShape &shape, int k_delay, double box_l, void *stream_or_null, int gj_group,
+             void *gj_block = nullptr);
     void release();
     // Replace the member list (descriptors re-uploaded, graph invalidated).
     int set_dets(const std::vector<DetSlot> &d);

@@ -91,7 +91,17 @@ struct BucketState {
     bool busy = false;
     bool dirty = false;
     hipEvent_t done = nullptr;
+    size_t ws_off = 0, ws_bytes = 0;  // the recompute workspace, carved from the arena
 };
+
+// Determinants recomputed per pass in a serving bucket.
+constexpr int kServerGjGroup = 4;
+
+// Arena bytes a bucket of size n takes for its recompute workspace.
+static size_t bucket_ws_bytes(int n) {
+    const int np = round_up(n, 64);
+    return GjWork::block_bytes(kServerGjGroup, np, n);
+}
 
 }  // namespace
 
@@ -114,15 +124,22 @@ static int bucket_for(dsu_server *s, int n, BucketState **out) {
     }
     std::unique_ptr<BucketState> b(new BucketState());
     const BucketShape sh = BucketShape::make(n, s->K, s->prec);
-    // recomputes run four determinants per pass; descriptor room for 64
-    int rc = b->bk.init(sh, s->K, s->L, nullptr, 4);
+    // the recompute workspace (four determinants per pass) is charged to the
+    // budget: carved from the arena, held while the server lives
+    b->ws_bytes = bucket_ws_bytes(n);
+    if (!s->arena.alloc(b->ws_bytes, &b->ws_off))
+        return fail(DSU_EBUDGET, "recompute workspace of size %d does not fit the free budget now", n);
+    // descriptor room for 64
+    int rc = b->bk.init(sh, s->K, s->L, nullptr, kServerGjGroup, s->arena_base + b->ws_off);
     if (rc == DSU_OK) rc = b->bk.reserve(64);
     if (rc != DSU_OK) {
         b->bk.release();
+        s->arena.release(b->ws_off, b->ws_bytes);
         return rc;
     }
     if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
         b->bk.release();
+        s->arena.release(b->ws_off, b->ws_bytes);
         return fail(DSU_EDEVICE, "hipEventCreate failed");
     }
     *out = b.get();
@@ -148,7 +165,11 @@ static int admit(dsu_server *s, const dsu_request &r, double now_s, int result_i
     if (r.n < 1 || r.n > 32768 || (r.spins != 1 && r.spins != 2) || r.sweeps < 0 || !r.positions)
         return fail(DSU_EINVAL, "bad request %llu", (unsigned long long)r.request_id);
     const size_t bytes = walker_bytes(r.n, r.spins, s->K, s->prec);
-    if (bytes > s->budget) return fail(DSU_EINVAL, "request %llu needs %zu bytes, budget %zu", (unsigned long long)r.request_id, bytes, s->budget);
+    // a walker of a size not resident yet also brings its bucket's workspace
+    const size_t ws = s->buckets.count(r.n) ? 0 : bucket_ws_bytes(r.n);
+    if (bytes + ws > s->budget)
+        return fail(DSU_EINVAL, "request %llu needs %zu bytes (walker %zu, recompute workspace %zu), budget %zu",
+                    (unsigned long long)r.request_id, bytes + ws, bytes, ws, s->budget);
     size_t off = 0;
     if (!s->arena.alloc(bytes, &off)) return fail(DSU_EBUDGET, "request does not fit the free budget now");
     BucketState *b = nullptr;
@@ -227,6 +248,22 @@ static int read_result(dsu_server *s, int slot, dsu_result *out) {
     return DSU_OK;
 }
 
+// Release idle buckets without members, with their recompute workspace
+// (charged to the budget only while a walker of that size is resident).
+static void drop_empty_buckets(dsu_server *s) {
+    for (auto it = s->buckets.begin(); it != s->buckets.end();) {
+        BucketState *b = it->second.get();
+        if (b->busy || !b->members.empty()) {
+            ++it;
+            continue;
+        }
+        b->bk.release();  // waits for the bucket's streams
+        if (b->done) (void)hipEventDestroy(b->done);
+        s->arena.release(b->ws_off, b->ws_bytes);
+        it = s->buckets.erase(it);
+    }
+}
+
 static void retire(dsu_server *s, int slot) {
     Resident &w = s->resident[slot];
     s->arena.release(w.off, w.bytes);
@@ -281,6 +318,11 @@ static int slot_of_det(dsu_server *s, BucketState *b, int pos) {
     return -1;
 }
 
+extern "C" size_t dsu_server_workspace_bytes(int32_t n) {
+    if (n < 1 || n > 32768) return 0;
+    return bucket_ws_bytes(n);
+}
+
 extern "C" int dsu_server_create(int32_t k_delay, int32_t precision, double box_L, size_t budget_bytes,
                                  int32_t recompute_every, dsu_server **out) {
     if (!out) return fail(DSU_EINVAL, "out is NULL");
@@ -329,6 +371,7 @@ extern "C" int dsu_server_add(dsu_server *s, const dsu_request *req, int32_t *sl
     const std::vector<int> bad = flag_singular(s, b);
     if (std::find(bad.begin(), bad.end(), slot) != bad.end()) {
         retire(s, slot);
+        drop_empty_buckets(s);
         return fail(DSU_ESINGULAR, "request %llu: Slater matrix is singular", (unsigned long long)req->request_id);
     }
     if (slot_out) *slot_out = slot;
@@ -364,7 +407,10 @@ extern "C" int dsu_server_result(dsu_server *s, int32_t slot, dsu_result *out, i
     auto it = s->buckets.find(n);
     if (it != s->buckets.end() && it->second->busy) return fail(DSU_ESTATE, "bucket busy");
     CHK(read_result(s, slot, out));
-    if (remove) retire(s, slot);
+    if (remove) {
+        retire(s, slot);
+        drop_empty_buckets(s);
+    }
     return DSU_OK;
 }
 
@@ -428,6 +474,7 @@ extern "C" int dsu_server_run(dsu_server *s, const dsu_request *reqs, int32_t co
             }
             CHK(recompute_due(s, b));
         }
+        drop_empty_buckets(s);
         // admission, first fit in arrival order, into idle buckets
         for (auto it = waiting.begin(); it != waiting.end();) {
             const dsu_request &r = reqs[*it];
@@ -436,7 +483,7 @@ extern "C" int dsu_server_run(dsu_server *s, const dsu_request *reqs, int32_t co
                 ++it;
                 continue;
             }
-            if (walker_bytes(r.n, r.spins, s->K, s->prec) > s->budget || r.sweeps == 0) {
+            if (walker_bytes(r.n, r.spins, s->K, s->prec) + bucket_ws_bytes(r.n) > s->budget || r.sweeps == 0) {
                 results[*it].status = r.sweeps == 0 ? DSU_OK : DSU_EBUDGET;
                 results[*it].admit_s = results[*it].finish_s = now_s();
                 ++completed;

@@ -67,26 +67,45 @@ size_t GjWork::bytes_per(int np_, int n) {
     return (size_t)np_ * np_ * 8 * 2 + (size_t)np_ * nb_ * 8 * 3 + (size_t)np_ * 12 + 128;
 }
 
-int GjWork::alloc(int groups, int np_, int n) {
+// Pieces of the workspace in carve order (bytes, each 256-byte aligned).
+static void gj_pieces(int g, int np, int nb, size_t out[15]) {
+    const size_t np2 = (size_t)np * np;
+    const size_t d = sizeof(double), i = sizeof(int);
+    const size_t v[15] = {np2 * g * d,          np2 * g * d,      (size_t)np * nb * g * d, (size_t)np * nb * g * d,
+                          (size_t)np * nb * g * d, (size_t)g * d, (size_t)np * g * i,      (size_t)np * g * i,
+                          (size_t)np * g * i,   (size_t)g * i,     (size_t)g * i,           (size_t)g * d,
+                          sizeof(GjDesc) * g,   sizeof(GjDesc) * g, sizeof(double *) * g};
+    for (int k = 0; k < 15; ++k) out[k] = (v[k] + 255) & ~(size_t)255;
+}
+
+size_t GjWork::block_bytes(int groups, int np_, int n) {
+    size_t p[15], b = 0;
+    gj_pieces(groups, np_, gj_panel_width(n), p);
+    for (size_t x : p) b += x;
+    return b;
+}
+
+int GjWork::alloc(int groups, int np_, int n, void *block) {
     g = groups;
     np = np_;
     nb = gj_panel_width(n);
+    owned = block == nullptr;
     const size_t np2 = (size_t)np * np;
-    CHK(dalloc(&m, np2 * g));
-    CHK(dalloc(&m2, np2 * g));
-    CHK(dalloc(&panel, (size_t)np * nb * g));
-    CHK(dalloc(&w, (size_t)np * nb * g));
-    CHK(dalloc(&q, (size_t)np * nb * g));
-    CHK(dalloc(&logdet, g));
-    CHK(dalloc(&piv, (size_t)np * g));
-    CHK(dalloc(&perm, (size_t)np * g));
-    CHK(dalloc(&rowsrc, (size_t)np * g));
-    CHK(dalloc(&sign, g));
-    CHK(dalloc(&status, g));
-    CHK(dalloc(&pmax, g));
-    CHK(dalloc(&gdesc, g));
-    CHK(dalloc(&gdesc_b, g));
-    CHK(dalloc(&mptr, g));
+    void **dst[15] = {(void **)&m,    (void **)&m2,     (void **)&panel, (void **)&w,      (void **)&q,
+                      (void **)&logdet, (void **)&piv, (void **)&perm,  (void **)&rowsrc, (void **)&sign,
+                      (void **)&status, (void **)&pmax, (void **)&gdesc, (void **)&gdesc_b, (void **)&mptr};
+    size_t p[15];
+    gj_pieces(g, np, nb, p);
+    char *c = static_cast<char *>(block);
+    if (c) HIPCHK(hipMemset(c, 0, block_bytes(groups, np_, n)));
+    for (int k = 0; k < 15; ++k) {
+        if (c) {
+            *dst[k] = c;
+            c += p[k];
+        } else {
+            CHK(dev_alloc(dst[k], p[k]));
+        }
+    }
     std::vector<GjDesc> ga(g), gb(g);
     std::vector<double *> mp(g);
     for (int i = 0; i < g; ++i) {
@@ -104,10 +123,11 @@ int GjWork::alloc(int groups, int np_, int n) {
 }
 
 void GjWork::release() {
-    for (void *p : {(void *)m, (void *)m2, (void *)panel, (void *)w, (void *)q, (void *)logdet, (void *)piv,
-                    (void *)perm, (void *)rowsrc, (void *)sign, (void *)status, (void *)gdesc, (void *)gdesc_b,
-                    (void *)mptr, (void *)pmax})
-        dfree(p);
+    if (owned)
+        for (void *p : {(void *)m, (void *)m2, (void *)panel, (void *)w, (void *)q, (void *)logdet, (void *)piv,
+                        (void *)perm, (void *)rowsrc, (void *)sign, (void *)status, (void *)gdesc, (void *)gdesc_b,
+                        (void *)mptr, (void *)pmax})
+            dfree(p);
     m = m2 = panel = w = q = logdet = pmax = nullptr;
     piv = perm = rowsrc = sign = status = nullptr;
     gdesc = gdesc_b = nullptr;

@@ -53,9 +53,14 @@ struct GjWork {
     hipError_t invert(int cnt, int n, hipStream_t s, const GjDesc **final_set) const {
         return launch_gj_invert(gdesc, gdesc_b, cnt, n, np, nb, s, final_set);
     }
-    int alloc(int groups, int np_, int n);
+    // Allocate for `groups` matrices; with `block` (block_bytes(groups, np_, n)
+    // bytes of device memory the caller owns) every buffer is carved from it
+    // and nothing is allocated.
+    int alloc(int groups, int np_, int n, void *block = nullptr);
     void release();
     static size_t bytes_per(int np_, int n);
+    static size_t block_bytes(int groups, int np_, int n);
+    bool owned = true;
 };
 
 }  // namespace dsu

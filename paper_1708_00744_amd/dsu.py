@@ -105,6 +105,7 @@ SIGNATURES = {
     "dsu_batch_kernel_time": (C.c_int, [_vp, _i32, _pi64, _pd]),
     "dsu_batch_use_graph": (C.c_int, [_vp, _i32]),
     "dsu_batch_set_delay": (C.c_int, [_vp, _i32]),
+    "dsu_server_workspace_bytes": (_sz, [_i32]),
     "dsu_server_create": (C.c_int, [_i32, _i32, _dbl, _sz, _i32, _pvp]),
     "dsu_server_destroy": (C.c_int, [_vp]),
     "dsu_server_run": (C.c_int, [_vp, C.POINTER(Request), _i32, C.POINTER(Result), _pd, _i64, _pi64]),
@@ -157,6 +158,11 @@ def _stream_ptr(stream):
 
 def footprint_bytes(n, k_delay, precision=FP32_MIXED):
     return int(lib().dsu_footprint_bytes(n, k_delay, precision))
+
+
+def server_workspace_bytes(n):
+    """Budget a serving pool charges for size n's recompute workspace."""
+    return int(lib().dsu_server_workspace_bytes(int(n)))
 
 
 def plane_wave_table(n):

@@ -303,6 +303,48 @@ def test_wide_windows_against_oracle(prec, n, K):
     b.close()
 
 
+def test_c3_shape_512_walkers():
+    """The 512-walker configuration at full width: 512 walkers x N = 512 in
+    one batch, K = 32, FP32 with FP64 recompute every 50 sweeps, acceptance
+    ~0.99, two sweeps.  The first 16 walkers start from equilibrated positions
+    (three oracle sweeps at sigma = 0.1 L) and are compared with the oracle
+    (OpenMP over walkers): decisions identical until the first marginal one,
+    ratios before it within the FP32 statistics bounds; the equilibrated
+    walkers' sampled right residual after the two sweeps within 1e-3, every
+    walker's (the others start uniform-random, cond(A) up to ~1e5) within
+    1e-2."""
+    require_gpu()
+    n, W, K, sigma, seed, nc = 512, 512, 32, 0.005, 61, 16
+    pos = np.stack([inputs.positions(seed, w, n, L).reshape(1, n, 3) for w in range(W)])
+    pos[:nc] = burned_in(n, nc, 1, seed)
+    b = dsu.Batch(n, pos, [seed] * W, list(range(W)), sigma, K, precision=dsu.FP32_MIXED, box_l=L,
+                  recompute_every=50)
+    b.set_trace(2)
+    b.sweep(2)
+    st = b.stats()
+    ratio, acc, _, _, _, threads = oracle.walkers_run(n, L, [seed] * nc, list(range(nc)), [0] * nc, sigma,
+                                                      pos[:nc, 0], 2)
+    errs, compared = [], 0
+    for w in range(nc):
+        r, a = b.trace(w)
+        diff = np.nonzero(a != acc[w])[0]
+        upto = int(diff[0]) if len(diff) else len(a)
+        if len(diff):
+            _, u = oracle.move_randoms(seed, w, upto // n, upto % n)
+            assert marginal(u, ratio[w, upto], 1e-2), (w, upto, r[upto], ratio[w, upto], u)
+        errs.append(rel_err(r[:upto], ratio[w, :upto]))
+        compared += upto
+    print(f"{compared} of {nc * 2 * n} moves compared ({threads} oracle threads); ratio error median/p99/max",
+          assert_fp32_ratio_stats(np.concatenate(errs)), flush=True)
+    assert compared > nc * n
+    right, _ = b.residual(16, left=False)
+    acc_all = st["accepted"].sum() / (W * 2 * n)
+    print(f"acceptance {acc_all:.4f}, right residual max: equilibrated {right[:nc].max():.2e}, all 512 walkers "
+          f"{right.max():.2e}", flush=True)
+    assert right[:nc].max() < FP32_RESIDUAL and right.max() < 1e-2 and acc_all > 0.97
+    b.close()
+
+
 @pytest.mark.parametrize("prec", [dsu.FP64, dsu.FP32_MIXED])
 def test_checkpoint_resume(prec):
     """Stop after 2 sweeps, keep {positions, seeds, walker ids, sweeps done},

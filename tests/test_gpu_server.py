@@ -68,7 +68,7 @@ def test_budget_admission_and_run():
     require_gpu()
     K, n, sweeps = 16, 256, 4
     per = dsu.footprint_bytes(n, K, dsu.FP32_MIXED)
-    budget = int(2.5 * per)  # two walkers at a time
+    budget = dsu.server_workspace_bytes(n) + int(2.5 * per)  # the size's workspace and two walkers at a time
     reqs = [{"request_id": 100 + i, "n": n, "spins": 1, "seed": 3, "sigma": 0.1, "sweeps": sweeps,
              "arrival_s": 0.0, "positions": positions(3, 100 + i, n, 1)} for i in range(5)]
     # one request that can never fit
@@ -132,3 +132,66 @@ def test_singular_walker_is_reported_not_fatal():
     assert results[1]["status"] == dsu.ESINGULAR
     alone = run_alone(dsu.FP32_MIXED, K, good, sweeps)
     assert results[0]["logdet"] == alone["logdet"] and results[0]["accepted"] == alone["accepted"]
+
+
+def test_recompute_groups_beyond_four_determinants():
+    """Three walkers x two spins of one size (six determinants: the serving
+    recompute runs four per pass, so the periodic recompute takes two passes):
+    each walker's result over five sweeps with a recompute every two equals
+    the same request alone (two determinants, one pass), bit for bit."""
+    require_gpu()
+    K, n, sweeps = 16, 96, 5
+    reqs = [{"request_id": 40 + i, "n": n, "spins": 2, "seed": 9, "sigma": 0.2,
+             "positions": positions(9, 40 + i, n, 2)} for i in range(3)]
+    for prec in (dsu.FP64, dsu.FP32_MIXED):
+        with dsu.Server(K, precision=prec, box_l=L, budget_bytes=1 << 30, recompute_every=2) as s:
+            slots = [s.add(r["request_id"], n, 2, r["seed"], r["sigma"], sweeps, r["positions"]) for r in reqs]
+            for _ in range(sweeps):
+                s.step()
+            mixed = [s.result(slot, remove=True) for slot in slots]
+        for r, m in zip(reqs, mixed):
+            with dsu.Server(K, precision=prec, box_l=L, budget_bytes=1 << 30, recompute_every=2) as s:
+                slot = s.add(r["request_id"], n, 2, r["seed"], r["sigma"], sweeps, r["positions"])
+                for _ in range(sweeps):
+                    s.step()
+                alone = s.result(slot, remove=True)
+            assert m["logdet"] == alone["logdet"] and m["sign"] == alone["sign"]
+            assert m["accepted"] == alone["accepted"] and m["sweeps_done"] == sweeps
+
+
+def test_device_memory_within_budget():
+    """Everything a pool holds on the device beyond its budget is its
+    descriptors, orbital tables and streams: walkers of three sizes resident at
+    once (their recompute workspaces included, 268 MB at n = 2048) raise the
+    device memory in use by the budget and at most 16 MiB more (measured: 4
+    MiB; the workspaces alone would be 357 MiB); dropping the last walker of a size releases that size's
+    workspace to the budget."""
+    torch = require_gpu()
+    K, budget = 64, 1 << 30
+    sizes = (512, 1024, 2048)
+    reqs = [(100 + i, n, positions(13, 100 + i, n, 2)) for i, n in enumerate(sizes)]
+
+    def fill(s):
+        return [s.add(rid, n, 2, 13, 0.01, 2, p) for rid, n, p in reqs]
+
+    with dsu.Server(K, precision=dsu.FP32_MIXED, box_l=L, budget_bytes=budget) as s:  # load the kernels once
+        fill(s)
+        s.step()
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    with dsu.Server(K, precision=dsu.FP32_MIXED, box_l=L, budget_bytes=budget) as s:
+        slots = fill(s)
+        s.step()
+        torch.cuda.synchronize()
+        free1, _ = torch.cuda.mem_get_info()
+        used, resident = s.usage()
+        ws = sum(dsu.server_workspace_bytes(n) for n in sizes)
+        walkers = sum(2 * dsu.footprint_bytes(n, K, dsu.FP32_MIXED) for n in sizes)
+        print(f"device memory raised by {(free0 - free1) / 2**20:.1f} MiB for a {budget / 2**20:.0f} MiB budget; "
+              f"arena in use {used / 2**20:.1f} MiB (workspaces {ws / 2**20:.1f}, walkers {walkers / 2**20:.1f})",
+              flush=True)
+        assert resident == 3 and used >= ws + walkers
+        assert free0 - free1 <= budget + (16 << 20)
+        s.result(slots[2], remove=True)
+        used2, _ = s.usage()
+        assert used - used2 >= dsu.server_workspace_bytes(2048) + 2 * dsu.footprint_bytes(2048, K, dsu.FP32_MIXED)
