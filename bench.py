@@ -386,39 +386,55 @@ def walker_propose(n=4096, K=128, moves=256):
                     "the flush pass (no separate read of BT)"}
 
 
-def fp64_single_walker(cache, n=1024, sweeps=1):
-    """The plain FP64 single-walker form: host-driven through the C ABI (one
-    propose/accept call per move, host decisions), plane-wave rows from the
-    library, and the same walker driven on the device (a batch of one)."""
+def c2_k_study(cache, n=1024, ks=(1, 4, 16, 32, 64, 128), device_sweeps=10, host_sweeps=1):
+    """One FP64 walker of N = 1024: moves/s against the delay K at acceptance
+    0.99 and 0.5 (sigma from the tuner) and with every move accepted (the
+    paper's test regime), driven on the device (a batch of one walker: K
+    proposals per window, decisions on the device, 10 sweeps) and from the
+    host through the C ABI (one propose/accept call per move, K accepted moves
+    per flush, one sweep), the latter with the flush on the vector ALUs and on
+    the matrix cores (the crossover of the two flush kernels)."""
     from paper_1708_00744_amd import dsu, inputs
-    sigma = sigma_or_default(n, 0.99, cache)
     pos0 = inputs.positions(2, 0, n, BOX_L)
-    res = {"n": n, "sigma": sigma}
     a0 = dsu.plane_wave_rows(n, BOX_L, pos0)
-    for K in (1, 16, 64):
-        pos = pos0.copy()
-        g = inputs.normals(3, (sweeps, n, 3))
-        us = inputs.uniforms(4, sweeps * n)
-        with dsu.Walker(a0, K, precision=dsu.FP64, policy=dsu.FLUSH_K_ACCEPTED) as w:
-            t0 = time.perf_counter()
-            for s in range(sweeps):
-                prop = pos + sigma * g[s]
-                rows = dsu.plane_wave_rows(n, BOX_L, prop)
-                for e in range(n):
-                    r = w.propose(e, rows[e])
-                    if us[s * n + e] < r * r:
-                        w.accept()
-                        pos[e] = prop[e]
-                    else:
-                        w.reject()
-            w.flush()
-            dt = time.perf_counter() - t0
-        res[f"host_driven_K{K}"] = n * sweeps / dt
-    for K in (1, 64):
-        with dsu.Batch(n, pos0[None], [2], [0], sigma, K, precision=dsu.FP64, box_l=BOX_L) as b:
-            dt = time_sweeps(b, 2, 1)
-        res[f"device_driven_K{K}"] = n * 2 / dt
-    return res
+    out = {"n": n, "K": list(ks), "device_sweeps": device_sweeps, "host_sweeps": host_sweeps}
+    for label, target in (("acc0.99", 0.99), ("acc0.5", 0.5), ("force_accept", None)):
+        sigma = sigma_or_default(n, target, cache) if target else sigma_or_default(n, 0.99, cache)
+        force = target is None
+        dev, acc = {}, {}
+        for K in ks:
+            with dsu.Batch(n, pos0[None], [2], [0], sigma, K, precision=dsu.FP64, box_l=BOX_L) as b:
+                dt = time_sweeps(b, device_sweeps, 1, force)
+                acc[str(K)] = float(b.stats()["accepted"][0]) / (n * (device_sweeps + 1))
+            dev[str(K)] = n * device_sweeps / dt
+        host = {}
+        g = inputs.normals(3, (host_sweeps, n, 3))
+        us = inputs.uniforms(4, host_sweeps * n)
+        for mode, mname in ((dsu.FLUSH_VALU, "valu"), (dsu.FLUSH_MFMA, "mfma")):
+            curve = {}
+            for K in ks:
+                if mode == dsu.FLUSH_VALU and K > 64:
+                    continue
+                pos = pos0.copy()
+                with dsu.Walker(a0, K, precision=dsu.FP64, policy=dsu.FLUSH_K_ACCEPTED) as w:
+                    w.set_flush_kernel(mode)
+                    t0 = time.perf_counter()
+                    for sw in range(host_sweeps):
+                        prop = pos + sigma * g[sw]
+                        rows = dsu.plane_wave_rows(n, BOX_L, prop)
+                        for e in range(n):
+                            r = w.propose(e, rows[e])
+                            if force or us[sw * n + e] < r * r:
+                                w.accept()
+                                pos[e] = prop[e]
+                            else:
+                                w.reject()
+                    w.flush()
+                    curve[str(K)] = n * host_sweeps / (time.perf_counter() - t0)
+            host[mname] = curve
+        out[label] = {"sigma": sigma, "device_driven_moves_per_s": dev, "device_acceptance": acc,
+                      "host_driven_moves_per_s": host}
+    return out
 
 
 def drift_single_walker(n=1024, moves=1024, tau=0.002):
@@ -580,30 +596,50 @@ def multidet_single_walker(n=1024, m=16, sigma=0.002):
     return res
 
 
-def serving(cache, count=40, seed=7):
-    from paper_1708_00744_amd import dsu, inputs
+def serving_requests(cache, count, seed, arrival_rate=None):
+    from paper_1708_00744_amd import inputs
     sizes, accs, seeds = inputs.serving_mix(seed, count)
+    arr = inputs.poisson_arrivals(seed, count, rate_per_s=arrival_rate) if arrival_rate else np.zeros(count)
     reqs = []
     for i in range(count):
         n = int(sizes[i])
-        s = sigma_or_default(n, float(accs[i]), cache) if n <= 2048 else 0.01
-        reqs.append({"request_id": i, "n": n, "spins": 2, "seed": int(seeds[i]), "sigma": s, "sweeps": 20,
-                     "arrival_s": 0.0, "positions": inputs.positions(int(seeds[i]), i, 2 * n, BOX_L)})
-    # arrivals: Poisson at the rate that keeps the pool busy (about one
-    # request per mean service time of a small walker)
-    arr = inputs.poisson_arrivals(seed, count, rate_per_s=40.0)
-    for q, t in zip(reqs, arr):
-        q["arrival_s"] = float(t)
-    with dsu.Server(64, precision=dsu.FP32_MIXED, box_l=BOX_L, budget_bytes=8 << 30, recompute_every=10) as srv:
+        reqs.append({"request_id": i, "n": n, "spins": 2, "seed": int(seeds[i]),
+                     "sigma": sigma_or_default(n, float(accs[i]), cache), "sweeps": 20, "arrival_s": float(arr[i]),
+                     "positions": inputs.positions(int(seeds[i]), i, 2 * n, BOX_L)})
+    return reqs
+
+
+def serve(reqs, budget, K=64):
+    from paper_1708_00744_amd import dsu
+    with dsu.Server(K, precision=dsu.FP32_MIXED, box_l=BOX_L, budget_bytes=budget, recompute_every=10) as srv:
         t0 = time.perf_counter()
         results, lat = srv.run(reqs)
         wall = time.perf_counter() - t0
-    moves = sum(2 * q["n"] * q["sweeps"] for q, r in zip(reqs, results) if r["status"] == 0)
-    e2e = [r["finish_s"] - q["arrival_s"] for q, r in zip(reqs, results) if r["status"] == 0]
-    wait = [r["admit_s"] - q["arrival_s"] for q, r in zip(reqs, results) if r["status"] == 0]
-    return {"requests": count, "wall_s": wall, "moves_per_s": moves / wall,
+    return results, lat, wall
+
+
+def serving(cache, count=200, seed=7, budget=8 << 30, load=0.8):
+    """Poisson stream of walker requests (N from {128, ..., 2048}, two spins,
+    target acceptance 0.5-0.99, 20 sweeps each, FP32 with an FP64 recompute
+    every 10 sweeps) into a pool with an 8 GiB budget.  The arrival rate is
+    `load` times the capacity measured first: the completion rate of the same
+    kind of requests all waiting at time zero (a closed, saturated pool)."""
+    cal = serving_requests(cache, 60, seed + 1000)
+    results, _, wall = serve(cal, budget)
+    capacity = sum(r["status"] == 0 for r in results) / wall
+    rate = load * capacity
+    reqs = serving_requests(cache, count, seed, arrival_rate=rate)
+    results, lat, wall = serve(reqs, budget)
+    ok = [(q, r) for q, r in zip(reqs, results) if r["status"] == 0]
+    moves = sum(2 * q["n"] * q["sweeps"] for q, _ in ok)
+    e2e = [r["finish_s"] - q["arrival_s"] for q, r in ok]
+    wait = [r["admit_s"] - q["arrival_s"] for q, r in ok]
+    return {"requests": count, "completed": len(ok), "budget_bytes": budget,
+            "capacity_requests_per_s": capacity, "arrival_rate_per_s": rate, "load": load, "wall_s": wall,
+            "moves_per_s": moves / wall,
             "sweep_latency_ms_p50": float(np.percentile(lat, 50)), "sweep_latency_ms_p99": float(np.percentile(lat, 99)),
-            "queue_wait_s_p50": float(np.percentile(wait, 50)), "end_to_end_s_p99": float(np.percentile(e2e, 99))}
+            "queue_wait_s_p50": float(np.percentile(wait, 50)), "queue_wait_s_p99": float(np.percentile(wait, 99)),
+            "end_to_end_s_p50": float(np.percentile(e2e, 50)), "end_to_end_s_p99": float(np.percentile(e2e, 99))}
 
 
 def ratio_accuracy(diag, r_or, upto, sigma):
@@ -745,9 +781,10 @@ def _cache():
 
 EXTRA_LEGS = {
     "walker_propose_n4096": lambda: walker_propose(),
+    "serving": lambda: serving(_cache()),
+    "c2_k_study_n1024": lambda: c2_k_study(_cache()),
     "c3_n512_w512": lambda: c3_batched(_cache(), burn=False),
     "c3_n512_w512_burn_in": lambda: c3_batched(_cache(), burn=True),
-    "fp64_single_walker_n1024": lambda: fp64_single_walker(_cache()),
     "complex_single_walker_n1024": lambda: complex_single_walker(),
     "multidet_single_walker_n1024": lambda: multidet_single_walker(),
     "fp64_drift_walker_n1024": lambda: drift_single_walker(),
@@ -812,8 +849,9 @@ def main():
         extras["fp32_batched_n2048"] = batched_at(2048, 64, cache, k_curve_ks=(16, 32, 128))
         extras["fp64_batched_n1024"] = batched_at(1024, 256, cache, precision=dsu.FP64)
         extras["fp64_batched_n2048"] = batched_at(2048, 64, cache, precision=dsu.FP64)
-        log("FP64 single walker N=1024")
-        extras["fp64_single_walker_n1024"] = fp64_single_walker(cache)
+        extras["fp64_batched_n4096"] = batched_at(4096, 32, cache, precision=dsu.FP64)
+        log("FP64 single walker N=1024: K study at acceptance 0.99, 0.5 and 1, VALU/MFMA flush")
+        extras["c2_k_study_n1024"] = c2_k_study(cache)
         log("complex-orbital walker N=1024")
         extras["complex_single_walker_n1024"] = complex_single_walker()
         log("multideterminant walker N=1024")
