@@ -113,3 +113,31 @@ def test_rendering_fp32_decisions():
         assert np.array_equal(r.accepted, t.accepted)
         e = rel_err(r.ratio, t.ratio)
         assert np.median(e) * 10 <= FP32_MEDIAN and e.max() * 10 <= FP32_MAX
+
+
+def test_rendering_fp32_c4_uniform_start():
+    """test_gpu_batch.test_c4_shape_sampled's inputs (N = 4096, K = 128,
+    sigma = 0.0015, one sweep of walkers 0 and 1 keyed (1000, w) from their
+    seeded uniform-random starts, the same 256 sampled rows): cond(A) ~1e5,
+    the worst case for FP32.  This measures where a correct FP32 delayed
+    implementation ends the sweep -- max |A^-1 A - I| on the sampled rows and
+    the running log-determinant against LAPACK's (measured: residual 6.2e-3
+    and 2.7e-2, log-determinant 3.2e-4 and 6.1e-4) -- and checks that the GPU
+    test's bounds (residual 0.2, log-determinant 2e-2) sit at least 7x and 30x
+    above it: the GPU rounds in another order and at this conditioning the
+    error is dominated by it."""
+    n, K, sigma, seed = 4096, 128, 0.0015, 1000
+    rng = np.random.default_rng(5)
+    kv = oracle.pw_kvectors(n)
+    pos = uniform(n, L, 2, 1, seed)
+    res, dld = [], []
+    for w in range(2):
+        rows = rng.choice(n, 256, replace=False)
+        r = render_delayed(n, L, K, np.float32, seed, w, 0, sigma, pos[w, 0], 1, residual=True, residual_rows=rows,
+                           lapack_start=True)
+        s_np, l_np = np.linalg.slogdet(oracle.pw_matrix(kv, L, r.pos))
+        res.append(r.residual[-1])
+        dld.append(abs(r.logdet - l_np))
+        assert r.sign == s_np
+    print(f"FP32 rendering, uniform start: residual {res}, log|det| error {dld}")
+    assert 1e-3 < max(res) and 7 * max(res) <= 0.2 and 30 * max(dld) <= 2e-2

@@ -236,10 +236,11 @@ def test_c4_shape_sampled(K):
         inv = b.inverse(w)
         res = np.abs(inv[rows] @ a_end - np.eye(n)[rows]).max()
         print(f"walker {w}: residual (256 rows) {res:.2e}, logdet diff {st['logdet'][w] - l_np:.2e}", flush=True)
-        # FP32 error growth over a sweep from this start: a CPU FP32 rendering of
-        # the same delayed updates ends at residual 6.8e-3 (walker 0) and 6.5e-2
-        # (walker 1, cond(A) 6e4 at the end)
-        assert st["sign"][w] == s_np and abs(st["logdet"][w] - l_np) < 0.1
+        # FP32 error growth over a sweep from this start: the CPU FP32 rendering
+        # of the same delayed updates on the same rows ends at residual 6.2e-3
+        # and 2.7e-2, log-determinant 3.2e-4 and 6.1e-4 off
+        # (test_delayed_rendering.test_rendering_fp32_c4_uniform_start)
+        assert st["sign"][w] == s_np and abs(st["logdet"][w] - l_np) < 2e-2
         assert res < 0.2
         if w > 0:
             continue
