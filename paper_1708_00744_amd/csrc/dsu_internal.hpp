@@ -102,9 +102,10 @@ template <typename T> struct DetDesc {
 
 // Flush (eq. (4)) of `ndesc` determinants with `kslots` delayed slots
 // (<= kp of the descriptors' buffers); mode 0 = MFMA fused, 1 = VALU.
+// ld: row length of BT, U and Vg (0 = np; MFMA mode only otherwise).
 template <typename T>
 hipError_t launch_flush(const FlushDesc<T> *descs_dev, int ndesc, int n, int np, int kslots, int mode,
-                        hipStream_t s);
+                        hipStream_t s, int ld = 0);
 
 // FP64 inversion by blocked Gauss-Jordan with partial pivoting.
 struct GjDesc {

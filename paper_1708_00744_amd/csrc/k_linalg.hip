@@ -31,8 +31,11 @@ template <typename T, int KP> struct FlushLds {
 // ---------------------------------------------------------------------------
 // Fused Woodbury flush, one 64-row block of one determinant per workgroup.
 // ---------------------------------------------------------------------------
+// Rows of BT, U and Vg are `ld` elements long (ld = np for a real inverse;
+// the complex walker passes its interleaved complex inverse as real rows of
+// 2 np, with U, Vg and C^{-1} in their real embedding).
 template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_flush_mfma(const FlushDesc<T> *__restrict__ descs, int np,
+__global__ __launch_bounds__(kThreads) void k_flush_mfma(const FlushDesc<T> *__restrict__ descs, int ld,
                                                          int nblk, int kslots) {
     __shared__ __attribute__((aligned(16))) T lds[FlushLds<T, KP>::elems];
     constexpr int LDY = FlushLds<T, KP>::LDY;
@@ -42,7 +45,7 @@ __global__ __launch_bounds__(kThreads) void k_flush_mfma(const FlushDesc<T> *__r
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     typename Mma<T>::acc_t acc[KP / 16];
-    rowblock_times_ut<T, KP>(fd.bt + (size_t)r0 * np, np, kRowBlock, fd.u, np, 0, np, lds, acc);
+    rowblock_times_ut<T, KP>(fd.bt + (size_t)r0 * ld, ld, kRowBlock, fd.u, ld, 0, ld, lds, acc);
 
     // Y block -> LDS, subtract E, then W = Y' C^{-T} on matrix cores.
 #pragma unroll
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(kThreads) void k_flush_mfma(const FlushDesc<T> *__r
 #pragma unroll
     for (int s = 0; s < KP / 4; ++s) wa[s] = -lds[(16 * wave + (lane & 15)) * LDY + 4 * s + (lane >> 4)];
     __syncthreads();
-    rowblock_plus_wv<T, KP>(fd.bt + (size_t)r0 * np, np, np, fd.vg, np, wa, lds);
+    rowblock_plus_wv<T, KP>(fd.bt + (size_t)r0 * ld, ld, ld, fd.vg, ld, wa, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -121,8 +124,10 @@ __global__ __launch_bounds__(kThreads) void k_flush_valu(const FlushDesc<T> *__r
 
 template <typename T>
 hipError_t launch_flush(const FlushDesc<T> *descs_dev, int ndesc, int n, int np, int kslots, int mode,
-                        hipStream_t s) {
+                        hipStream_t s, int ld) {
     (void)n;
+    if (ld == 0) ld = np;
+    if (mode == 1 && ld != np) return hipErrorInvalidValue;
     if (ndesc <= 0 || kslots <= 0) return hipSuccess;
     if (mode == 1) {
         const int blocks = ndesc * np / 4;
@@ -139,15 +144,15 @@ hipError_t launch_flush(const FlushDesc<T> *descs_dev, int ndesc, int n, int np,
     const dim3 grid(ndesc * nblk);
 #define DSU_MFMA(KPV)                                                                            \
     if (kslots <= KPV) {                                                                         \
-        hipLaunchKernelGGL((k_flush_mfma<T, KPV>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk, kslots); \
+        hipLaunchKernelGGL((k_flush_mfma<T, KPV>), grid, dim3(kThreads), 0, s, descs_dev, ld, nblk, kslots); \
         return hipGetLastError();                                                                \
     }
     DSU_MFMA(16) DSU_MFMA(32) DSU_MFMA(64) DSU_MFMA(128) DSU_MFMA(256)
 #undef DSU_MFMA
     return hipErrorInvalidValue;
 }
-template hipError_t launch_flush<float>(const FlushDesc<float> *, int, int, int, int, int, hipStream_t);
-template hipError_t launch_flush<double>(const FlushDesc<double> *, int, int, int, int, int, hipStream_t);
+template hipError_t launch_flush<float>(const FlushDesc<float> *, int, int, int, int, int, hipStream_t, int);
+template hipError_t launch_flush<double>(const FlushDesc<double> *, int, int, int, int, int, hipStream_t, int);
 
 // ---------------------------------------------------------------------------
 // Blocked Gauss-Jordan inversion (FP64, in place, partial pivoting).

@@ -83,6 +83,7 @@ SIGNATURES = {
     "dsu_zget_inverse": (C.c_int, [_vp, _pd]),
     "dsu_zget_logdet": (C.c_int, [_vp, _pd, _pd]),
     "dsu_zwalker_pending": (C.c_int, [_vp, _pi32]),
+    "dsu_zwalker_set_flush_kernel": (C.c_int, [_vp, _i32]),
     "dsu_batch_create": (C.c_int, [_i32, _i32, _i32, _i32, _i32, _dbl, _pu64, _pu64, _pd, _pd, _i32, _vp, _pvp]),
     "dsu_batch_destroy": (C.c_int, [_vp]),
     "dsu_batch_sweep": (C.c_int, [_vp, _i32, _i32]),
@@ -366,6 +367,9 @@ class ZWalker:
         k = C.c_int32()
         _check(lib().dsu_zwalker_pending(self._h, C.byref(k)))
         return k.value
+
+    def set_flush_kernel(self, mode):
+        _check(lib().dsu_zwalker_set_flush_kernel(self._h, mode))
 
 
 class Batch:

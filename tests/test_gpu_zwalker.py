@@ -36,7 +36,7 @@ def twisted_system(n, L, seed):
     return kv, pos, oracle.zpw_matrix(kv, THETA, L, pos)
 
 
-def run_zwalker(n, K, policy, nmoves, seed, L=4.0, sigma=0.15):
+def run_zwalker(n, K, policy, nmoves, seed, L=4.0, sigma=0.15, mode=None):
     kv, pos, a = twisted_system(n, L, seed)
     ainv, _, _ = oracle.zinverse(a)
     order = inputs.electron_order(seed + 1, n, nmoves)
@@ -44,6 +44,8 @@ def run_zwalker(n, K, policy, nmoves, seed, L=4.0, sigma=0.15):
     us = inputs.uniforms(seed + 3, nmoves)
     errs = []
     w = dsu.ZWalker(a, K, policy=policy)
+    if mode is not None:
+        w.set_flush_kernel(mode)
     for m in range(nmoves):
         e = int(order[m])
         rt = pos[e] + sigma * g[m]
@@ -76,13 +78,19 @@ def test_zcreate_inverts(n):
     assert abs(la - l) < 1e-10 * max(1, abs(l)) and phase_diff(ph, np.angle(s)) < 1e-10
 
 
-@pytest.mark.parametrize("K,policy", [(1, dsu.FLUSH_K_ACCEPTED), (4, dsu.FLUSH_K_PROPOSED), (16, dsu.FLUSH_K_ACCEPTED),
-                                      (40, dsu.FLUSH_K_PROPOSED), (64, dsu.FLUSH_K_ACCEPTED),
-                                      (128, dsu.FLUSH_K_ACCEPTED)])
-def test_zratios_decisions_inverse(K, policy):
+@pytest.mark.parametrize("K,policy,mode", [(1, dsu.FLUSH_K_ACCEPTED, None), (4, dsu.FLUSH_K_PROPOSED, None),
+                                           (4, dsu.FLUSH_K_PROPOSED, dsu.FLUSH_VALU),
+                                           (16, dsu.FLUSH_K_ACCEPTED, None), (16, dsu.FLUSH_K_ACCEPTED, dsu.FLUSH_VALU),
+                                           (40, dsu.FLUSH_K_PROPOSED, dsu.FLUSH_MFMA),
+                                           (64, dsu.FLUSH_K_ACCEPTED, None), (64, dsu.FLUSH_K_ACCEPTED, dsu.FLUSH_VALU),
+                                           (128, dsu.FLUSH_K_ACCEPTED, None), (200, dsu.FLUSH_K_ACCEPTED, None)])
+def test_zratios_decisions_inverse(K, policy, mode):
+    """Both flush kernels (matrix cores through the real embedding, and the
+    vector-ALU complex kernels; K = 200 exceeds the embedding's 256 slots and
+    takes the latter) against the complex oracle."""
     require_gpu()
     n = 96
-    w, a, ainv, errs = run_zwalker(n, K, policy, 3 * n, seed=300 + K)
+    w, a, ainv, errs = run_zwalker(n, K, policy, 3 * n, seed=300 + K, mode=mode)
     assert len(errs) > 2 * n and errs.max() < FP64_TOL
     np.testing.assert_allclose(w.inverse(), ainv, rtol=1e-9, atol=1e-10)
     la, ph = w.logdet()
@@ -168,6 +176,23 @@ def test_zrecompute_and_drift():
     s, l = np.linalg.slogdet(b)
     assert abs(la2 - l) < 1e-10 and phase_diff(ph2, np.angle(s)) < 1e-10
     w.close()
+
+
+def test_zwalker_n1024_k64_matrix_cores():
+    """N = 1024, K = 64 with the flush on the matrix cores: 300 moves, every
+    ratio against the complex oracle (complex Sherman-Morrison), the final
+    inverse against the oracle's, and the flush kernels' results against each
+    other: the same walk with the vector-ALU flush lands on the same inverse
+    to rounding."""
+    require_gpu()
+    inv = {}
+    for mode in (dsu.FLUSH_MFMA, dsu.FLUSH_VALU):
+        w, a, ainv, errs = run_zwalker(1024, 64, dsu.FLUSH_K_ACCEPTED, 300, seed=71, L=10.0, sigma=0.05, mode=mode)
+        assert len(errs) == 300 and errs.max() < FP64_TOL
+        inv[mode] = w.inverse()
+        np.testing.assert_allclose(inv[mode], ainv, rtol=1e-8, atol=1e-9 * np.abs(ainv).max())
+        w.close()
+    assert np.abs(inv[dsu.FLUSH_MFMA] - inv[dsu.FLUSH_VALU]).max() < 1e-9 * np.abs(ainv).max()
 
 
 def test_zwalker_n512_sampled():
