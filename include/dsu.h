@@ -242,12 +242,13 @@ int dsu_zget_inverse(dsu_zwalker *w, double *out_host);
  * since the last fresh inverse). */
 int dsu_zget_logdet(dsu_zwalker *w, double *logabs, double *phase);
 int dsu_zwalker_pending(dsu_zwalker *w, int32_t *k_out);
-/* Flush kernel of the complex walker: DSU_FLUSH_MFMA applies eq. (4) on the
- * FP64 matrix cores through the real embedding of the complex operands (each
- * complex product as its four real products: the complex inverse read as real
- * rows of 2n values, U, Vg and C^{-1} expanded to 2k real slots), for
- * 2k <= 256; DSU_FLUSH_VALU uses the vector-ALU complex kernels;
- * DSU_FLUSH_AUTO (default) takes the matrix cores for 2 < k <= 128. */
+/* Flush kernel of the complex walker.  W = (BT U^T - E) C^{-T} is formed row
+ * by row on the vector ALUs; the rank-k update BT -= W Vg then runs, with
+ * DSU_FLUSH_MFMA, on the FP64 matrix cores through the real embedding of the
+ * complex operands (the inverse and W read as real rows of interleaved
+ * doubles, Vg expanded to 2k real rows: each complex product as its four real
+ * products), tiled over rows and columns, when 2k <= 256; otherwise, and
+ * with DSU_FLUSH_VALU, as a complex product on the vector ALUs.  DSU_FLUSH_AUTO (default): the matrix cores for k > 2. */
 int dsu_zwalker_set_flush_kernel(dsu_zwalker *w, int32_t mode);
 
 /* ======================================================================

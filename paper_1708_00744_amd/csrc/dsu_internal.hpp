@@ -107,6 +107,11 @@ template <typename T>
 hipError_t launch_flush(const FlushDesc<T> *descs_dev, int ndesc, int n, int np, int kslots, int mode,
                         hipStream_t s, int ld = 0);
 
+// C[0:nrows, 0:ncols] -= W[:, 0:kslots] V[0:kslots, :] (FP64, matrix cores;
+// V rows kslots .. padded width zero; nrows and ncols multiples of 64).
+hipError_t launch_gemm_sub(const double *W, int ldw, int kslots, const double *V, int ldv, double *C, int ldc,
+                           int nrows, int ncols, hipStream_t s);
+
 // FP64 inversion by blocked Gauss-Jordan with partial pivoting.
 struct GjDesc {
     double *m;        // np x np work (in: A^T padded with identity; out: inverse scrambled)

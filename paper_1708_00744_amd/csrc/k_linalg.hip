@@ -73,6 +73,42 @@ __global__ __launch_bounds__(kThreads) void k_flush_mfma(const FlushDesc<T> *__r
 }
 
 // ---------------------------------------------------------------------------
+// C[0:nrows, 0:ncols] -= W[:, 0:kslots] V[0:kslots, :] in FP64 on matrix cores,
+// tiled over rows and columns (64 x 64 per workgroup) so that one matrix
+// fills the GPU.  W fragments beyond kslots are taken as zero; V rows beyond
+// kslots (up to KP) must be zero.  nrows and ncols multiples of 64.
+// ---------------------------------------------------------------------------
+template <int KP>
+__global__ __launch_bounds__(kThreads) void k_gemm_sub(const double *__restrict__ W, int ldw, int kslots,
+                                                       const double *__restrict__ V, int ldv, double *C, int ldc,
+                                                       int ncb) {
+    __shared__ __attribute__((aligned(16))) double lds[KP * Phase3Cfg<double, KP>::LDV];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int r0 = (b / ncb) * kRowBlock, c0 = (b % ncb) * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double wa[KP / 4];
+    const double *wr = W + (size_t)(r0 + 16 * wave + (lane & 15)) * ldw + (lane >> 4);
+#pragma unroll
+    for (int s = 0; s < KP / 4; ++s) wa[s] = 4 * s + (lane >> 4) < kslots ? -wr[4 * s] : 0.0;
+    rowblock_plus_wv<double, KP>(C + (size_t)r0 * ldc + c0, ldc, 64, V + c0, ldv, wa, lds);
+}
+
+hipError_t launch_gemm_sub(const double *W, int ldw, int kslots, const double *V, int ldv, double *C, int ldc,
+                           int nrows, int ncols, hipStream_t s) {
+    if (nrows % kRowBlock || ncols % 64 || kslots < 1) return hipErrorInvalidValue;
+    const int ncb = ncols / 64;
+    const dim3 grid((nrows / kRowBlock) * ncb);
+#define DSU_GS(KPV)                                                                                              \
+    if (kslots <= KPV) {                                                                                         \
+        hipLaunchKernelGGL((k_gemm_sub<KPV>), grid, dim3(kThreads), 0, s, W, ldw, kslots, V, ldv, C, ldc, ncb);  \
+        return hipGetLastError();                                                                                \
+    }
+    DSU_GS(16) DSU_GS(32) DSU_GS(64) DSU_GS(128) DSU_GS(256)
+#undef DSU_GS
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
 // VALU flush: one wave per row of BT, k <= KMAX slots in registers.
 // ---------------------------------------------------------------------------
 template <typename T>

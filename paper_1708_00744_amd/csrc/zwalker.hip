@@ -246,39 +246,21 @@ __global__ __launch_bounds__(kThreads) void k_zflush_w(ZWalkerDev w, int np, int
     }
 }
 
-// Real embedding of the flush's complex operands, for the FP64 matrix-core
-// flush kernel (k_flush_mfma on BT read as real rows of 2 np values: each
-// complex entry is two adjacent doubles).  For slot j and column k, with
-// U[j][k] = a + i b, Vg[j][k] = c + i d and C^{-1}[j][l] = al + i be:
-//   Uh[2j][2k] = a,  Uh[2j][2k+1] = -b,  Uh[2j+1][2k] = b,  Uh[2j+1][2k+1] = a
-//   Vh[2j][2k] = c,  Vh[2j][2k+1] =  d,  Vh[2j+1][2k] = -d, Vh[2j+1][2k+1] = c
-//   Ch[2j][2l] = al, Ch[2j][2l+1] = -be, Ch[2j+1][2l] = be, Ch[2j+1][2l+1] = al
-// so that (interleaved BT row) . Uh[2j], . Uh[2j+1] are the real and imaginary
-// parts of BT[i] . U[j]; Y' Ch^T the parts of W = Y' C^{-T}; and W Vh the
-// parts of W Vg -- the four real products of each complex one, the slots
-// beyond 2k zero.  idx_h[2j] = idx[j] (the real part takes E), idx_h[2j+1] = -1.
-__global__ void k_zembed(ZWalkerDev w, double *uh, double *vh, double *ch, int *idx_h, int np, int k, int kp2,
-                         int ldh) {
-    const int r = blockIdx.y;  // embedded slot row, 0 .. kp2-1
+// Real embedding of the rank-k update BT -= W Vg for the FP64 matrix cores.
+// Read as real matrices (each complex entry two adjacent doubles), BT is
+// np x 2np and W np x 2k; with Vg[j][c] = x + i y,
+//   Vh[2j][2c] = x,  Vh[2j][2c+1] = y,  Vh[2j+1][2c] = -y,  Vh[2j+1][2c+1] = x
+// the real product W Vh is W Vg: each complex product as its four real
+// products.  Rows 2k .. kp2-1 of Vh are zero.
+__global__ void k_zembed_v(ZWalkerDev w, double *vh, int np, int k) {
+    const int r = blockIdx.y;  // embedded slot row
     const int j = r >> 1, odd = r & 1;
     const bool live = j < k;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < np; c += gridDim.x * blockDim.x) {
-        const zc uu = live ? w.u[(size_t)j * np + c] : make_double2(0.0, 0.0);
-        const zc vv = live ? w.vg[(size_t)j * np + c] : make_double2(0.0, 0.0);
-        double *ur = uh + (size_t)r * 2 * np + 2 * c, *vr = vh + (size_t)r * 2 * np + 2 * c;
-        ur[0] = odd ? uu.y : uu.x;
-        ur[1] = odd ? uu.x : -uu.y;
-        vr[0] = odd ? -vv.y : vv.x;
-        vr[1] = odd ? vv.x : vv.y;
-    }
-    if (blockIdx.x == 0) {
-        for (int l = threadIdx.x; l < kp2 / 2; l += blockDim.x) {
-            const zc cc = (live && l < k) ? w.cinv[(size_t)j * w.ldc + l] : make_double2(0.0, 0.0);
-            double *cr = ch + (size_t)r * ldh + 2 * l;
-            cr[0] = odd ? cc.y : cc.x;
-            cr[1] = odd ? cc.x : -cc.y;
-        }
-        if (threadIdx.x == 0) idx_h[r] = (live && !odd) ? w.idx[j] : -1;
+        const zc v = live ? w.vg[(size_t)j * np + c] : make_double2(0.0, 0.0);
+        double *vr = vh + (size_t)r * 2 * np + 2 * c;
+        vr[0] = odd ? -v.y : v.x;
+        vr[1] = odd ? v.x : v.y;
     }
 }
 
@@ -399,11 +381,9 @@ using namespace dsu;
 
 struct dsu_zwalker {
     int n = 0, np = 0, K = 0, kp = 0, policy = 0;
-    // real embedding of the flush operands (k_zembed) and its descriptor, for
-    // delays whose embedded width 2k fits the matrix-core flush (<= 256)
-    double *uh = nullptr, *vh = nullptr, *ch = nullptr;
-    int *idx_h = nullptr;
-    FlushDesc<double> *fdesc = nullptr;
+    // real embedding of the stale rows for the matrix-core rank-k update
+    // (k_zembed_v), for delays whose embedded width 2k is at most 256
+    double *vh = nullptr;
     int kp2 = 0;
     int flush_mode = DSU_FLUSH_AUTO;
     hipStream_t stream = nullptr;
@@ -433,8 +413,7 @@ static void zwalker_free(dsu_zwalker *w) {
     for (void *p : {(void *)w->wd.bt, (void *)w->wd.u, (void *)w->wd.vg, (void *)w->wd.a, (void *)w->wd.phi,
                     (void *)w->wd.cinv, (void *)w->wd.dots, (void *)w->wd.t, (void *)w->wd.ratio, (void *)w->wd.idx,
                     (void *)w->wd.counter, (void *)w->wd.w, (void *)w->wd.fcol, (void *)w->wd.piv,
-                    (void *)w->wd.stat, (void *)w->wd.status, (void *)w->inv_tmp, (void *)w->uh, (void *)w->vh,
-                    (void *)w->ch, (void *)w->idx_h, (void *)w->fdesc})
+                    (void *)w->wd.stat, (void *)w->wd.status, (void *)w->inv_tmp, (void *)w->vh})
         dfree(p);
     if (w->ratio_h) (void)hipHostFree(w->ratio_h);
     if (w->row_stage) (void)hipHostFree(w->row_stage);
@@ -469,20 +448,20 @@ static int zwalker_recompute(dsu_zwalker *w, double *logabs, double *phase) {
 static int zwalker_flush(dsu_zwalker *w) {
     const int k = w->k, np = w->np, kp = w->kp;
     if (k > 0) {
-        const bool mfma = w->uh && 2 * k <= 256 &&
+        // W = (BT U^T - E) C^{-T}, row by row (vector ALUs); then BT -= W Vg:
+        // on the matrix cores through the real embedding when its width fits
+        // (2k <= 256), else as a complex product on the vector ALUs
+        hipLaunchKernelGGL(k_zflush_w, dim3(np / 4), dim3(kThreads), 0, w->stream, w->wd, np, k);
+        HIPCHK(hipGetLastError());
+        const bool mfma = w->vh && 2 * k <= w->kp2 &&
                           (w->flush_mode == DSU_FLUSH_MFMA || (w->flush_mode == DSU_FLUSH_AUTO && k > 2));
         if (mfma) {
-            // the fused matrix-core flush on the real embedding: Y = BT U^T,
-            // W = (Y - E) C^{-T}, BT -= W Vg, four real products per complex one
             const int bx = np >= 256 ? np / 256 : 1;
-            hipLaunchKernelGGL(k_zembed, dim3(bx, w->kp2), dim3(256), 0, w->stream, w->wd, w->uh, w->vh, w->ch,
-                               w->idx_h, np, k, w->kp2, w->kp2);
+            hipLaunchKernelGGL(k_zembed_v, dim3(bx, kpad(2 * k)), dim3(256), 0, w->stream, w->wd, w->vh, np, k);
             HIPCHK(hipGetLastError());
-            HIPCHK(launch_flush<double>(w->fdesc, 1, w->n, np, 2 * k, 0, w->stream, 2 * np));
+            HIPCHK(launch_gemm_sub(reinterpret_cast<const double *>(w->wd.w), 2 * w->wd.ldc, 2 * k, w->vh, 2 * np,
+                                   reinterpret_cast<double *>(w->wd.bt), 2 * np, np, 2 * np, w->stream));
         } else {
-            // W = (BT U^T - E) C^{-T}, row by row; then BT -= W Vg (vector ALUs)
-            hipLaunchKernelGGL(k_zflush_w, dim3(np / 4), dim3(kThreads), 0, w->stream, w->wd, np, k);
-            HIPCHK(hipGetLastError());
             HIPCHK((zgemm<false, true>(w->wd.w, w->wd.ldc, w->wd.vg, np, w->wd.bt, np, np, np, k, w->stream)));
         }
     }
@@ -542,21 +521,9 @@ extern "C" int dsu_zwalker_create(int32_t n, int32_t k_delay, int32_t policy, co
     TRY(dalloc(&w->wd.piv, np));
     TRY(dalloc(&w->wd.stat, 3));
     TRY(dalloc(&w->wd.status, 1));
-    // embedded operands: 2 kp slots (capped at the matrix-core flush's 256)
+    // embedded stale rows: 2 kp slots (capped at 256, the widest matrix-core update)
     w->kp2 = std::min<int>(256, kpad(std::min<int>(2 * (int)kp, 256)));
-    TRY(dalloc(&w->uh, (size_t)w->kp2 * 2 * np));
     TRY(dalloc(&w->vh, (size_t)w->kp2 * 2 * np));
-    TRY(dalloc(&w->ch, (size_t)w->kp2 * w->kp2));
-    TRY(dalloc(&w->idx_h, (size_t)w->kp2));
-    TRY(dalloc(&w->fdesc, 1));
-    {
-        const FlushDesc<double> fd{reinterpret_cast<double *>(w->wd.bt), w->uh, w->vh, w->ch, w->idx_h, w->kp2};
-        if (hipMemcpy(w->fdesc, &fd, sizeof(fd), hipMemcpyHostToDevice) != hipSuccess) {
-            zwalker_free(w);
-            delete w;
-            return fail(DSU_EDEVICE, "descriptor upload failed");
-        }
-    }
     w->wd.ldc = (int)kp + 1;
     // coherent: the host watches the completion tag while the kernel runs
     if (hipHostMalloc((void **)&w->ratio_h, 3 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
