@@ -200,6 +200,15 @@ def headline(args, cache):
     roof["flops_per_launch"] = flops
     roof["bytes_per_launch"] = bytes_
     per_ms = sorted(1e3 * x for x in per)
+    # repeated runs of the same length (each with its share of periodic
+    # recomputes and the watchdog), after the timed region: run-to-run spread
+    runs = [moves / dt]
+    for _ in range(args.repeats - 1):
+        b.sync()
+        t1 = time.perf_counter()
+        b.sweep(args.steps)
+        b.sync()
+        runs.append(moves / (time.perf_counter() - t1))
     # ratio accuracy against the FP64 oracle at the end of a recompute interval:
     # run to the last sweep before the next periodic recompute and record that
     # sweep's ratios and decisions for the first walkers (the oracle replays
@@ -227,6 +236,10 @@ def headline(args, cache):
     out = {
         "moves_per_s": moves / dt, "ms_per_step": 1e3 * dt / args.steps, "K": K, "sigma": sigma,
         "sweep_ms": {"median": per_ms[len(per_ms) // 2], "min": per_ms[0], "max": per_ms[-1]},
+        "runs_moves_per_s": {"runs": len(runs), "median": float(np.median(runs)), "min": float(min(runs)),
+                             "max": float(max(runs)),
+                             "protocol": "the timed run (value) and %d more runs of the same length after it"
+                                         % (len(runs) - 1)},
         "accepted_moves_per_s": None,
         "acceptance": acc, "setup_s": setup_s,
         "burn_in": {"sweeps": BURN_SWEEPS, "sigma": BURN_SIGMA, "precision": "fp64", "acceptance": acc_burn,
@@ -796,6 +809,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="runs of --steps sweeps for the run-to-run spread (the first is the timed one)")
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", default=None, choices=sorted(EXTRA_LEGS),
