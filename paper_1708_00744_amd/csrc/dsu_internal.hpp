@@ -116,9 +116,8 @@ hipError_t launch_gemm_sub(const double *W, int ldw, int kslots, const double *V
 struct GjDesc {
     double *m;        // np x np work (in: A^T padded with identity; out: inverse scrambled)
     double *m2;       // np x np: the other buffer of the ping-pong trailing update
-    double *panel;    // np x nb
-    double *w;        // np x nb
-    double *q;        // nb x np
+    double *panel;    // np x nb: the panel's columns, column-major (factored in place)
+    double *w;        // np x nb: a column group's update (E - S), column-major
     int *piv;         // n pivots
     int *perm;        // np final column permutation
     int *rowsrc;      // np: the panel's row interchanges, composed (row i <- row rowsrc[i])

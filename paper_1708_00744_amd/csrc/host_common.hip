@@ -64,22 +64,24 @@ static int gj_panel_width(int n) { return n >= 512 ? 64 : (n >= 64 ? 32 : 16); }
 
 size_t GjWork::bytes_per(int np_, int n) {
     const size_t nb_ = gj_panel_width(n);
-    return (size_t)np_ * np_ * 8 * 2 + (size_t)np_ * nb_ * 8 * 3 + (size_t)np_ * 12 + 128;
+    return (size_t)np_ * np_ * 8 * 2 + (size_t)np_ * nb_ * 8 * 2 + (size_t)np_ * 12 + 128;
 }
 
 // Pieces of the workspace in carve order (bytes, each 256-byte aligned).
-static void gj_pieces(int g, int np, int nb, size_t out[15]) {
+static constexpr int kGjPieces = 14;
+static void gj_pieces(int g, int np, int nb, size_t out[kGjPieces]) {
     const size_t np2 = (size_t)np * np;
     const size_t d = sizeof(double), i = sizeof(int);
-    const size_t v[15] = {np2 * g * d,          np2 * g * d,      (size_t)np * nb * g * d, (size_t)np * nb * g * d,
-                          (size_t)np * nb * g * d, (size_t)g * d, (size_t)np * g * i,      (size_t)np * g * i,
-                          (size_t)np * g * i,   (size_t)g * i,     (size_t)g * i,           (size_t)g * d,
-                          sizeof(GjDesc) * g,   sizeof(GjDesc) * g, sizeof(double *) * g};
-    for (int k = 0; k < 15; ++k) out[k] = (v[k] + 255) & ~(size_t)255;
+    const size_t v[kGjPieces] = {np2 * g * d,          np2 * g * d,        (size_t)np * nb * g * d,
+                                 (size_t)np * nb * g * d, (size_t)g * d,   (size_t)np * g * i,
+                                 (size_t)np * g * i,   (size_t)np * g * i, (size_t)g * i,
+                                 (size_t)g * i,        (size_t)g * d,      sizeof(GjDesc) * g,
+                                 sizeof(GjDesc) * g,   sizeof(double *) * g};
+    for (int k = 0; k < kGjPieces; ++k) out[k] = (v[k] + 255) & ~(size_t)255;
 }
 
 size_t GjWork::block_bytes(int groups, int np_, int n) {
-    size_t p[15], b = 0;
+    size_t p[kGjPieces], b = 0;
     gj_pieces(groups, np_, gj_panel_width(n), p);
     for (size_t x : p) b += x;
     return b;
@@ -91,14 +93,15 @@ int GjWork::alloc(int groups, int np_, int n, void *block) {
     nb = gj_panel_width(n);
     owned = block == nullptr;
     const size_t np2 = (size_t)np * np;
-    void **dst[15] = {(void **)&m,    (void **)&m2,     (void **)&panel, (void **)&w,      (void **)&q,
-                      (void **)&logdet, (void **)&piv, (void **)&perm,  (void **)&rowsrc, (void **)&sign,
-                      (void **)&status, (void **)&pmax, (void **)&gdesc, (void **)&gdesc_b, (void **)&mptr};
-    size_t p[15];
+    void **dst[kGjPieces] = {(void **)&m,      (void **)&m2,    (void **)&panel, (void **)&w,
+                             (void **)&logdet, (void **)&piv,   (void **)&perm,  (void **)&rowsrc,
+                             (void **)&sign,   (void **)&status, (void **)&pmax, (void **)&gdesc,
+                             (void **)&gdesc_b, (void **)&mptr};
+    size_t p[kGjPieces];
     gj_pieces(g, np, nb, p);
     char *c = static_cast<char *>(block);
     if (c) HIPCHK(hipMemset(c, 0, block_bytes(groups, np_, n)));
-    for (int k = 0; k < 15; ++k) {
+    for (int k = 0; k < kGjPieces; ++k) {
         if (c) {
             *dst[k] = c;
             c += p[k];
@@ -109,9 +112,10 @@ int GjWork::alloc(int groups, int np_, int n, void *block) {
     std::vector<GjDesc> ga(g), gb(g);
     std::vector<double *> mp(g);
     for (int i = 0; i < g; ++i) {
-        ga[i] = GjDesc{m + np2 * i, m2 + np2 * i, panel + (size_t)np * nb * i, w + (size_t)np * nb * i,
-                       q + (size_t)np * nb * i, piv + (size_t)np * i, perm + (size_t)np * i, rowsrc + (size_t)np * i,
-                       logdet + i, sign + i, status + i, pmax + i};
+        ga[i] = GjDesc{m + np2 * i,           m2 + np2 * i,       panel + (size_t)np * nb * i,
+                       w + (size_t)np * nb * i, piv + (size_t)np * i, perm + (size_t)np * i,
+                       rowsrc + (size_t)np * i, logdet + i,         sign + i,
+                       status + i,              pmax + i};
         gb[i] = ga[i];
         std::swap(gb[i].m, gb[i].m2);
         mp[i] = ga[i].m;
@@ -124,11 +128,11 @@ int GjWork::alloc(int groups, int np_, int n, void *block) {
 
 void GjWork::release() {
     if (owned)
-        for (void *p : {(void *)m, (void *)m2, (void *)panel, (void *)w, (void *)q, (void *)logdet, (void *)piv,
+        for (void *p : {(void *)m, (void *)m2, (void *)panel, (void *)w, (void *)logdet, (void *)piv,
                         (void *)perm, (void *)rowsrc, (void *)sign, (void *)status, (void *)gdesc, (void *)gdesc_b,
                         (void *)mptr, (void *)pmax})
             dfree(p);
-    m = m2 = panel = w = q = logdet = pmax = nullptr;
+    m = m2 = panel = w = logdet = pmax = nullptr;
     piv = perm = rowsrc = sign = status = nullptr;
     gdesc = gdesc_b = nullptr;
     mptr = nullptr;

@@ -42,7 +42,7 @@ inline size_t elem_size(int prec) { return prec == DSU_FP64 ? sizeof(double) : s
 // Workspace of the blocked Gauss-Jordan inversion for `g` matrices at once.
 struct GjWork {
     int g = 0, np = 0, nb = 32;
-    double *m = nullptr, *m2 = nullptr, *panel = nullptr, *w = nullptr, *q = nullptr, *logdet = nullptr,
+    double *m = nullptr, *m2 = nullptr, *panel = nullptr, *w = nullptr, *logdet = nullptr,
            *pmax = nullptr;
     int *piv = nullptr, *perm = nullptr, *rowsrc = nullptr, *sign = nullptr, *status = nullptr;
     GjDesc *gdesc = nullptr;   // set A: m = first buffer (the input, see mptr)

@@ -313,12 +313,6 @@ __global__ __launch_bounds__(DecideCfg<KP>::threads) void k_window_decide(const 
     }
 }
 
-// Calls f(integral_constant<int, I>) for I = 0, 1, ... in order.
-template <int... I, typename F>
-__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &&f) {
-    (f(std::integral_constant<int, I>{}), ...);
-}
-
 // The same decisions for windows of up to 128 slots as an in-place
 // Gauss-Jordan sweep over G in slot order, pivoting only on accepted slots:
 // before slot a is decided, G[a][a] has had every earlier accepted slot

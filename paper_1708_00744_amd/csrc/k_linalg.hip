@@ -279,11 +279,6 @@ __global__ __launch_bounds__(kThreads) void k_gj_panel(const GjDesc *__restrict_
         }
         __syncthreads();
     }
-    // W = E_R - T (np x nb row-major), zero columns beyond the panel width.
-    for (int v = tid; v < np * nb; v += kThreads) {
-        const int i = v / nb, j = v % nb;
-        g.w[v] = j < w ? ((i == k0 + j ? 1.0 : 0.0) - P[(size_t)j * np + i]) : 0.0;
-    }
 }
 
 // The panel's row interchanges, composed: rowsrc[i] = the row of M whose
@@ -316,90 +311,128 @@ __global__ __launch_bounds__(kThreads) void k_gj_rowsrc(const GjDesc *__restrict
         for (int i = threadIdx.x; i < np; i += kThreads) g.rowsrc[i] = s_rs[i];
 }
 
-// Q[j][c] = (swapped M)[k0 + j][c] = M[rowsrc[k0 + j]][c] for the non-panel
-// columns, 0 in the panel's columns and for j >= w (nb rows).
-__global__ __launch_bounds__(kThreads) void k_gj_qgather(const GjDesc *__restrict__ descs, int np, int nb, int k0,
-                                                         int w) {
-    const GjDesc g = descs[blockIdx.y];
-    const int c = blockIdx.x * kThreads + threadIdx.x;
-    if (c >= np) return;
-    const bool panel = c >= k0 && c < k0 + w;
-    for (int j = 0; j < nb; ++j)
-        g.q[(size_t)j * np + c] = (j < w && !panel) ? g.m[(size_t)g.rowsrc[k0 + j] * np + c] : 0.0;
-}
-
 // Trailing update with the row interchanges folded in, into the other buffer:
 //     m2[i][c] = m[rowsrc[i]][c] - sum_j W[i][j] Q[j][c]     (c outside the panel)
 //     m2[i][c] = T[i][c - k0]                                 (the panel's columns)
 // One workgroup per 64 rows (wave w: rows 16w..16w+15, KP/4 W fragments in
-// registers), Q staged in LDS by 64-column chunks, the next chunk's source
-// rows loaded before the current chunk's products.  FP64 16x16x4 matrix cores.
+// registers), FP64 16x16x4 matrix cores, the columns in chunks of CW = 32
+// (two 16-wide tiles):
+//  * Q chunks go global -> LDS directly (no registers), double-buffered in two
+//    arrays the compiler can tell apart, so the next chunk's copy stays in
+//    flight while the current chunk's products read the other array;
+//  * two accumulator sets serve even and odd chunks: while one set runs a
+//    chunk's products, the other is stored (the previous chunk's results) and
+//    reloaded with the next chunk's source rows, so every global access has a
+//    chunk of products to complete in before the barrier that waits for it.
 template <int KP>
-__global__ __launch_bounds__(kThreads) void k_gj_update(const GjDesc *__restrict__ descs, int np, int nblk, int k0,
+__global__ __launch_bounds__(kThreads, 3) void k_gj_update(const GjDesc *__restrict__ descs, int np, int nblk, int k0,
                                                         int w) {
-    constexpr int CW = 64, LDQ = CW + 8;  // +64 B row pad
-    __shared__ __attribute__((aligned(16))) double q_lds[KP * LDQ];
+    constexpr int CW = 32, NT = CW / 16;
+    constexpr int PIECES = KP * CW / 2;         // 16-byte pieces of one Q chunk
+    constexpr int IPW = PIECES / kThreads;      // direct copies per wave per chunk (64 pieces each)
+    static_assert(IPW >= 1 && IPW * kThreads == PIECES, "copy split");
+    __shared__ __attribute__((aligned(16))) double q_even[KP * CW];
+    __shared__ __attribute__((aligned(16))) double q_odd[KP * CW];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int d = b / nblk, r0 = (b % nblk) * kRowBlock;
     const GjDesc g = descs[d];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
     DSU_GLOBAL const double *msrc = gmem(g.m);
     DSU_GLOBAL double *mdst = gmem(g.m2);
-    DSU_GLOBAL const double *qg = gmem(g.q);
+    // -W = T - E_R from the factored panel T (column-major), zero beyond its width
     double wa[KP / 4];
     {
-        DSU_GLOBAL const double *wr = gmem(g.w) + (size_t)(r0 + 16 * wave + lr) * KP + lk;
+        const int ra = r0 + 16 * wave + lr;
+        DSU_GLOBAL const double *tp = gmem(g.panel) + ra;
 #pragma unroll
-        for (int s = 0; s < KP / 4; ++s) wa[s] = -wr[4 * s];
+        for (int s = 0; s < KP / 4; ++s) {
+            const int j = 4 * s + lk;
+            wa[s] = j < w ? tp[(size_t)j * np] - (ra == k0 + j ? 1.0 : 0.0) : 0.0;
+        }
     }
-    // result rows of this lane (FP64 tile layout: row (lane / 16) + 4 i)
+    // Q row j = row k0 + j after the interchanges = M[rowsrc[k0 + j]] (rows
+    // j >= w meet zero columns of W; the panel's own columns of the result
+    // are replaced below).  This lane's copy pieces: piece p = (wave * IPW +
+    // i) * 64 + lane lands at LDS byte 16 p, i.e. Q row p / (CW / 2), columns
+    // 2 (p % (CW / 2)) + {0, 1} of the chunk
+    size_t qoff[IPW];
+#pragma unroll
+    for (int i = 0; i < IPW; ++i) {
+        const int p = (wave * IPW + i) * 64 + lane;
+        qoff[i] = (size_t)g.rowsrc[k0 + p / (CW / 2)] * np + 2 * (p % (CW / 2));
+    }
+    auto copy_q = [&](int c0, double *dstl) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < IPW; ++i)
+            __builtin_amdgcn_global_load_lds((const DSU_GLOBAL void *)(msrc + qoff[i] + c0),
+                                             (__attribute__((address_space(3))) void *)(dstl + (wave * IPW + i) * 128),
+                                             16, 0, 0);
+    };
+    // result rows of this lane (FP64 tile layout: row (lane / 16) + 4 i), column lr of each tile
     int row[4];
     DSU_GLOBAL const double *src[4];
+    DSU_GLOBAL double *dst[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         row[i] = r0 + 16 * wave + Mma<double>::row0(lane) + i * Mma<double>::row_step;
         src[i] = msrc + (size_t)g.rowsrc[row[i]] * np + lr;
+        dst[i] = mdst + (size_t)row[i] * np + lr;
     }
-    double pre[CW / 16][4];
+    Mma<double>::acc_t acc_e[NT], acc_o[NT];
+    copy_q(0, q_even);
 #pragma unroll
-    for (int t = 0; t < CW / 16; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) pre[t][i] = src[i][16 * t];
-    for (int c0 = 0; c0 < np; c0 += CW) {
-        for (int v = tid; v < KP * (CW / 2); v += kThreads) {
-            const int r = v / (CW / 2), cc = (v % (CW / 2)) * 2;
-            typedef double d2 __attribute__((ext_vector_type(2)));
-            *reinterpret_cast<d2 *>(q_lds + r * LDQ + cc) =
-                *reinterpret_cast<DSU_GLOBAL const d2 *>(qg + (size_t)r * np + c0 + cc);
-        }
-        Mma<double>::acc_t acc[CW / 16];
-#pragma unroll
-        for (int t = 0; t < CW / 16; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[t][i] = pre[t][i];
-        if (c0 + CW < np) {
-#pragma unroll
-            for (int t = 0; t < CW / 16; ++t)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) pre[t][i] = src[i][c0 + CW + 16 * t];
-        }
+        for (int i = 0; i < 4; ++i) acc_e[t][i] = src[i][16 * t];
+    // chunk c0 runs its products on `cur` (loaded with its source rows) and Q
+    // in q_cur; `oth` holds chunk c0 - CW's results (c0 > 0), is stored, and
+    // takes chunk c0 + CW's source rows (the last chunk re-reads its own rows,
+    // so the load is unconditional)
+    auto chunk = [&](int c0, const double *q_cur, double *q_nxt, Mma<double>::acc_t (&cur)[NT],
+                     Mma<double>::acc_t (&oth)[NT]) __attribute__((always_inline)) {
+        // chunk c0's Q is in q_cur (the barrier waits for this wave's copies,
+        // and with them for everything issued before); every wave is done
+        // reading q_nxt
         __syncthreads();
+        if (c0 > 0)
 #pragma unroll
-        for (int s = 0; s < KP / 4; ++s) {
-            const double *bp = q_lds + (4 * s + lk) * LDQ + lr;
+            for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int t = 0; t < CW / 16; ++t) acc[t] = Mma<double>::mma(wa[s], bp[16 * t], acc[t]);
-        }
+                for (int i = 0; i < 4; ++i) dst[i][c0 - CW + 16 * t] = oth[t][i];
+        const int c1 = c0 + CW;
+        if (c1 < np) copy_q(c1, q_nxt);
+        const int cl = c1 < np ? c1 : c0;
 #pragma unroll
-        for (int t = 0; t < CW / 16; ++t) {
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) oth[t][i] = src[i][cl + 16 * t];
+        __builtin_amdgcn_sched_barrier(0);  // stores and next loads issued before the products
+        const double *qb = q_cur + lk * CW + lr;
+#pragma unroll
+        for (int s = 0; s < KP / 4; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) cur[t] = Mma<double>::mma(wa[s], qb[4 * s * CW + 16 * t], cur[t]);
+    };
+    // np is a multiple of 2 CW = 64: chunks come in pairs, and the loop body
+    // is straight-line code over fixed register sets
+    for (int c0 = 0; c0 < np; c0 += 2 * CW) {
+        chunk(c0, q_even, q_odd, acc_e, acc_o);
+        chunk(c0 + CW, q_odd, q_even, acc_o, acc_e);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dst[i][np - CW + 16 * t] = acc_o[t][i];
+    // The panel's columns: the lane that stored each of them overwrites it with
+    // the factored panel (same thread, same address: program order holds).
+    for (int c0 = k0 - k0 % CW; c0 < k0 + w; c0 += CW)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
             const int c = c0 + 16 * t + lr;
-            const bool panel = c >= k0 && c < k0 + w;
+            if (c >= k0 && c < k0 + w)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                mdst[(size_t)row[i] * np + c] = panel ? g.panel[(size_t)(c - k0) * np + row[i]] : acc[t][i];
+                for (int i = 0; i < 4; ++i) dst[i][c - lr] = g.panel[(size_t)(c - k0) * np + row[i]];
         }
-        __syncthreads();
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -529,60 +562,174 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_sub(const GjDesc *__restrict_
     }
 }
 
+// Register-resident form of the group step above: thread t owns rows
+// t + 1024 r (r < RPT) of the group's WS columns in registers, so a group can
+// be WS = 32 / RPT columns wide where the LDS form holds 4 (np = 4096).  Per
+// column two barriers: one for the waves' pivot candidates, one for the
+// pivot row and the old row k, which their owners publish in LDS.  Same
+// arithmetic, in the same order, as k_gj_sub.
+template <int WS, int RPT>
+__global__ __launch_bounds__(kGjThreads) void k_gj_subr(const GjDesc *__restrict__ descs, int n, int np, int k0,
+                                                        int j0, int ws) {
+    __shared__ double s_v[kGjThreads / 64];
+    __shared__ int s_i[kGjThreads / 64];
+    __shared__ double s_prow[WS], s_krow[WS];
+    const GjDesc g = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *P = g.panel + (size_t)j0 * np;
+    double sv[RPT][WS];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int i = tid + kGjThreads * r;
+#pragma unroll
+        for (int j = 0; j < WS; ++j) sv[r][j] = (i < np && j < ws) ? P[(size_t)j * np + i] : 0.0;
+    }
+    double logdet = 0.0, pmax = 0.0;
+    int sign = 1, status = 0;
+    if (!(k0 == 0 && j0 == 0)) {
+        pmax = *g.pmax;
+        if (tid == 0) {
+            logdet = *g.logdet;
+            sign = *g.sign;
+            status = *g.status;
+        }
+    }
+    // fully unrolled (every register index fixed); columns past ws skipped
+    auto step = [&](auto kk_c) __attribute__((always_inline)) {
+        constexpr int kk = decltype(kk_c)::value;
+        if (kk >= ws) return;  // uniform
+        const int k = k0 + j0 + kk;
+        double best = -1.0;
+        int bi = n;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = tid + kGjThreads * r;
+            if (i >= k && i < n) argmax_combine(best, bi, fabs(sv[r][kk]), i);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v2 = __shfl_xor(best, o, 64);
+            const int i2 = __shfl_xor(bi, o, 64);
+            argmax_combine(best, bi, v2, i2);
+        }
+        if (lane == 0) { s_v[wave] = best; s_i[wave] = bi; }
+        __syncthreads();
+        double bv = s_v[0];
+        int p = s_i[0];
+#pragma unroll
+        for (int q = 1; q < kGjThreads / 64; ++q) argmax_combine(bv, p, s_v[q], s_i[q]);
+        pmax = fmax(pmax, bv);
+        if (!(bv > (double)n * 2.220446049250313e-16 * pmax)) {
+            status = -3;
+            p = k;
+        }
+        // the owners publish the pivot row (old row p) and the old row k
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = tid + kGjThreads * r;
+            if (i == p)
+#pragma unroll
+                for (int j = 0; j < WS; ++j) s_prow[j] = sv[r][j];
+            if (i == k)
+#pragma unroll
+                for (int j = 0; j < WS; ++j) s_krow[j] = sv[r][j];
+        }
+        __syncthreads();
+        const double d = s_prow[kk];
+        const double dinv = d != 0.0 ? 1.0 / d : 0.0;
+        if (tid == 0) {
+            g.piv[k] = p;
+            if (d != 0.0) logdet += log(fabs(d));
+            if (p != k) sign = -sign;
+            if (d < 0.0) sign = -sign;
+        }
+        // row k = the scaled pivot row, row p = old row k eliminated, every
+        // other row eliminated in place
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = tid + kGjThreads * r;
+            if (i >= np) continue;
+            const bool is_k = i == k, is_p = i == p && p != k;
+            const double f = is_p ? s_krow[kk] : sv[r][kk];
+#pragma unroll
+            for (int j = 0; j < WS; ++j) {
+                const double rpj = j == kk ? dinv : s_prow[j] * dinv;
+                const double cur = is_p ? s_krow[j] : sv[r][j];
+                sv[r][j] = is_k ? rpj : (j == kk ? -f * dinv : cur - f * rpj);
+            }
+        }
+    };
+    static_for(std::make_integer_sequence<int, WS>{}, step);
+    if (tid == 0) {
+        *g.logdet = logdet;
+        *g.pmax = pmax;
+        *g.sign = sign;
+        *g.status = status;
+    }
+    // the factored columns, and the group's update (E - S) column-major in w
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int i = tid + kGjThreads * r;
+        if (i >= np) continue;
+#pragma unroll
+        for (int j = 0; j < WS; ++j) {
+            if (j >= ws) continue;
+            P[(size_t)j * np + i] = sv[r][j];
+            g.w[(size_t)j * np + i] = (i == k0 + j0 + j ? 1.0 : 0.0) - sv[r][j];
+        }
+    }
+}
+
 // The group's swaps, then P_c -= (E - S) Q_c, for every other panel column c.
+// The swaps k <-> piv[k] (k = k0 + j0 .. + ws - 1, in order) compose into a
+// permutation of at most 2 ws rows: row r ends up holding the old row
+// s_0(s_1(...s_{ws-1}(r))), traced by one thread per involved row, so the
+// values move in one parallel round of loads and stores.
 __global__ __launch_bounds__(kThreads) void k_gj_sub_apply(const GjDesc *__restrict__ descs, int np, int k0, int j0,
                                                            int ws) {
     const int c = blockIdx.x;
     if (c >= j0 && c < j0 + ws) return;
-    __shared__ double q[64];
+    __shared__ int s_k[64], s_p[64];
+    __shared__ double s_val[128];
     const GjDesc g = descs[blockIdx.y];
     double *col = g.panel + (size_t)c * np;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        for (int kk = 0; kk < ws; ++kk) {
-            const int k = k0 + j0 + kk, p = g.piv[k];
-            if (p != k) {
-                const double t = col[k];
-                col[k] = col[p];
-                col[p] = t;
-            }
-        }
-        for (int kk = 0; kk < ws; ++kk) q[kk] = col[k0 + j0 + kk];
+    if (tid < ws) {
+        s_k[tid] = k0 + j0 + tid;
+        s_p[tid] = g.piv[k0 + j0 + tid];
     }
     __syncthreads();
+    int r = -1;
+    if (tid < 2 * ws) {
+        r = tid < ws ? s_k[tid] : s_p[tid - ws];
+        int x = r;
+        for (int kk = ws - 1; kk >= 0; --kk) x = x == s_k[kk] ? s_p[kk] : (x == s_p[kk] ? s_k[kk] : x);
+        s_val[tid] = col[x];
+    }
+    __syncthreads();
+    if (r >= 0) col[r] = s_val[tid];  // rows named twice receive the same value
+    __syncthreads();
+    // q[kk] = the value at row k0 + j0 + kk after the swaps = s_val[kk]
     for (int i = tid; i < np; i += kThreads) {
         double a = col[i];
-        for (int kk = 0; kk < ws; ++kk) a -= g.w[(size_t)kk * np + i] * q[kk];
+        for (int kk = 0; kk < ws; ++kk) a -= g.w[(size_t)kk * np + i] * s_val[kk];
         col[i] = a;
     }
 }
 
-// W = E_R - P, np x nb row-major, zero beyond the panel width (64-row tiles).
-__global__ __launch_bounds__(kThreads) void k_gj_wout(const GjDesc *__restrict__ descs, int np, int nb, int k0, int w) {
-    __shared__ double t[64][65];
-    const GjDesc g = descs[blockIdx.y];
-    const int r0 = blockIdx.x * 64, tid = threadIdx.x;
-    for (int v = tid; v < 64 * w; v += kThreads) {
-        const int j = v / 64, i = v % 64;
-        t[i][j] = g.panel[(size_t)j * np + r0 + i];
-    }
-    __syncthreads();
-    for (int v = tid; v < 64 * nb; v += kThreads) {
-        const int i = v / nb, j = v % nb, r = r0 + i;
-        g.w[(size_t)r * nb + j] = j < w ? ((r == k0 + j ? 1.0 : 0.0) - t[i][j]) : 0.0;
-    }
-}
-
-template <int WS, int NPMAX>
+template <int WS, int NPMAX, bool REG = false>
 static void launch_gj_panel2(const GjDesc *descs_dev, int ndesc, int n, int np, int nb, int k0, int w, hipStream_t s) {
     hipLaunchKernelGGL(k_gj_gather, dim3(np / 64, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, w);
     for (int j0 = 0; j0 < w; j0 += WS) {
         const int ws = j0 + WS <= w ? WS : w - j0;
-        hipLaunchKernelGGL((k_gj_sub<WS, NPMAX>), dim3(ndesc), dim3(kGjThreads), 0, s, descs_dev, n, np, k0, j0, ws);
+        if constexpr (REG)
+            hipLaunchKernelGGL((k_gj_subr<WS, NPMAX / kGjThreads>), dim3(ndesc), dim3(kGjThreads), 0, s, descs_dev, n,
+                               np, k0, j0, ws);
+        else
+            hipLaunchKernelGGL((k_gj_sub<WS, NPMAX>), dim3(ndesc), dim3(kGjThreads), 0, s, descs_dev, n, np, k0, j0,
+                               ws);
         if (w > ws)
             hipLaunchKernelGGL(k_gj_sub_apply, dim3(w, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, j0, ws);
     }
-    hipLaunchKernelGGL(k_gj_wout, dim3(np / 64, ndesc), dim3(kThreads), 0, s, descs_dev, np, nb, k0, w);
 }
 
 // Final column permutation: idx = identity, then for k = n-1..0 swap idx[k], idx[piv[k]].
@@ -601,23 +748,22 @@ __global__ void k_gj_perm(const GjDesc *__restrict__ descs, int n, int np) {
 hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc, int n, int np, int nb,
                             hipStream_t s, const GjDesc **final_set) {
     if (nb != 16 && nb != 32 && nb != 64) return hipErrorInvalidValue;
+    if (np % 64) return hipErrorInvalidValue;  // the trailing update takes column chunks in pairs of 32
     const GjDesc *cur = set_a, *nxt = set_b;
     const int nblk = np / kRowBlock;
     for (int k0 = 0; k0 < n; k0 += nb) {
         const int k1 = k0 + nb < n ? k0 + nb : n;
-        // factor the panel: group width such that the group's np x WS columns fill at most 128 KB of LDS
-        if (np <= 512) launch_gj_panel2<16, 512>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
-        else if (np <= 1024) launch_gj_panel2<16, 1024>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
-        else if (np <= 2048) launch_gj_panel2<8, 2048>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
-        else if (np <= 4096) launch_gj_panel2<4, 4096>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
+        // factor the panel: groups of 32 / 16 / 8 columns in registers up to np = 4096 (32 doubles a
+        // thread), then 2 columns in LDS up to 8192, else one column at a time
+        if (np <= 1024) launch_gj_panel2<32, 1024, true>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
+        else if (np <= 2048) launch_gj_panel2<16, 2048, true>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
+        else if (np <= 4096) launch_gj_panel2<8, 4096, true>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
         else if (np <= 8192) launch_gj_panel2<2, 8192>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
         else hipLaunchKernelGGL(k_gj_panel, dim3(ndesc), dim3(kThreads), 0, s, cur, n, np, nb, k0, k1);
         // row interchanges, pivot rows, then the trailing update into the other buffer
         const int in_lds = np <= 8192;  // 32 KB of dynamic LDS at most
         hipLaunchKernelGGL(k_gj_rowsrc, dim3(ndesc), dim3(kThreads), in_lds ? np * sizeof(int) : 0, s, cur, np, k0,
                            k1, in_lds);
-        hipLaunchKernelGGL(k_gj_qgather, dim3((np + kThreads - 1) / kThreads, ndesc), dim3(kThreads), 0, s, cur, np,
-                           nb, k0, k1 - k0);
         const dim3 grid(ndesc * nblk);
         if (nb == 16) hipLaunchKernelGGL((k_gj_update<16>), grid, dim3(kThreads), 0, s, cur, np, nblk, k0, k1 - k0);
         else if (nb == 32) hipLaunchKernelGGL((k_gj_update<32>), grid, dim3(kThreads), 0, s, cur, np, nblk, k0, k1 - k0);

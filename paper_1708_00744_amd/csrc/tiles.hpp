@@ -4,7 +4,17 @@
 #pragma once
 #include "dsu_internal.hpp"
 
+#include <type_traits>
+#include <utility>
+
 namespace dsu {
+
+// Calls f(integral_constant<int, I>) for I = 0, 1, ... in order (compile-time
+// unrolling that keeps register-array indices fixed).
+template <int... I, typename F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &&f) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
 
 template <typename T> struct alignas(16) V16 { T v[16 / sizeof(T)]; };
 

@@ -132,6 +132,7 @@ def burn_in_fp64(n, pos, seeds, wids, sweeps, sigma, K=128):
             b.stats()["accepted"].sum()) / (len(seeds) * n * sweeps)
 
 
+@pytest.mark.timeout(400)  # LAPACK and oracle checks at N = 4096 on the host take most of it
 def test_c4_accuracy_over_recompute_interval():
     """N = 4096, two walkers, K = 128, FP32 with FP64 recompute every 20
     sweeps, sigma for acceptance 0.99, from starts equilibrated by 10 FP64
