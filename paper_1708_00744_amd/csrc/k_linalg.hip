@@ -314,40 +314,42 @@ __global__ __launch_bounds__(kThreads) void k_gj_rowsrc(const GjDesc *__restrict
 // Trailing update with the row interchanges folded in, into the other buffer:
 //     m2[i][c] = m[rowsrc[i]][c] - sum_j W[i][j] Q[j][c]     (c outside the panel)
 //     m2[i][c] = T[i][c - k0]                                 (the panel's columns)
-// One workgroup per 64 rows (wave w: rows 16w..16w+15, KP/4 W fragments in
-// registers), FP64 16x16x4 matrix cores, the columns in chunks of CW = 32
-// (two 16-wide tiles):
+// One workgroup per 64 RT rows (wave w: RT row tiles of 16 rows, their W
+// fragments in registers), FP64 16x16x4 matrix cores, the columns in chunks
+// of CW = 32 or 64 (two or four 16-wide tiles):
 //  * Q chunks go global -> LDS directly (no registers), double-buffered in two
 //    arrays the compiler can tell apart, so the next chunk's copy stays in
-//    flight while the current chunk's products read the other array;
+//    flight while the current chunk's products read the other array; each B
+//    operand read from LDS serves the wave's RT row tiles;
 //  * two accumulator sets serve even and odd chunks: while one set runs a
 //    chunk's products, the other is stored (the previous chunk's results) and
 //    reloaded with the next chunk's source rows, so every global access has a
 //    chunk of products to complete in before the barrier that waits for it.
-template <int KP>
-__global__ __launch_bounds__(kThreads, 3) void k_gj_update(const GjDesc *__restrict__ descs, int np, int nblk, int k0,
+template <int KP, int RT, int CW>
+__global__ __launch_bounds__(kThreads, 2) void k_gj_update(const GjDesc *__restrict__ descs, int np, int nblk, int k0,
                                                         int w) {
-    constexpr int CW = 32, NT = CW / 16;
+    constexpr int NT = CW / 16, RB = 64 * RT;
     constexpr int PIECES = KP * CW / 2;         // 16-byte pieces of one Q chunk
     constexpr int IPW = PIECES / kThreads;      // direct copies per wave per chunk (64 pieces each)
     static_assert(IPW >= 1 && IPW * kThreads == PIECES, "copy split");
     __shared__ __attribute__((aligned(16))) double q_even[KP * CW];
     __shared__ __attribute__((aligned(16))) double q_odd[KP * CW];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int d = b / nblk, r0 = (b % nblk) * kRowBlock;
+    const int d = b / nblk, r0 = (b % nblk) * RB;
     const GjDesc g = descs[d];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
     DSU_GLOBAL const double *msrc = gmem(g.m);
     DSU_GLOBAL double *mdst = gmem(g.m2);
     // -W = T - E_R from the factored panel T (column-major), zero beyond its width
-    double wa[KP / 4];
-    {
-        const int ra = r0 + 16 * wave + lr;
+    double wa[RT][KP / 4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int ra = r0 + 16 * (RT * wave + rt) + lr;
         DSU_GLOBAL const double *tp = gmem(g.panel) + ra;
 #pragma unroll
         for (int s = 0; s < KP / 4; ++s) {
             const int j = 4 * s + lk;
-            wa[s] = j < w ? tp[(size_t)j * np] - (ra == k0 + j ? 1.0 : 0.0) : 0.0;
+            wa[rt][s] = j < w ? tp[(size_t)j * np] - (ra == k0 + j ? 1.0 : 0.0) : 0.0;
         }
     }
     // Q row j = row k0 + j after the interchanges = M[rowsrc[k0 + j]] (rows
@@ -369,60 +371,75 @@ __global__ __launch_bounds__(kThreads, 3) void k_gj_update(const GjDesc *__restr
                                              16, 0, 0);
     };
     // result rows of this lane (FP64 tile layout: row (lane / 16) + 4 i), column lr of each tile
-    int row[4];
-    DSU_GLOBAL const double *src[4];
-    DSU_GLOBAL double *dst[4];
+    int row[RT][4];
+    DSU_GLOBAL const double *src[RT][4];
+    DSU_GLOBAL double *dst[RT][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        row[i] = r0 + 16 * wave + Mma<double>::row0(lane) + i * Mma<double>::row_step;
-        src[i] = msrc + (size_t)g.rowsrc[row[i]] * np + lr;
-        dst[i] = mdst + (size_t)row[i] * np + lr;
-    }
-    Mma<double>::acc_t acc_e[NT], acc_o[NT];
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            row[rt][i] = r0 + 16 * (RT * wave + rt) + Mma<double>::row0(lane) + i * Mma<double>::row_step;
+            src[rt][i] = msrc + (size_t)g.rowsrc[row[rt][i]] * np + lr;
+            dst[rt][i] = mdst + (size_t)row[rt][i] * np + lr;
+        }
+    typedef Mma<double>::acc_t acc_set[RT][NT];
+    acc_set acc_e, acc_o;
     copy_q(0, q_even);
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc_e[t][i] = src[i][16 * t];
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc_e[rt][t][i] = src[rt][i][16 * t];
     // chunk c0 runs its products on `cur` (loaded with its source rows) and Q
     // in q_cur; `oth` holds chunk c0 - CW's results (c0 > 0), is stored, and
     // takes chunk c0 + CW's source rows (the last chunk re-reads its own rows,
     // so the load is unconditional)
-    auto chunk = [&](int c0, const double *q_cur, double *q_nxt, Mma<double>::acc_t (&cur)[NT],
-                     Mma<double>::acc_t (&oth)[NT]) __attribute__((always_inline)) {
+    auto chunk = [&](int c0, const double *q_cur, double *q_nxt, acc_set &cur, acc_set &oth)
+        __attribute__((always_inline)) {
         // chunk c0's Q is in q_cur (the barrier waits for this wave's copies,
         // and with them for everything issued before); every wave is done
         // reading q_nxt
         __syncthreads();
         if (c0 > 0)
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) dst[i][c0 - CW + 16 * t] = oth[t][i];
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) dst[rt][i][c0 - CW + 16 * t] = oth[rt][t][i];
         const int c1 = c0 + CW;
         if (c1 < np) copy_q(c1, q_nxt);
         const int cl = c1 < np ? c1 : c0;
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) oth[t][i] = src[i][cl + 16 * t];
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) oth[rt][t][i] = src[rt][i][cl + 16 * t];
         __builtin_amdgcn_sched_barrier(0);  // stores and next loads issued before the products
         const double *qb = q_cur + lk * CW + lr;
 #pragma unroll
         for (int s = 0; s < KP / 4; ++s)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) cur[t] = Mma<double>::mma(wa[s], qb[4 * s * CW + 16 * t], cur[t]);
+            for (int t = 0; t < NT; ++t) {
+                const double bq = qb[4 * s * CW + 16 * t];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) cur[rt][t] = Mma<double>::mma(wa[rt][s], bq, cur[rt][t]);
+            }
     };
-    // np is a multiple of 2 CW = 64: chunks come in pairs, and the loop body
-    // is straight-line code over fixed register sets
+    // np is a multiple of 2 CW (the launcher's choice of CW): chunks come in
+    // pairs, and the loop body is straight-line code over fixed register sets
     for (int c0 = 0; c0 < np; c0 += 2 * CW) {
         chunk(c0, q_even, q_odd, acc_e, acc_o);
         chunk(c0 + CW, q_odd, q_even, acc_o, acc_e);
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dst[i][np - CW + 16 * t] = acc_o[t][i];
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dst[rt][i][np - CW + 16 * t] = acc_o[rt][t][i];
     // The panel's columns: the lane that stored each of them overwrites it with
     // the factored panel (same thread, same address: program order holds).
     for (int c0 = k0 - k0 % CW; c0 < k0 + w; c0 += CW)
@@ -431,7 +448,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_gj_update(const GjDesc *__restr
             const int c = c0 + 16 * t + lr;
             if (c >= k0 && c < k0 + w)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) dst[i][c - lr] = g.panel[(size_t)(c - k0) * np + row[i]];
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        dst[rt][i][c - lr] = g.panel[(size_t)(c - k0) * np + row[rt][i]];
         }
 }
 
@@ -716,6 +736,15 @@ __global__ __launch_bounds__(kThreads) void k_gj_sub_apply(const GjDesc *__restr
     }
 }
 
+template <int RT, int CW>
+static void launch_gj_update(const GjDesc *descs_dev, int ndesc, int np, int nb, int k0, int w, hipStream_t s) {
+    const int nblk = np / (64 * RT);
+    const dim3 grid(ndesc * nblk);
+    if (nb == 16) hipLaunchKernelGGL((k_gj_update<16, RT, CW>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk, k0, w);
+    else if (nb == 32) hipLaunchKernelGGL((k_gj_update<32, RT, CW>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk, k0, w);
+    else hipLaunchKernelGGL((k_gj_update<64, RT, CW>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk, k0, w);
+}
+
 template <int WS, int NPMAX, bool REG = false>
 static void launch_gj_panel2(const GjDesc *descs_dev, int ndesc, int n, int np, int nb, int k0, int w, hipStream_t s) {
     hipLaunchKernelGGL(k_gj_gather, dim3(np / 64, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, w);
@@ -748,9 +777,8 @@ __global__ void k_gj_perm(const GjDesc *__restrict__ descs, int n, int np) {
 hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc, int n, int np, int nb,
                             hipStream_t s, const GjDesc **final_set) {
     if (nb != 16 && nb != 32 && nb != 64) return hipErrorInvalidValue;
-    if (np % 64) return hipErrorInvalidValue;  // the trailing update takes column chunks in pairs of 32
+    if (np % 64) return hipErrorInvalidValue;  // the trailing update takes column chunks in pairs
     const GjDesc *cur = set_a, *nxt = set_b;
-    const int nblk = np / kRowBlock;
     for (int k0 = 0; k0 < n; k0 += nb) {
         const int k1 = k0 + nb < n ? k0 + nb : n;
         // factor the panel: groups of 32 / 16 / 8 columns in registers up to np = 4096 (32 doubles a
@@ -764,10 +792,13 @@ hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc,
         const int in_lds = np <= 8192;  // 32 KB of dynamic LDS at most
         hipLaunchKernelGGL(k_gj_rowsrc, dim3(ndesc), dim3(kThreads), in_lds ? np * sizeof(int) : 0, s, cur, np, k0,
                            k1, in_lds);
-        const dim3 grid(ndesc * nblk);
-        if (nb == 16) hipLaunchKernelGGL((k_gj_update<16>), grid, dim3(kThreads), 0, s, cur, np, nblk, k0, k1 - k0);
-        else if (nb == 32) hipLaunchKernelGGL((k_gj_update<32>), grid, dim3(kThreads), 0, s, cur, np, nblk, k0, k1 - k0);
-        else hipLaunchKernelGGL((k_gj_update<64>), grid, dim3(kThreads), 0, s, cur, np, nblk, k0, k1 - k0);
+        // column chunks of 64 where the columns pair up in them, else 32
+        // (measured at N = 4096: 64-column chunks 3 % faster; 128-row
+        // workgroups, RT = 2, no faster than 64-row ones)
+        if (np % 128 == 0)
+            launch_gj_update<1, 64>(cur, ndesc, np, nb, k0, k1 - k0, s);
+        else
+            launch_gj_update<1, 32>(cur, ndesc, np, nb, k0, k1 - k0, s);
         const GjDesc *t = cur;
         cur = nxt;
         nxt = t;
