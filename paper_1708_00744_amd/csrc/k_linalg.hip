@@ -596,13 +596,24 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_subr(const GjDesc *__restrict
     __shared__ double s_prow[WS], s_krow[WS];
     const GjDesc g = descs[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double *P = g.panel + (size_t)j0 * np;
+    DSU_GLOBAL double *P = gmem(g.panel) + (size_t)j0 * np;
+    DSU_GLOBAL double *Wg = gmem(g.w);
     double sv[RPT][WS];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int i = tid + kGjThreads * r;
 #pragma unroll
-        for (int j = 0; j < WS; ++j) sv[r][j] = (i < np && j < ws) ? P[(size_t)j * np + i] : 0.0;
+        for (int j = 0; j < WS; ++j) sv[r][j] = 0.0;
+        if (i < np) {
+            if (ws == WS) {
+#pragma unroll
+                for (int j = 0; j < WS; ++j) sv[r][j] = P[(size_t)j * np + i];
+            } else {
+#pragma unroll
+                for (int j = 0; j < WS; ++j)
+                    if (j < ws) sv[r][j] = P[(size_t)j * np + i];
+            }
+        }
     }
     double logdet = 0.0, pmax = 0.0;
     int sign = 1, status = 0;
@@ -643,6 +654,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_subr(const GjDesc *__restrict
             p = k;
         }
         // the owners publish the pivot row (old row p) and the old row k
+        // (rows p and k have one owner each: rare, divergent branches)
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int i = tid + kGjThreads * r;
@@ -662,19 +674,44 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_subr(const GjDesc *__restrict
             if (p != k) sign = -sign;
             if (d < 0.0) sign = -sign;
         }
-        // row k = the scaled pivot row, row p = old row k eliminated, every
-        // other row eliminated in place
+        if constexpr (RPT >= 4) {
+            // narrow groups: the scaled pivot row (its own column becomes 1/d)
+            // in registers; every row eliminated in place, then the owners of
+            // rows k and p overwrite theirs: row k = the scaled pivot row, row
+            // p = old row k eliminated
+            double rp[WS];
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int i = tid + kGjThreads * r;
-            if (i >= np) continue;
-            const bool is_k = i == k, is_p = i == p && p != k;
-            const double f = is_p ? s_krow[kk] : sv[r][kk];
+            for (int j = 0; j < WS; ++j) rp[j] = j == kk ? dinv : s_prow[j] * dinv;
 #pragma unroll
-            for (int j = 0; j < WS; ++j) {
-                const double rpj = j == kk ? dinv : s_prow[j] * dinv;
-                const double cur = is_p ? s_krow[j] : sv[r][j];
-                sv[r][j] = is_k ? rpj : (j == kk ? -f * dinv : cur - f * rpj);
+            for (int r = 0; r < RPT; ++r) {
+                const int i = tid + kGjThreads * r;
+                const double f = sv[r][kk];
+#pragma unroll
+                for (int j = 0; j < WS; ++j) sv[r][j] = j == kk ? -f * dinv : sv[r][j] - f * rp[j];
+                if (i == k) {
+#pragma unroll
+                    for (int j = 0; j < WS; ++j) sv[r][j] = rp[j];
+                } else if (i == p) {
+                    const double fk = s_krow[kk];
+#pragma unroll
+                    for (int j = 0; j < WS; ++j) sv[r][j] = j == kk ? -fk * dinv : s_krow[j] - fk * rp[j];
+                }
+            }
+        } else {
+            // wide groups (registers are short): the same values by selects,
+            // the pivot row read from LDS where it is used
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = tid + kGjThreads * r;
+                if (i >= np) continue;
+                const bool is_k = i == k, is_p = i == p && p != k;
+                const double f = is_p ? s_krow[kk] : sv[r][kk];
+#pragma unroll
+                for (int j = 0; j < WS; ++j) {
+                    const double rpj = j == kk ? dinv : s_prow[j] * dinv;
+                    const double cur = is_p ? s_krow[j] : sv[r][j];
+                    sv[r][j] = is_k ? rpj : (j == kk ? -f * dinv : cur - f * rpj);
+                }
             }
         }
     };
@@ -694,7 +731,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_subr(const GjDesc *__restrict
         for (int j = 0; j < WS; ++j) {
             if (j >= ws) continue;
             P[(size_t)j * np + i] = sv[r][j];
-            g.w[(size_t)j * np + i] = (i == k0 + j0 + j ? 1.0 : 0.0) - sv[r][j];
+            Wg[(size_t)j * np + i] = (i == k0 + j0 + j ? 1.0 : 0.0) - sv[r][j];
         }
     }
 }
@@ -703,36 +740,60 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_subr(const GjDesc *__restrict
 // The swaps k <-> piv[k] (k = k0 + j0 .. + ws - 1, in order) compose into a
 // permutation of at most 2 ws rows: row r ends up holding the old row
 // s_0(s_1(...s_{ws-1}(r))), traced by one thread per involved row, so the
-// values move in one parallel round of loads and stores.
+// values move in one parallel round of loads and stores.  A workgroup takes
+// CPB columns, so each element of (E - S) it reads serves CPB of them.
+template <int CPB>
 __global__ __launch_bounds__(kThreads) void k_gj_sub_apply(const GjDesc *__restrict__ descs, int np, int k0, int j0,
-                                                           int ws) {
-    const int c = blockIdx.x;
-    if (c >= j0 && c < j0 + ws) return;
-    __shared__ int s_k[64], s_p[64];
-    __shared__ double s_val[128];
+                                                           int ws, int w) {
+    __shared__ int s_k[64], s_p[64], s_src[128];
+    __shared__ double s_val[CPB][128];
+    const int c0 = blockIdx.x * CPB, tid = threadIdx.x;
+    bool on[CPB], any = false;  // columns of this block that take the update: in the panel, outside the group
+#pragma unroll
+    for (int q = 0; q < CPB; ++q) {
+        on[q] = c0 + q < w && !(c0 + q >= j0 && c0 + q < j0 + ws);
+        any = any || on[q];
+    }
+    if (!any) return;  // uniform
     const GjDesc g = descs[blockIdx.y];
-    double *col = g.panel + (size_t)c * np;
-    const int tid = threadIdx.x;
+    DSU_GLOBAL double *P = gmem(g.panel);
+    DSU_GLOBAL const double *Wg = gmem(g.w);
     if (tid < ws) {
         s_k[tid] = k0 + j0 + tid;
         s_p[tid] = g.piv[k0 + j0 + tid];
     }
     __syncthreads();
-    int r = -1;
     if (tid < 2 * ws) {
-        r = tid < ws ? s_k[tid] : s_p[tid - ws];
-        int x = r;
+        int x = tid < ws ? s_k[tid] : s_p[tid - ws];
         for (int kk = ws - 1; kk >= 0; --kk) x = x == s_k[kk] ? s_p[kk] : (x == s_p[kk] ? s_k[kk] : x);
-        s_val[tid] = col[x];
+        s_src[tid] = x;
     }
     __syncthreads();
-    if (r >= 0) col[r] = s_val[tid];  // rows named twice receive the same value
+    for (int v = tid; v < CPB * 2 * ws; v += kThreads) {
+        const int q = v / (2 * ws), t = v % (2 * ws);
+        if (on[q]) s_val[q][t] = P[(size_t)(c0 + q) * np + s_src[t]];
+    }
     __syncthreads();
-    // q[kk] = the value at row k0 + j0 + kk after the swaps = s_val[kk]
+    for (int v = tid; v < CPB * 2 * ws; v += kThreads) {
+        const int q = v / (2 * ws), t = v % (2 * ws);
+        const int r = t < ws ? s_k[t] : s_p[t - ws];
+        if (on[q]) P[(size_t)(c0 + q) * np + r] = s_val[q][t];  // rows named twice receive the same value
+    }
+    __syncthreads();
+    // q[kk] = the value at row k0 + j0 + kk after the swaps = s_val[.][kk]
     for (int i = tid; i < np; i += kThreads) {
-        double a = col[i];
-        for (int kk = 0; kk < ws; ++kk) a -= g.w[(size_t)kk * np + i] * s_val[kk];
-        col[i] = a;
+        double a[CPB];
+#pragma unroll
+        for (int q = 0; q < CPB; ++q) a[q] = on[q] ? P[(size_t)(c0 + q) * np + i] : 0.0;
+#pragma unroll 8
+        for (int kk = 0; kk < ws; ++kk) {
+            const double e = Wg[(size_t)kk * np + i];
+#pragma unroll
+            for (int q = 0; q < CPB; ++q) a[q] -= e * s_val[q][kk];
+        }
+#pragma unroll
+        for (int q = 0; q < CPB; ++q)
+            if (on[q]) P[(size_t)(c0 + q) * np + i] = a[q];
     }
 }
 
@@ -756,8 +817,13 @@ static void launch_gj_panel2(const GjDesc *descs_dev, int ndesc, int n, int np, 
         else
             hipLaunchKernelGGL((k_gj_sub<WS, NPMAX>), dim3(ndesc), dim3(kGjThreads), 0, s, descs_dev, n, np, k0, j0,
                                ws);
-        if (w > ws)
-            hipLaunchKernelGGL(k_gj_sub_apply, dim3(w, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, j0, ws);
+        // four columns a workgroup on tall panels (measured faster from
+        // N = 2048), one on short ones (enough workgroups to fill the GPU)
+        if (w > ws && np >= 2048)
+            hipLaunchKernelGGL((k_gj_sub_apply<4>), dim3((w + 3) / 4, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0,
+                               j0, ws, w);
+        else if (w > ws)
+            hipLaunchKernelGGL((k_gj_sub_apply<1>), dim3(w, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, j0, ws, w);
     }
 }
 
