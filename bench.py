@@ -127,6 +127,9 @@ def headline(args, cache):
     setup_s = time.perf_counter() - t0
     b.set_sweep(BURN_SWEEPS)  # the random stream continues after the burn-in sweeps
     b.set_delay(K)
+    tiles = tune.recompute_tiles_for(n, walkers, cache)
+    if tiles:
+        b.set_recompute_tiles(*tiles)
     b.set_residual_watchdog(RESID_SAMPLES, RESID_THRESHOLD)
     b.sweep(args.warmup)
     b.sync()
@@ -246,6 +249,7 @@ def headline(args, cache):
                     "seconds": burn_s},
         "phase_ms_per_sweep": {k: v[1] for k, v in phases.items()},
         "phase_split_from": "one sweep after the timed region, events around every launch",
+        "recompute_tiles": dict(b.recompute_tiles(), source="autotuner" if tiles else "built-in"),
         "roofline": roof, "accuracy": accuracy, "diag": diag, "batch": b,
     }
     out["accepted_moves_per_s"] = out["moves_per_s"] * acc
@@ -274,6 +278,9 @@ def batched_at(n, walkers, cache, steps=2, precision=None, k_curve_ks=()):
     with dsu.Batch(n, pos, [1000 + w for w in range(walkers)], list(range(walkers)), sigma, kmax,
                    precision=precision, box_l=BOX_L) as b:
         b.set_delay(K)
+        tiles = tune.recompute_tiles_for(n, walkers, cache)
+        if tiles:
+            b.set_recompute_tiles(*tiles)
         dt = time_sweeps(b, steps, 1)
         out["moves_per_s"] = walkers * n * steps / dt
         if k_curve_ks:
@@ -294,7 +301,7 @@ def c3_batched(cache, burn, n=512, walkers=512, K=32, sweeps=100, recompute_ever
     on 64 rows; and the FP32 ratios of the last sweep before the first
     recompute against the oracle's FP64 ones on the first 16 walkers."""
     import oracle
-    from paper_1708_00744_amd import dsu
+    from paper_1708_00744_amd import dsu, tune
     sigma = sigma_or_default(n, 0.99, cache)
     seeds, wids = [1000 + w for w in range(walkers)], list(range(walkers))
     pos = batch_positions(n, walkers)
@@ -306,6 +313,9 @@ def c3_batched(cache, burn, n=512, walkers=512, K=32, sweeps=100, recompute_ever
                    recompute_every=recompute_every) as b:
         if burn:
             b.set_sweep(2)
+        tiles = tune.recompute_tiles_for(n, walkers, cache)
+        if tiles:
+            b.set_recompute_tiles(*tiles)
         b.set_residual_watchdog(16, 1e-3)
         per, right, drift, left_end = [], [], [], []
         last = b.accuracy()["drift"]

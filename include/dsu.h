@@ -340,6 +340,17 @@ int dsu_batch_residual_noalloc(dsu_batch *b, int32_t samples, double *right_host
  * residual's kernels (one pass over every inverse) and one synchronisation
  * per sweep. */
 int dsu_batch_set_residual_watchdog(dsu_batch *b, int32_t samples, double threshold);
+/* Blocking of the FP64 Gauss-Jordan recompute (Sec. III's direct
+ * calculation; the paper leaves such parameters to an autotuner, Sec. II):
+ * panel = columns factored per pass over the matrix (16, 32 or 64), chunk =
+ * columns of the trailing update per step (32, or 64 when n rounded up to a
+ * multiple of 64 is a multiple of 128), apply_columns = panel columns one
+ * workgroup updates after each group of pivots (1 or 4).  0 keeps the
+ * built-in choice for this n.  Results agree to FP64 rounding whatever the
+ * choice.  Waits for the batch's stream; DSU_EINVAL for other values. */
+int dsu_batch_set_recompute_tiles(dsu_batch *b, int32_t panel, int32_t chunk, int32_t apply_columns);
+/* The blocking in use (any output may be NULL). */
+int dsu_batch_get_recompute_tiles(dsu_batch *b, int32_t *panel, int32_t *chunk, int32_t *apply_columns);
 /* Accuracy record, per determinant d (any pointer may be NULL):
  * residual_out[d] = the sampled right residual after the latest sweep run
  * with the residual watchdog on (before any recompute it triggered; 0 before

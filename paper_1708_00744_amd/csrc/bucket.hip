@@ -837,6 +837,33 @@ extern "C" int dsu_batch_set_residual_watchdog(dsu_batch *b, int32_t samples, do
     return DSU_OK;
 }
 
+extern "C" int dsu_batch_set_recompute_tiles(dsu_batch *b, int32_t panel, int32_t chunk, int32_t apply_columns) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    const int np = b->bk.sh.np;
+    const GjTiles def = gj_tiles_default(b->bk.sh.n, np);
+    GjTiles t;
+    t.nb = panel ? panel : def.nb;
+    t.cw = chunk ? chunk : def.cw;
+    t.cpb = apply_columns ? apply_columns : def.cpb;
+    if (t.nb != 16 && t.nb != 32 && t.nb != 64) return fail(DSU_EINVAL, "panel width %d not 0, 16, 32 or 64", panel);
+    if (t.cw != 32 && t.cw != 64) return fail(DSU_EINVAL, "update chunk %d not 0, 32 or 64", chunk);
+    if (t.cw == 64 && np % 128)
+        return fail(DSU_EINVAL, "update chunk 64 needs the padded size (%d) to be a multiple of 128", np);
+    if (t.cpb != 1 && t.cpb != 4) return fail(DSU_EINVAL, "apply columns %d not 0, 1 or 4", apply_columns);
+    HIPCHK(hipStreamSynchronize(b->bk.stream));
+    b->bk.set_recompute_tiles(t);
+    return DSU_OK;
+}
+
+extern "C" int dsu_batch_get_recompute_tiles(dsu_batch *b, int32_t *panel, int32_t *chunk, int32_t *apply_columns) {
+    if (!b) return fail(DSU_EINVAL, "batch is NULL");
+    const GjTiles t = b->bk.recompute_tiles();
+    if (panel) *panel = t.nb;
+    if (chunk) *chunk = t.cw;
+    if (apply_columns) *apply_columns = t.cpb;
+    return DSU_OK;
+}
+
 extern "C" int dsu_batch_accuracy(dsu_batch *b, double *residual_out, double *drift_out,
                                   int64_t *residual_recomputes) {
     if (!b) return fail(DSU_EINVAL, "batch is NULL");

@@ -83,6 +83,9 @@ class Bucket {
     size_t residual_scratch_bytes(int samples) const;
     // Pre-size the descriptor arrays for n members.
     int reserve(int n) { return ensure_capacity(n); }
+    // Blocking of the FP64 recompute (panel width, update chunk, apply columns).
+    GjTiles recompute_tiles() const { return gj_.tiles; }
+    void set_recompute_tiles(const GjTiles &t) { gj_.tiles = t; }
     int harvest_events();
     long long t_count[PH_COUNT] = {0};
     double t_ms[PH_COUNT] = {0};

@@ -133,10 +133,18 @@ struct GjDesc {
 template <typename T> struct RatioFloor;
 template <> struct RatioFloor<double> { static constexpr double value = 1e-12; };
 template <> struct RatioFloor<float> { static constexpr double value = 1e-6; };
+// Blocking of the Gauss-Jordan inversion: panel width nb (16, 32, 64), the
+// trailing update's column chunk cw (32, or 64 when np is a multiple of 128)
+// and the panel columns one apply workgroup takes, cpb (1 or 4).
+struct GjTiles {
+    int nb = 64, cw = 32, cpb = 1;
+};
+GjTiles gj_tiles_default(int n, int np);
 // Two descriptor sets of the same matrices with m and m2 exchanged: panel p
 // reads set (p mod 2)'s m and writes its m2.  *final_set receives the set
-// whose m holds the result (for launch_cast_perm).
-hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc, int n, int np, int nb,
+// whose m holds the result (for launch_cast_perm).  The panel buffers hold
+// 64 columns (any nb fits).
+hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc, int n, int np, const GjTiles &tiles,
                             hipStream_t s, const GjDesc **final_set);
 // BT[i][j] = T(M[i][perm[j]]) for i, j < n, zero padding elsewhere.
 template <typename T>

@@ -60,10 +60,12 @@ int make_stream(void *given, hipStream_t *s, bool *own) {
     return DSU_OK;
 }
 
-static int gj_panel_width(int n) { return n >= 512 ? 64 : (n >= 64 ? 32 : 16); }
+// Panel buffers hold the widest panel (64 columns), so any blocking fits.
+static constexpr int kGjPanelMax = 64;
 
 size_t GjWork::bytes_per(int np_, int n) {
-    const size_t nb_ = gj_panel_width(n);
+    (void)n;
+    const size_t nb_ = kGjPanelMax;
     return (size_t)np_ * np_ * 8 * 2 + (size_t)np_ * nb_ * 8 * 2 + (size_t)np_ * 12 + 128;
 }
 
@@ -82,7 +84,8 @@ static void gj_pieces(int g, int np, int nb, size_t out[kGjPieces]) {
 
 size_t GjWork::block_bytes(int groups, int np_, int n) {
     size_t p[kGjPieces], b = 0;
-    gj_pieces(groups, np_, gj_panel_width(n), p);
+    (void)n;
+    gj_pieces(groups, np_, kGjPanelMax, p);
     for (size_t x : p) b += x;
     return b;
 }
@@ -90,7 +93,8 @@ size_t GjWork::block_bytes(int groups, int np_, int n) {
 int GjWork::alloc(int groups, int np_, int n, void *block) {
     g = groups;
     np = np_;
-    nb = gj_panel_width(n);
+    nb = kGjPanelMax;
+    tiles = gj_tiles_default(n, np_);
     owned = block == nullptr;
     const size_t np2 = (size_t)np * np;
     void **dst[kGjPieces] = {(void **)&m,      (void **)&m2,    (void **)&panel, (void **)&w,

@@ -41,7 +41,8 @@ inline size_t elem_size(int prec) { return prec == DSU_FP64 ? sizeof(double) : s
 
 // Workspace of the blocked Gauss-Jordan inversion for `g` matrices at once.
 struct GjWork {
-    int g = 0, np = 0, nb = 32;
+    int g = 0, np = 0, nb = 64;  // nb: panel columns the buffers hold
+    GjTiles tiles;               // blocking used by invert()
     double *m = nullptr, *m2 = nullptr, *panel = nullptr, *w = nullptr, *logdet = nullptr,
            *pmax = nullptr;
     int *piv = nullptr, *perm = nullptr, *rowsrc = nullptr, *sign = nullptr, *status = nullptr;
@@ -51,7 +52,7 @@ struct GjWork {
     // Invert the first `cnt` matrices (inputs in mptr); returns the descriptor
     // set holding the result.
     hipError_t invert(int cnt, int n, hipStream_t s, const GjDesc **final_set) const {
-        return launch_gj_invert(gdesc, gdesc_b, cnt, n, np, nb, s, final_set);
+        return launch_gj_invert(gdesc, gdesc_b, cnt, n, np, tiles, s, final_set);
     }
     // Allocate for `groups` matrices; with `block` (block_bytes(groups, np_, n)
     // bytes of device memory the caller owns) every buffer is carved from it

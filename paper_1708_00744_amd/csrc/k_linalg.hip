@@ -807,7 +807,8 @@ static void launch_gj_update(const GjDesc *descs_dev, int ndesc, int np, int nb,
 }
 
 template <int WS, int NPMAX, bool REG = false>
-static void launch_gj_panel2(const GjDesc *descs_dev, int ndesc, int n, int np, int nb, int k0, int w, hipStream_t s) {
+static void launch_gj_panel2(const GjDesc *descs_dev, int ndesc, int n, int np, int nb, int k0, int w, int cpb,
+                             hipStream_t s) {
     hipLaunchKernelGGL(k_gj_gather, dim3(np / 64, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, w);
     for (int j0 = 0; j0 < w; j0 += WS) {
         const int ws = j0 + WS <= w ? WS : w - j0;
@@ -817,9 +818,7 @@ static void launch_gj_panel2(const GjDesc *descs_dev, int ndesc, int n, int np, 
         else
             hipLaunchKernelGGL((k_gj_sub<WS, NPMAX>), dim3(ndesc), dim3(kGjThreads), 0, s, descs_dev, n, np, k0, j0,
                                ws);
-        // four columns a workgroup on tall panels (measured faster from
-        // N = 2048), one on short ones (enough workgroups to fill the GPU)
-        if (w > ws && np >= 2048)
+        if (w > ws && cpb == 4)
             hipLaunchKernelGGL((k_gj_sub_apply<4>), dim3((w + 3) / 4, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0,
                                j0, ws, w);
         else if (w > ws)
@@ -840,28 +839,39 @@ __global__ void k_gj_perm(const GjDesc *__restrict__ descs, int n, int np) {
     }
 }
 
-hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc, int n, int np, int nb,
+GjTiles gj_tiles_default(int n, int np) {
+    // measured on MI355X: 64-column panels from N = 512; 64-column update
+    // chunks where np pairs them up (3 % faster than 32 at N = 4096); four
+    // apply columns a workgroup from N = 2048 (one below: enough workgroups)
+    GjTiles t;
+    t.nb = n >= 512 ? 64 : (n >= 64 ? 32 : 16);
+    t.cw = np % 128 == 0 ? 64 : 32;
+    t.cpb = np >= 2048 ? 4 : 1;
+    return t;
+}
+
+hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc, int n, int np, const GjTiles &tiles,
                             hipStream_t s, const GjDesc **final_set) {
+    const int nb = tiles.nb, cw = tiles.cw, cpb = tiles.cpb;
     if (nb != 16 && nb != 32 && nb != 64) return hipErrorInvalidValue;
     if (np % 64) return hipErrorInvalidValue;  // the trailing update takes column chunks in pairs
+    if (!(cw == 32 || (cw == 64 && np % 128 == 0)) || (cpb != 1 && cpb != 4)) return hipErrorInvalidValue;
     const GjDesc *cur = set_a, *nxt = set_b;
     for (int k0 = 0; k0 < n; k0 += nb) {
         const int k1 = k0 + nb < n ? k0 + nb : n;
         // factor the panel: groups of 32 / 16 / 8 columns in registers up to np = 4096 (32 doubles a
         // thread), then 2 columns in LDS up to 8192, else one column at a time
-        if (np <= 1024) launch_gj_panel2<32, 1024, true>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
-        else if (np <= 2048) launch_gj_panel2<16, 2048, true>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
-        else if (np <= 4096) launch_gj_panel2<8, 4096, true>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
-        else if (np <= 8192) launch_gj_panel2<2, 8192>(cur, ndesc, n, np, nb, k0, k1 - k0, s);
+        if (np <= 1024) launch_gj_panel2<32, 1024, true>(cur, ndesc, n, np, nb, k0, k1 - k0, cpb, s);
+        else if (np <= 2048) launch_gj_panel2<16, 2048, true>(cur, ndesc, n, np, nb, k0, k1 - k0, cpb, s);
+        else if (np <= 4096) launch_gj_panel2<8, 4096, true>(cur, ndesc, n, np, nb, k0, k1 - k0, cpb, s);
+        else if (np <= 8192) launch_gj_panel2<2, 8192>(cur, ndesc, n, np, nb, k0, k1 - k0, cpb, s);
         else hipLaunchKernelGGL(k_gj_panel, dim3(ndesc), dim3(kThreads), 0, s, cur, n, np, nb, k0, k1);
         // row interchanges, pivot rows, then the trailing update into the other buffer
         const int in_lds = np <= 8192;  // 32 KB of dynamic LDS at most
         hipLaunchKernelGGL(k_gj_rowsrc, dim3(ndesc), dim3(kThreads), in_lds ? np * sizeof(int) : 0, s, cur, np, k0,
                            k1, in_lds);
-        // column chunks of 64 where the columns pair up in them, else 32
-        // (measured at N = 4096: 64-column chunks 3 % faster; 128-row
-        // workgroups, RT = 2, no faster than 64-row ones)
-        if (np % 128 == 0)
+        // (128-row workgroups, RT = 2, measured no faster than 64-row ones)
+        if (cw == 64)
             launch_gj_update<1, 64>(cur, ndesc, np, nb, k0, k1 - k0, s);
         else
             launch_gj_update<1, 32>(cur, ndesc, np, nb, k0, k1 - k0, s);

@@ -99,6 +99,8 @@ SIGNATURES = {
     "dsu_batch_residual_noalloc": (C.c_int, [_vp, _i32, _pd, _pd]),
     "dsu_batch_set_residual_watchdog": (C.c_int, [_vp, _i32, _dbl]),
     "dsu_batch_accuracy": (C.c_int, [_vp, _pd, _pd, _pi64]),
+    "dsu_batch_set_recompute_tiles": (C.c_int, [_vp, _i32, _i32, _i32]),
+    "dsu_batch_get_recompute_tiles": (C.c_int, [_vp, _pi32, _pi32, _pi32]),
     "dsu_batch_get_inverse": (C.c_int, [_vp, _i32, _pd]),
     "dsu_batch_set_trace": (C.c_int, [_vp, _i32]),
     "dsu_batch_get_trace": (C.c_int, [_vp, _i32, _pd, _pu8]),
@@ -452,6 +454,15 @@ class Batch:
 
     def set_residual_watchdog(self, samples, threshold=1e-3):
         _check(lib().dsu_batch_set_residual_watchdog(self._h, int(samples), float(threshold)))
+
+    def set_recompute_tiles(self, panel=0, chunk=0, apply_columns=0):
+        """Blocking of the FP64 recompute; 0 keeps the built-in choice."""
+        _check(lib().dsu_batch_set_recompute_tiles(self._h, int(panel), int(chunk), int(apply_columns)))
+
+    def recompute_tiles(self):
+        p, c, a = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().dsu_batch_get_recompute_tiles(self._h, C.byref(p), C.byref(c), C.byref(a)))
+        return {"panel": p.value, "chunk": c.value, "apply_columns": a.value}
 
     def accuracy(self):
         """Latest sampled right residual of the residual watchdog, drift of the

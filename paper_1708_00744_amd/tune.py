@@ -3,8 +3,10 @@
 * tune_sigma: Gaussian step sigma that gives a target acceptance for a matrix
   size (bisection on log sigma; acceptance falls monotonically with sigma).
 * tune_delay: the delay K with the highest moves/s for a workload (Sec. III:
-  the optimum K depends on the architecture and the size and "could be
-  chosen automatically via an autotuner").
+  the best K depends on the architecture and the matrix size, and the paper
+  suggests leaving its choice to an autotuner).
+* tune_recompute: the blocking of the FP64 recompute (panel width, update
+  chunk, apply columns per workgroup) with the shortest recompute.
 
 Results are cached in tuning.json next to this file, keyed by workload.
 Run `python -m paper_1708_00744_amd.tune` on the GPU to fill the cache.
@@ -101,12 +103,51 @@ def tune_delay(n, walkers, sigma, candidates=(32, 64, 128, 256), precision=dsu.F
     return best, out
 
 
+def recompute_key(n, walkers, precision):
+    return f"n={n},walkers={walkers},prec={precision}"
+
+
+def recompute_candidates(n):
+    """Blockings of the FP64 recompute worth timing at this n: panel width,
+    update chunk (64 only where the padded size is a multiple of 128) and
+    apply columns per workgroup."""
+    np_ = -(-n // 64) * 64
+    panels = (32, 64) if n >= 64 else (16, 32)
+    chunks = (32, 64) if np_ % 128 == 0 else (32,)
+    return [(p, c, a) for p in panels for c in chunks for a in (1, 4)]
+
+
+def tune_recompute(n, walkers, precision=dsu.FP32_MIXED, reps=2, seed=1000):
+    """Time the batch's FP64 recompute for every candidate blocking; returns the
+    fastest and the seconds per recompute of each."""
+    pos = np.stack([inputs.positions(seed + w, w, n, BOX_L) for w in range(walkers)])
+    out = {}
+    with dsu.Batch(n, pos, [seed + w for w in range(walkers)], list(range(walkers)), 0.001, 32,
+                   precision=precision, box_l=BOX_L) as b:
+        for cand in recompute_candidates(n):
+            b.set_recompute_tiles(*cand)
+            b.recompute()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                b.recompute()
+            out[cand] = (time.perf_counter() - t0) / reps
+    best = min(out, key=out.get)
+    return best, out
+
+
+def recompute_tiles_for(n, walkers, cache=None, precision=dsu.FP32_MIXED):
+    c = cache if cache is not None else load_cache()
+    e = c.get("recompute", {}).get(recompute_key(n, walkers, precision))
+    return tuple(e["best"]) if e else None
+
+
 def main(argv):
     import torch
     torch.cuda.set_device(0)
     c = load_cache()
     out_path = CACHE
-    delay_only = "--delay-only" in argv
+    recompute_only = "--recompute-only" in argv
+    delay_only = "--delay-only" in argv or recompute_only
     for a in argv:
         if a.startswith("--out="):
             out_path = a.split("=", 1)[1]
@@ -118,10 +159,17 @@ def main(argv):
             print(f"sigma n={n} target={t}: sigma={s:.5g} acc={acc:.4f}", flush=True)
         save_cache(c, out_path)
     for n, w in ((4096, 32), (2048, 64), (1024, 256), (512, 512)):
-        s = sigma_for(n, 0.99, c)
-        best, rates = tune_delay(n, w, s)
-        c["delay"][delay_key(n, w, dsu.FP32_MIXED)] = {"best": best, "moves_per_s": {str(k): v for k, v in rates.items()}}
-        print(f"delay n={n} walkers={w}: best K={best} {rates}", flush=True)
+        if not recompute_only:
+            s = sigma_for(n, 0.99, c)
+            best, rates = tune_delay(n, w, s)
+            c["delay"][delay_key(n, w, dsu.FP32_MIXED)] = {"best": best,
+                                                           "moves_per_s": {str(k): v for k, v in rates.items()}}
+            print(f"delay n={n} walkers={w}: best K={best} {rates}", flush=True)
+        best, secs = tune_recompute(n, w)
+        c.setdefault("recompute", {})[recompute_key(n, w, dsu.FP32_MIXED)] = {
+            "best": list(best), "seconds": {",".join(map(str, k)): v for k, v in secs.items()}}
+        print(f"recompute n={n} walkers={w}: best (panel, chunk, apply)={best} "
+              f"{ {k: round(v * 1e3, 2) for k, v in secs.items()} } ms", flush=True)
         save_cache(c, out_path)
 
 

@@ -223,3 +223,51 @@ def test_fp64_recompute_full_size(n):
         if u < ro * ro:
             oracle.sm_accept(ainv, a, e, row, ro)
             cur[e] = rt
+
+
+@pytest.mark.parametrize("n", [1024, 960, 300, 48])
+def test_recompute_tiles_agree(n):
+    """Every blocking the autotuner may pick (panel width, update chunk, apply
+    columns per workgroup) gives the FP64 inverse and log-determinant of the
+    same matrices to FP64 accuracy: sampled rows against LAPACK's inverse
+    within 1e-9 of its largest entry, log|det| within 1e-9, the sign exact.
+    Sizes: np a multiple of 128 (both chunks), 960 (np = 960: chunk 32 only),
+    ragged 300, and 48 (16-column panels)."""
+    require_gpu()
+    from paper_1708_00744_amd import tune
+    walkers, seed = 2, 1000
+    pos = uniform(n, walkers, seed)
+    kv = oracle.pw_kvectors(n)
+    ref = []
+    for d in range(walkers):
+        a = oracle.pw_matrix(kv, L, pos[d, 0])
+        ref.append((np.linalg.inv(a), np.linalg.slogdet(a)))
+    rows = np.random.default_rng(5).choice(n, min(n, 48), replace=False)
+    with dsu.Batch(n, pos, [seed + w for w in range(walkers)], list(range(walkers)), 0.001, 16,
+                   precision=dsu.FP32_MIXED, box_l=L) as b:
+        default = b.recompute_tiles()
+        for cand in tune.recompute_candidates(n):
+            b.set_recompute_tiles(*cand)
+            assert tuple(b.recompute_tiles().values()) == cand
+            b.recompute()
+            st = b.stats()
+            for d in range(walkers):
+                ainv, (s_np, l_np) = ref[d]
+                x = b.inverse(d)  # the FP32 inverse the recompute left: FP32 rounding of the FP64 result
+                err = np.abs(x[rows] - ainv[rows]).max() / np.abs(ainv[rows]).max()
+                assert err < 2e-7, (cand, d, err)
+                assert st["sign"][d] == s_np and abs(st["logdet"][d] - l_np) < 1e-9, (cand, d)
+        b.set_recompute_tiles(0, 0, 0)
+        assert b.recompute_tiles() == default
+
+
+def test_recompute_tiles_arguments():
+    """Blockings outside the kernels' shapes are refused."""
+    require_gpu()
+    pos = uniform(960, 1, 1000)
+    with dsu.Batch(960, pos, [1000], [0], 0.001, 16, precision=dsu.FP32_MIXED, box_l=L) as b:
+        for bad in [(48, 0, 0), (0, 64, 0), (0, 16, 0), (0, 0, 2)]:
+            with pytest.raises(dsu.DsuError):
+                b.set_recompute_tiles(*bad)
+        b.set_recompute_tiles(16, 32, 4)
+        assert b.recompute_tiles() == {"panel": 16, "chunk": 32, "apply_columns": 4}
