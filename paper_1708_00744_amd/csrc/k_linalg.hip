@@ -586,8 +586,8 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_sub(const GjDesc *__restrict_
 // t + 1024 r (r < RPT) of the group's WS columns in registers, so a group can
 // be WS = 32 / RPT columns wide where the LDS form holds 4 (np = 4096).  Per
 // column two barriers: one for the waves' pivot candidates, one for the
-// pivot row and the old row k, which their owners publish in LDS.  Same
-// arithmetic, in the same order, as k_gj_sub.
+// pivot row and the old row k, which their owners publish in LDS.  Every
+// element gets the same operations as in k_gj_sub.
 template <int WS, int RPT>
 __global__ __launch_bounds__(kGjThreads) void k_gj_subr(const GjDesc *__restrict__ descs, int n, int np, int k0,
                                                         int j0, int ws) {
