@@ -139,6 +139,43 @@ __global__ __launch_bounds__(kThreads) void k_window_rows(const DetDesc<T> *__re
             s_s[a][ax][m] = sn;
         }
         __syncthreads();
+        if (cols == kThreads) {
+            // one column per thread (uniform): its plane wave decoded once, the
+            // group's proposals unrolled into independent chains; the same
+            // operations per orbital as below
+            const int c = c_begin + tid;
+            const bool live = c < n;
+            const int4 kv = live ? kvec[c] : make_int4(0, 0, 0, 0);
+            const int mm[3] = {kv.x < 0 ? -kv.x : kv.x, kv.y < 0 ? -kv.y : kv.y, kv.z < 0 ? -kv.z : kv.z};
+            const bool ng[3] = {kv.x < 0, kv.y < 0, kv.z < 0};
+#pragma unroll 4
+            for (int a = 0; a < ga; ++a) {
+                const int ag = a0 + a;
+                T val = T(0), vgv = T(0);
+                if (ag < kw) {
+                    if (live) {
+                        double o = 1.0;
+                        if (kv.w != 0) {
+                            double re = 1.0, im = 0.0;
+#pragma unroll
+                            for (int ax = 0; ax < 3; ++ax) {
+                                const double fc = s_c[a][ax][mm[ax]];
+                                const double fs = ng[ax] ? -s_s[a][ax][mm[ax]] : s_s[a][ax][mm[ax]];
+                                const double t = re * fc - im * fs;
+                                im = re * fs + im * fc;
+                                re = t;
+                            }
+                            o = kv.w == 1 ? re : im;
+                        }
+                        val = T(o);
+                    }
+                    if (copy_vg) vgv = d.bt[(size_t)(e0 + ag) * np + c];
+                }
+                uo[(size_t)ag * np + c] = val;
+                if (copy_vg) vo[(size_t)ag * np + c] = vgv;
+            }
+            continue;
+        }
         for (int v = tid; v < ga * cols; v += kThreads) {
             const int a = v / cols, c = c_begin + v % cols, ag = a0 + a;
             T val = T(0), vgv = T(0);
