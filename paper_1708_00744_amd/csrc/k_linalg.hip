@@ -826,17 +826,30 @@ static void launch_gj_panel2(const GjDesc *descs_dev, int ndesc, int n, int np, 
     }
 }
 
-// Final column permutation: idx = identity, then for k = n-1..0 swap idx[k], idx[piv[k]].
-__global__ void k_gj_perm(const GjDesc *__restrict__ descs, int n, int np) {
+// Final column permutation: idx = identity, then for k = n-1..0 swap idx[k],
+// idx[piv[k]].  The swaps are a serial chain on one thread; it runs over LDS
+// copies of the pivots and the permutation (dynamic LDS: 8 np bytes) when
+// they fit, which the workgroup loads and stores in parallel, else in place.
+__global__ __launch_bounds__(kThreads) void k_gj_perm(const GjDesc *__restrict__ descs, int n, int np, int in_lds) {
+    extern __shared__ int s_pp[];
     const GjDesc g = descs[blockIdx.x];
-    if (threadIdx.x != 0) return;
-    for (int j = 0; j < np; ++j) g.perm[j] = j;
-    for (int k = n - 1; k >= 0; --k) {
-        const int p = g.piv[k];
-        const int t = g.perm[k];
-        g.perm[k] = g.perm[p];
-        g.perm[p] = t;
+    int *perm = in_lds ? s_pp : g.perm;
+    const int *piv = in_lds ? s_pp + np : g.piv;
+    for (int j = threadIdx.x; j < np; j += kThreads) {
+        perm[j] = j;
+        if (in_lds) s_pp[np + j] = j < n ? g.piv[j] : j;
     }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = n - 1; k >= 0; --k) {
+            const int p = piv[k];
+            const int t = perm[k];
+            perm[k] = perm[p];
+            perm[p] = t;
+        }
+    __syncthreads();
+    if (in_lds)
+        for (int j = threadIdx.x; j < np; j += kThreads) g.perm[j] = s_pp[j];
 }
 
 GjTiles gj_tiles_default(int n, int np) {
@@ -879,7 +892,9 @@ hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc,
         cur = nxt;
         nxt = t;
     }
-    hipLaunchKernelGGL(k_gj_perm, dim3(ndesc), dim3(64), 0, s, cur, n, np);
+    const int perm_lds = np <= 8192;  // 64 KB of dynamic LDS at most
+    hipLaunchKernelGGL(k_gj_perm, dim3(ndesc), dim3(kThreads), perm_lds ? (size_t)np * 2 * sizeof(int) : 0, s, cur, n,
+                       np, perm_lds);
     if (final_set) *final_set = cur;
     return hipGetLastError();
 }
@@ -897,25 +912,42 @@ __global__ __launch_bounds__(kThreads) void k_cast_perm(const GjDesc *__restrict
     out[(size_t)i * np + j] = (i < n && j < n) ? T(g.m[(size_t)i * np + g.perm[j]]) : T(0);
 }
 
-// The same with the row staged in LDS first (one row per workgroup): the
-// permuted gather then reads LDS instead of scattered global lines.
+// The same with the row staged in LDS first (one row per workgroup, dynamic
+// LDS of np doubles): the permuted gather then reads LDS instead of scattered
+// global lines; the row comes in with 16-byte loads and leaves four columns a
+// thread (np is a multiple of 64).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cast_perm_row(const GjDesc *__restrict__ gj, T *const *__restrict__ bt,
                                                             int n, int np) {
-    __shared__ double row[8192];
+    extern __shared__ double s_row[];
+    typedef double d2 __attribute__((ext_vector_type(2)));
     const GjDesc g = gj[blockIdx.y];
     T *out = bt[blockIdx.y] + (size_t)blockIdx.x * np;
     const int i = blockIdx.x;
-    const double *src = g.m + (size_t)i * np;
-    for (int j = threadIdx.x; j < np; j += kThreads) row[j] = src[j];
+    const d2 *src = reinterpret_cast<const d2 *>(g.m + (size_t)i * np);
+    for (int j = threadIdx.x; j < np / 2; j += kThreads) reinterpret_cast<d2 *>(s_row)[j] = src[j];
     __syncthreads();
-    for (int j = threadIdx.x; j < np; j += kThreads) out[j] = (i < n && j < n) ? T(row[g.perm[j]]) : T(0);
+    for (int j4 = threadIdx.x; j4 < np / 4; j4 += kThreads) {
+        const int j = 4 * j4;
+        const int4 pv = reinterpret_cast<const int4 *>(g.perm)[j4];
+        const int pj[4] = {pv.x, pv.y, pv.z, pv.w};
+        T v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (i < n && j + e < n) ? T(s_row[pj[e]]) : T(0);
+        if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4 *>(out + j) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+            reinterpret_cast<d2 *>(out + j)[0] = d2{(double)v[0], (double)v[1]};
+            reinterpret_cast<d2 *>(out + j)[1] = d2{(double)v[2], (double)v[3]};
+        }
+    }
 }
 
 template <typename T>
 hipError_t launch_cast_perm(const GjDesc *gj_dev, T *const *bt_dev, int ndesc, int n, int np, hipStream_t s) {
     if (np <= 8192)
-        hipLaunchKernelGGL((k_cast_perm_row<T>), dim3(np, ndesc), dim3(kThreads), 0, s, gj_dev, bt_dev, n, np);
+        hipLaunchKernelGGL((k_cast_perm_row<T>), dim3(np, ndesc), dim3(kThreads), (size_t)np * sizeof(double), s,
+                           gj_dev, bt_dev, n, np);
     else
         hipLaunchKernelGGL((k_cast_perm<T>), dim3((np + kThreads - 1) / kThreads, np, ndesc), dim3(kThreads), 0, s,
                            gj_dev, bt_dev, n, np);
