@@ -35,7 +35,7 @@ BucketShape BucketShape::make(int n, int kmax, int prec) {
 }
 
 // Piece sizes in carve order.
-static constexpr int kPieces = 14;
+static constexpr int kPieces = 15;
 static void pieces(const BucketShape &s, size_t out[kPieces]) {
     const size_t e = elem_size(s.prec), np = s.np, kp = s.kp;
     out[0] = np * np * e;                           // bt
@@ -52,6 +52,7 @@ static void pieces(const BucketShape &s, size_t out[kPieces]) {
     out[11] = kp * np * e;                          // vg2
     out[12] = np * kp * e;                          // y
     out[13] = kp * 4 * 8;                           // prop2
+    out[14] = s.prec == DSU_FP32_MIXED ? kp * kp * 4 : 0;  // cfl32
 }
 
 size_t BucketShape::det_bytes() const {
@@ -85,6 +86,7 @@ DetSlot BucketShape::carve(char *base) const {
     d.vg2 = ptr[11];
     d.y = ptr[12];
     d.prop2 = (double *)ptr[13];
+    d.cfl32 = (float *)ptr[14];
     return d;
 }
 
@@ -186,6 +188,7 @@ template <typename T> static DetDesc<T> to_desc(const DetSlot &s) {
     d.u = (T *)s.u;
     d.vg = (T *)s.vg;
     d.cfl = s.cfl;
+    d.cfl32 = s.cfl32;
     d.cwork = s.cwork;
     d.gwork = s.gwork;
     d.prop = s.prop;

@@ -16,6 +16,7 @@ namespace dsu {
 struct DetSlot {
     void *bt = nullptr, *u = nullptr, *vg = nullptr, *u2 = nullptr, *vg2 = nullptr, *y = nullptr;
     double *cfl = nullptr, *cwork = nullptr, *gwork = nullptr, *prop = nullptr, *pos = nullptr, *prop2 = nullptr;
+    float *cfl32 = nullptr;
     int *idx = nullptr;
     DetState *st = nullptr;
     double *trace_r = nullptr;

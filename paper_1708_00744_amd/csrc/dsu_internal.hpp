@@ -48,6 +48,15 @@ template <> struct Mma<double> {
     }
 };
 
+// Position of C^{-1}[l][j] (window tile KP) in the FP32 copy the streaming
+// flush reads as the B operand of W = Y' C^{-T} on 16x16x4 matrix cores: tile
+// t = l / 16, step s = j / 4; lane (l % 16) + 16 (j % 4) reads steps 4q..4q+3
+// of tile t as one 16-byte vector.
+template <int KP> __host__ __device__ __forceinline__ int cfl32_index(int l, int j) {
+    const int t = l >> 4, s = j >> 2, lane = (l & 15) + 16 * (j & 3);
+    return ((t * (KP / 16) + (s >> 2)) * 64 + lane) * 4 + (s & 3);
+}
+
 // --------------------------------------------------- descriptors (device)
 // One rank-k update target: BT <- BT - ((BT U^T - E) C^T) Vg   (eq. (4),
 // transposed and row-local).  idx[j] = electron of slot j (-1 = unused).
@@ -76,6 +85,8 @@ template <typename T> struct DetDesc {
     T *u;            // kp x np
     T *vg;           // kp x np
     double *cfl;     // kp x kp
+    float *cfl32;    // FP32 batched form, window tiles of 32..128: C^{-1} in FP32, laid out as the
+                     // W product's B operand (cfl32_index), written by the decisions
     double *cwork;   // kp x (kp+1) when the bordered inverse does not fit LDS
     double *gwork;   // kp x (kp+1) when G does not fit LDS
     double *prop;    // kp x 4 : proposed position (x, y, z) and Metropolis uniform

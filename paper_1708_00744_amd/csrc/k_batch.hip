@@ -506,6 +506,16 @@ __global__ __launch_bounds__(256) void k_window_decide_gj(const DetDesc<T> *__re
             const int a = wave * RW + r, b = lane + 64 * h;
             if (b < KP) d.cfl[(size_t)a * kp + b] = (s_ok[a] && s_ok[b]) ? g[r][h] : 0.0;
         }
+    // the FP32 form's streaming flush reads the same matrix in FP32, laid out
+    // as its W product's B operand
+    if constexpr (sizeof(T) == 4 && KP >= 32)
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int h = 0; h < CPL; ++h) {
+                const int a = wave * RW + r, b = lane + 64 * h;
+                if (b < KP) d.cfl32[cfl32_index<KP>(a, b)] = (s_ok[a] && s_ok[b]) ? (float)g[r][h] : 0.0f;
+            }
     for (int a = tid; a < KP; a += 256) d.idx[a] = a < kw ? e0 + a : -1;
     for (int v = tid; v < kw * 3; v += 256) {
         const int a = v / 3, c = v % 3;

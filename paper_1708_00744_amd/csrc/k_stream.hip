@@ -222,13 +222,40 @@ __global__ __launch_bounds__(kThreads) void k_flush_stream(const DetDesc<T> *__r
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kRowBlock32 = 128;
 
+// W = Y' C^{-T} for the wave's 16 rows of a 64-row half (Y' staged in LDS,
+// ldy floats a row), on 16x16x4 matrix cores: the B operand straight from
+// the FP32 copy of C^{-1} the decisions wrote (cfl32_index layout, one
+// 16-byte load per tile and four steps; L2-resident, shared by the
+// determinant's workgroups), so no staging, conversion or barrier.
+template <int KP>
+__device__ __forceinline__ void w_from_y32(const float *ylds, int ldy, const float *__restrict__ c32,
+                                           f32x4 (&wacc)[KP / 16]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t) wacc[t] = f32x4{0, 0, 0, 0};
+    DSU_GLOBAL const f32x4 *cg = (DSU_GLOBAL const f32x4 *)c32 + lane;
+    const float *yrow = ylds + (16 * wave + (lane & 15)) * ldy + (lane >> 4);
+#pragma unroll 2
+    for (int q = 0; q < KP / 16; ++q) {
+        f32x4 b[KP / 16];
+#pragma unroll
+        for (int t = 0; t < KP / 16; ++t) b[t] = cg[(t * (KP / 16) + q) * 64];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float a = yrow[4 * (4 * q + e)];
+#pragma unroll
+            for (int t = 0; t < KP / 16; ++t) wacc[t] = Mma<float>::mma(a, b[t][e], wacc[t]);
+        }
+    }
+}
+
 template <int KP> struct Stream32Cfg {
     static constexpr int CW = KP <= 64 ? 64 : 32, VEC = 4, KH = KP / 2;
     static constexpr int LDVT = KP + 4, LDU = CW + 4, LDY = KP + 4;
     static constexpr int NV = KP * (CW / VEC) / kThreads;
     static constexpr int buf = CW * LDVT + KP * LDU;
     static constexpr int chunk = 2 * buf;
-    static constexpr int wpart = 64 * LDY + WCfg<float, KP>::elems;  // one 64-row half of W at a time
+    static constexpr int wpart = 64 * LDY;  // one 64-row half of Y' at a time
     static constexpr int elems = chunk > wpart ? chunk : wpart;
     static_assert(NV >= 1 && NV * kThreads == KP * (CW / VEC), "staging split");
 };
@@ -284,7 +311,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_flush_stream32(const DetDesc<fl
         }
         __syncthreads();
         f32x4 w[KP / 16];
-        w_from_y<float, KP>(lds, LDY, dd.cfl, kp, kslots, lds + 64 * LDY, w);
+        w_from_y32<KP>(lds, LDY, dd.cfl32, w);
 #pragma unroll
         for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
