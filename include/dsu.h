@@ -342,9 +342,12 @@ int dsu_batch_residual_noalloc(dsu_batch *b, int32_t samples, double *right_host
 int dsu_batch_set_residual_watchdog(dsu_batch *b, int32_t samples, double threshold);
 /* Blocking of the FP64 Gauss-Jordan recompute (Sec. III's direct
  * calculation; the paper leaves such parameters to an autotuner, Sec. II):
- * panel = columns factored per pass over the matrix (16, 32 or 64), chunk =
- * columns of the trailing update per step (32, or 64 when n rounded up to a
- * multiple of 64 is a multiple of 128), apply_columns = panel columns one
+ * panel = columns factored per pass over the matrix (16, 32, 64, or 128 =
+ * two 64-column panels factored one after the other that share one pass;
+ * single 64-column panels where fewer than 128 columns remain or the padded
+ * n exceeds 4096), chunk = columns of the single-panel trailing update per
+ * step (32, or 64 when n rounded up to a multiple of 64 is a multiple of
+ * 128; a pair's update takes 32), apply_columns = panel columns one
  * workgroup updates after each group of pivots (1 or 4).  0 keeps the
  * built-in choice for this n.  Results agree to FP64 rounding whatever the
  * choice.  Waits for the batch's stream; DSU_EINVAL for other values. */

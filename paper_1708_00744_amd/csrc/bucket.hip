@@ -848,7 +848,8 @@ extern "C" int dsu_batch_set_recompute_tiles(dsu_batch *b, int32_t panel, int32_
     t.nb = panel ? panel : def.nb;
     t.cw = chunk ? chunk : def.cw;
     t.cpb = apply_columns ? apply_columns : def.cpb;
-    if (t.nb != 16 && t.nb != 32 && t.nb != 64) return fail(DSU_EINVAL, "panel width %d not 0, 16, 32 or 64", panel);
+    if (t.nb != 16 && t.nb != 32 && t.nb != 64 && t.nb != 128)
+        return fail(DSU_EINVAL, "panel width %d not 0, 16, 32, 64 or 128", panel);
     if (t.cw != 32 && t.cw != 64) return fail(DSU_EINVAL, "update chunk %d not 0, 32 or 64", chunk);
     if (t.cw == 64 && np % 128)
         return fail(DSU_EINVAL, "update chunk 64 needs the padded size (%d) to be a multiple of 128", np);

@@ -136,6 +136,11 @@ struct GjDesc {
     int *sign;        // out
     int *status;      // out: 0 or -3 singular
     double *pmax;     // largest pivot magnitude so far (singularity threshold)
+    // fused panel pairs (two 64-column panels, one rank-128 trailing update)
+    double *panel_b;  // np x 64: the pair's first factored panel, column-major
+    double *q2;       // 64 x np: the second panel's pivot rows after the first panel's update
+    int *rowsrc_b;    // np: the second panel's own row interchanges, composed
+    int *qrow;        // 64: rows of M that hold the first panel's pivot rows
 };
 
 // A ratio whose magnitude is at or below this cannot be accepted: the
@@ -144,9 +149,10 @@ struct GjDesc {
 template <typename T> struct RatioFloor;
 template <> struct RatioFloor<double> { static constexpr double value = 1e-12; };
 template <> struct RatioFloor<float> { static constexpr double value = 1e-6; };
-// Blocking of the Gauss-Jordan inversion: panel width nb (16, 32, 64), the
-// trailing update's column chunk cw (32, or 64 when np is a multiple of 128)
-// and the panel columns one apply workgroup takes, cpb (1 or 4).
+// Blocking of the Gauss-Jordan inversion: panel width nb (16, 32, 64, or 128
+// = 64-column panels factored in pairs that share one rank-128 trailing
+// update), the single-panel update's column chunk cw (32, or 64 when np is a
+// multiple of 128) and the panel columns one apply workgroup takes, cpb (1 or 4).
 struct GjTiles {
     int nb = 64, cw = 32, cpb = 1;
 };
@@ -154,7 +160,7 @@ GjTiles gj_tiles_default(int n, int np);
 // Two descriptor sets of the same matrices with m and m2 exchanged: panel p
 // reads set (p mod 2)'s m and writes its m2.  *final_set receives the set
 // whose m holds the result (for launch_cast_perm).  The panel buffers hold
-// 64 columns (any nb fits).
+// 64 columns (a pair uses panel and panel_b).
 hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc, int n, int np, const GjTiles &tiles,
                             hipStream_t s, const GjDesc **final_set);
 // BT[i][j] = T(M[i][perm[j]]) for i, j < n, zero padding elsewhere.

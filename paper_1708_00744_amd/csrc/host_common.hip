@@ -60,17 +60,18 @@ int make_stream(void *given, hipStream_t *s, bool *own) {
     return DSU_OK;
 }
 
-// Panel buffers hold the widest panel (64 columns), so any blocking fits.
+// Panel buffers hold the widest panel (64 columns), so any blocking fits;
+// a panel pair adds the second panel buffer, its pivot rows and row maps.
 static constexpr int kGjPanelMax = 64;
 
 size_t GjWork::bytes_per(int np_, int n) {
     (void)n;
     const size_t nb_ = kGjPanelMax;
-    return (size_t)np_ * np_ * 8 * 2 + (size_t)np_ * nb_ * 8 * 2 + (size_t)np_ * 12 + 128;
+    return (size_t)np_ * np_ * 8 * 2 + (size_t)np_ * nb_ * 8 * 4 + (size_t)np_ * 16 + nb_ * 4 + 128;
 }
 
 // Pieces of the workspace in carve order (bytes, each 256-byte aligned).
-static constexpr int kGjPieces = 14;
+static constexpr int kGjPieces = 18;
 static void gj_pieces(int g, int np, int nb, size_t out[kGjPieces]) {
     const size_t np2 = (size_t)np * np;
     const size_t d = sizeof(double), i = sizeof(int);
@@ -78,7 +79,8 @@ static void gj_pieces(int g, int np, int nb, size_t out[kGjPieces]) {
                                  (size_t)np * nb * g * d, (size_t)g * d,   (size_t)np * g * i,
                                  (size_t)np * g * i,   (size_t)np * g * i, (size_t)g * i,
                                  (size_t)g * i,        (size_t)g * d,      sizeof(GjDesc) * g,
-                                 sizeof(GjDesc) * g,   sizeof(double *) * g};
+                                 sizeof(GjDesc) * g,   sizeof(double *) * g, (size_t)np * nb * g * d,
+                                 (size_t)np * nb * g * d, (size_t)np * g * i, (size_t)nb * g * i};
     for (int k = 0; k < kGjPieces; ++k) out[k] = (v[k] + 255) & ~(size_t)255;
 }
 
@@ -100,7 +102,8 @@ int GjWork::alloc(int groups, int np_, int n, void *block) {
     void **dst[kGjPieces] = {(void **)&m,      (void **)&m2,    (void **)&panel, (void **)&w,
                              (void **)&logdet, (void **)&piv,   (void **)&perm,  (void **)&rowsrc,
                              (void **)&sign,   (void **)&status, (void **)&pmax, (void **)&gdesc,
-                             (void **)&gdesc_b, (void **)&mptr};
+                             (void **)&gdesc_b, (void **)&mptr, (void **)&panel_b, (void **)&q2,
+                             (void **)&rowsrc_b, (void **)&qrow};
     size_t p[kGjPieces];
     gj_pieces(g, np, nb, p);
     char *c = static_cast<char *>(block);
@@ -119,7 +122,8 @@ int GjWork::alloc(int groups, int np_, int n, void *block) {
         ga[i] = GjDesc{m + np2 * i,           m2 + np2 * i,       panel + (size_t)np * nb * i,
                        w + (size_t)np * nb * i, piv + (size_t)np * i, perm + (size_t)np * i,
                        rowsrc + (size_t)np * i, logdet + i,         sign + i,
-                       status + i,              pmax + i};
+                       status + i,              pmax + i,           panel_b + (size_t)np * nb * i,
+                       q2 + (size_t)np * nb * i, rowsrc_b + (size_t)np * i, qrow + (size_t)nb * i};
         gb[i] = ga[i];
         std::swap(gb[i].m, gb[i].m2);
         mp[i] = ga[i].m;
@@ -134,10 +138,10 @@ void GjWork::release() {
     if (owned)
         for (void *p : {(void *)m, (void *)m2, (void *)panel, (void *)w, (void *)logdet, (void *)piv,
                         (void *)perm, (void *)rowsrc, (void *)sign, (void *)status, (void *)gdesc, (void *)gdesc_b,
-                        (void *)mptr, (void *)pmax})
+                        (void *)mptr, (void *)pmax, (void *)panel_b, (void *)q2, (void *)rowsrc_b, (void *)qrow})
             dfree(p);
-    m = m2 = panel = w = logdet = pmax = nullptr;
-    piv = perm = rowsrc = sign = status = nullptr;
+    m = m2 = panel = w = logdet = pmax = panel_b = q2 = nullptr;
+    piv = perm = rowsrc = sign = status = rowsrc_b = qrow = nullptr;
     gdesc = gdesc_b = nullptr;
     mptr = nullptr;
 }

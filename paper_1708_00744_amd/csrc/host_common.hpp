@@ -46,6 +46,8 @@ struct GjWork {
     double *m = nullptr, *m2 = nullptr, *panel = nullptr, *w = nullptr, *logdet = nullptr,
            *pmax = nullptr;
     int *piv = nullptr, *perm = nullptr, *rowsrc = nullptr, *sign = nullptr, *status = nullptr;
+    double *panel_b = nullptr, *q2 = nullptr;  // panel pairs
+    int *rowsrc_b = nullptr, *qrow = nullptr;
     GjDesc *gdesc = nullptr;   // set A: m = first buffer (the input, see mptr)
     GjDesc *gdesc_b = nullptr; // set B: the buffers exchanged
     double **mptr = nullptr;   // per matrix: the input buffer (set A's m)

@@ -325,13 +325,22 @@ __global__ __launch_bounds__(kThreads) void k_gj_rowsrc(const GjDesc *__restrict
 //    chunk's products, the other is stored (the previous chunk's results) and
 //    reloaded with the next chunk's source rows, so every global access has a
 //    chunk of products to complete in before the barrier that waits for it.
-template <int KP, int RT, int CW>
+// PAIR: two 64-column panels R1 = [k0, k0 + 64) and R2 = [k0 + 64, k0 + 128)
+// in one pass (KP = 128).  With P1, P2 the panels' interchanges, T1, T2 their
+// factored columns and Q1 = (P1 M)[R1], Q2 = (P2 M1)[R2] the pivot rows
+// before each panel's update (M1 = M after the first panel):
+//     m2 = P2 P1 M + P2 (T1 - E1) Q1 + (T2 - E2) Q2
+// outside R1 and R2; rowsrc holds P2 P1, rowsrc_b P2, qrow the rows of M
+// that are Q1, q2 the rows Q2.  R2's columns are T2 (the tail below), R1's
+// are written afterwards by k_gj_pair_fix.
+template <int KP, int RT, int CW, bool PAIR = false>
 __global__ __launch_bounds__(kThreads, 2) void k_gj_update(const GjDesc *__restrict__ descs, int np, int nblk, int k0,
                                                         int w) {
     constexpr int NT = CW / 16, RB = 64 * RT;
     constexpr int PIECES = KP * CW / 2;         // 16-byte pieces of one Q chunk
     constexpr int IPW = PIECES / kThreads;      // direct copies per wave per chunk (64 pieces each)
     static_assert(IPW >= 1 && IPW * kThreads == PIECES, "copy split");
+    static_assert(!PAIR || KP == 128, "a pair is two 64-column panels");
     __shared__ __attribute__((aligned(16))) double q_even[KP * CW];
     __shared__ __attribute__((aligned(16))) double q_odd[KP * CW];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -346,10 +355,23 @@ __global__ __launch_bounds__(kThreads, 2) void k_gj_update(const GjDesc *__restr
     for (int rt = 0; rt < RT; ++rt) {
         const int ra = r0 + 16 * (RT * wave + rt) + lr;
         DSU_GLOBAL const double *tp = gmem(g.panel) + ra;
+        if constexpr (PAIR) {
+            // steps s < 16 are the first panel's columns j < 64 (row P2[ra] of T1 - E1),
+            // the rest the second panel's (row ra of T2 - E2)
+            const int rb = g.rowsrc_b[ra];
+            DSU_GLOBAL const double *tb = gmem(g.panel_b) + rb;
 #pragma unroll
-        for (int s = 0; s < KP / 4; ++s) {
-            const int j = 4 * s + lk;
-            wa[rt][s] = j < w ? tp[(size_t)j * np] - (ra == k0 + j ? 1.0 : 0.0) : 0.0;
+            for (int s = 0; s < KP / 4; ++s) {
+                const int j = 4 * s + lk;
+                wa[rt][s] = s < KP / 8 ? tb[(size_t)j * np] - (rb == k0 + j ? 1.0 : 0.0)
+                                       : tp[(size_t)(j - KP / 2) * np] - (ra == k0 + j ? 1.0 : 0.0);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < KP / 4; ++s) {
+                const int j = 4 * s + lk;
+                wa[rt][s] = j < w ? tp[(size_t)j * np] - (ra == k0 + j ? 1.0 : 0.0) : 0.0;
+            }
         }
     }
     // Q row j = row k0 + j after the interchanges = M[rowsrc[k0 + j]] (rows
@@ -357,16 +379,24 @@ __global__ __launch_bounds__(kThreads, 2) void k_gj_update(const GjDesc *__restr
     // are replaced below).  This lane's copy pieces: piece p = (wave * IPW +
     // i) * 64 + lane lands at LDS byte 16 p, i.e. Q row p / (CW / 2), columns
     // 2 (p % (CW / 2)) + {0, 1} of the chunk
+    // (a pair's Q rows 64.. are the rows of q2)
     size_t qoff[IPW];
+    DSU_GLOBAL const double *qbase[IPW];
 #pragma unroll
     for (int i = 0; i < IPW; ++i) {
-        const int p = (wave * IPW + i) * 64 + lane;
-        qoff[i] = (size_t)g.rowsrc[k0 + p / (CW / 2)] * np + 2 * (p % (CW / 2));
+        const int p = (wave * IPW + i) * 64 + lane, qr = p / (CW / 2);
+        if constexpr (PAIR) {
+            qbase[i] = qr < KP / 2 ? msrc : gmem<const double>(g.q2);
+            qoff[i] = (size_t)(qr < KP / 2 ? g.qrow[qr] : qr - KP / 2) * np + 2 * (p % (CW / 2));
+        } else {
+            qbase[i] = msrc;
+            qoff[i] = (size_t)g.rowsrc[k0 + qr] * np + 2 * (p % (CW / 2));
+        }
     }
     auto copy_q = [&](int c0, double *dstl) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < IPW; ++i)
-            __builtin_amdgcn_global_load_lds((const DSU_GLOBAL void *)(msrc + qoff[i] + c0),
+            __builtin_amdgcn_global_load_lds((const DSU_GLOBAL void *)(qbase[i] + qoff[i] + c0),
                                              (__attribute__((address_space(3))) void *)(dstl + (wave * IPW + i) * 128),
                                              16, 0, 0);
     };
@@ -440,18 +470,20 @@ __global__ __launch_bounds__(kThreads, 2) void k_gj_update(const GjDesc *__restr
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) dst[rt][i][np - CW + 16 * t] = acc_o[rt][t][i];
-    // The panel's columns: the lane that stored each of them overwrites it with
-    // the factored panel (same thread, same address: program order holds).
-    for (int c0 = k0 - k0 % CW; c0 < k0 + w; c0 += CW)
+    // The panel's columns (a pair's second panel): the lane that stored each of
+    // them overwrites it with the factored panel (same thread, same address:
+    // program order holds).
+    const int tk0 = PAIR ? k0 + KP / 2 : k0, tw = PAIR ? KP / 2 : w;
+    for (int c0 = tk0 - tk0 % CW; c0 < tk0 + tw; c0 += CW)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int c = c0 + 16 * t + lr;
-            if (c >= k0 && c < k0 + w)
+            if (c >= tk0 && c < tk0 + tw)
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        dst[rt][i][c - lr] = g.panel[(size_t)(c - k0) * np + row[rt][i]];
+                        dst[rt][i][c - lr] = g.panel[(size_t)(c - tk0) * np + row[rt][i]];
         }
 }
 
@@ -797,6 +829,178 @@ __global__ __launch_bounds__(kThreads) void k_gj_sub_apply(const GjDesc *__restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Panel pairs: the pieces of the fused two-panel step around k_gj_update's
+// PAIR form (same notation: R1, R2, P1, P2, T1, T2, Q1, Q2, M1).
+// ---------------------------------------------------------------------------
+
+// After the first panel: R2's columns of M1 = P1 M + (T1 - E1) Q1 become the
+// second panel, and T1 moves to panel_b.  Rows are independent, so each block
+// rewrites the rows it read.  One block per 64 rows; every global load of a
+// thread is issued before its first store (the stores may alias the loads for
+// all the compiler knows, which would otherwise serialise them).
+constexpr int kPairLoads = 64 * 64 / kThreads;  // elements of a 64 x 64 tile per thread
+
+__global__ __launch_bounds__(kThreads) void k_gj_pair_slab(const GjDesc *__restrict__ descs, int np, int k0) {
+    __shared__ double s_t[64][64];  // (T1 - E1)[r0 + i][l] at s_t[l][i]
+    __shared__ double s_q[64][64];  // Q1[l][R2 column j] at s_q[l][j]
+    const GjDesc g = descs[blockIdx.y];
+    const int r0 = blockIdx.x * 64, tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+    DSU_GLOBAL const double *m = gmem<const double>(g.m);
+    DSU_GLOBAL double *pb = gmem(g.panel_b), *pa = gmem(g.panel);
+    // element q of this thread: column / row a = grp + 4 q, the other index lane
+    double tv[kPairLoads], qv[kPairLoads], acc[16];
+    int qr[kPairLoads];
+#pragma unroll
+    for (int q = 0; q < kPairLoads; ++q) qr[q] = g.rowsrc[k0 + grp + 4 * q];
+    // lane = row, 16 columns a thread (one 128-byte line of its row of P1 M)
+    DSU_GLOBAL const double *mr = m + (size_t)g.rowsrc[r0 + lane] * np + k0 + 64 + 16 * grp;
+#pragma unroll
+    for (int q = 0; q < kPairLoads; ++q) {
+        tv[q] = pa[(size_t)(grp + 4 * q) * np + r0 + lane];
+        qv[q] = m[(size_t)qr[q] * np + k0 + 64 + lane];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = mr[q];
+#pragma unroll
+    for (int q = 0; q < kPairLoads; ++q) {
+        const int a = grp + 4 * q;
+        pb[(size_t)a * np + r0 + lane] = tv[q];
+        s_t[a][lane] = tv[q] - (r0 + lane == k0 + a ? 1.0 : 0.0);
+        s_q[a][lane] = qv[q];
+    }
+    __syncthreads();
+    for (int l = 0; l < 64; ++l) {
+        const double t = s_t[l][lane];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(t, s_q[l][16 * grp + q], acc[q]);
+    }
+    // column-major stores, coalesced
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pa[(size_t)(16 * grp + q) * np + r0 + lane] = acc[q];
+}
+
+// After the second panel: rowsrc_b = P2 (its own swaps), rowsrc = P2 P1 (row
+// i of the result <- row rowsrc[i] of M), qrow[l] = P1's source of row k0 + l.
+// One workgroup per determinant; both maps in dynamic LDS (8 np bytes).
+__global__ __launch_bounds__(kThreads) void k_gj_pair_rowsrc(const GjDesc *__restrict__ descs, int np, int k0) {
+    extern __shared__ int s_rr[];
+    __shared__ int s_piv[64];
+    const GjDesc g = descs[blockIdx.x];
+    int *r1 = s_rr, *r2 = s_rr + np;
+    if (threadIdx.x < 64) s_piv[threadIdx.x] = g.piv[k0 + 64 + threadIdx.x];
+    for (int i = threadIdx.x; i < np; i += kThreads) {
+        r1[i] = g.rowsrc[i];
+        r2[i] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int kk = 0; kk < 64; ++kk) {
+            const int k = k0 + 64 + kk, p = s_piv[kk];
+            if (p != k) {
+                const int t = r2[k];
+                r2[k] = r2[p];
+                r2[p] = t;
+            }
+        }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += kThreads) {
+        g.rowsrc_b[i] = r2[i];
+        g.rowsrc[i] = r1[r2[i]];
+    }
+    if (threadIdx.x < 64) g.qrow[threadIdx.x] = r1[k0 + threadIdx.x];
+}
+
+// Q2[j] = M1[P2 row k0 + 64 + j] = M[rowsrc[k0 + 64 + j]] + (T1 - E1)[r_j] Q1,
+// r_j = rowsrc_b[k0 + 64 + j], for all columns (R1's and R2's are not used).
+// One block per 64 columns; loads first, as above.
+__global__ __launch_bounds__(kThreads) void k_gj_pair_q2(const GjDesc *__restrict__ descs, int np, int k0) {
+    __shared__ double s_w[64][64];  // (T1 - E1)[r_j][l] at s_w[l][j]
+    __shared__ double s_q[64][64];  // Q1[l][c0 + c] at s_q[l][c]
+    const GjDesc g = descs[blockIdx.y];
+    const int c0 = blockIdx.x * 64, tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+    DSU_GLOBAL const double *m = gmem<const double>(g.m), *pb = gmem<const double>(g.panel_b);
+    double wv[kPairLoads], qv[kPairLoads], acc[16];
+    int qr[kPairLoads], sr[16];
+    const int r = g.rowsrc_b[k0 + 64 + lane];  // r_j of j = lane
+#pragma unroll
+    for (int q = 0; q < kPairLoads; ++q) qr[q] = g.qrow[grp + 4 * q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sr[q] = g.rowsrc[k0 + 64 + 16 * grp + q];
+#pragma unroll
+    for (int q = 0; q < kPairLoads; ++q) {
+        qv[q] = m[(size_t)qr[q] * np + c0 + lane];
+        wv[q] = pb[(size_t)(grp + 4 * q) * np + r];
+    }
+    // lane = column, 16 rows of Q2 a thread
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = m[(size_t)sr[q] * np + c0 + lane];
+#pragma unroll
+    for (int q = 0; q < kPairLoads; ++q) {
+        const int a = grp + 4 * q;
+        s_q[a][lane] = qv[q];
+        s_w[a][lane] = wv[q] - (r == k0 + a ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int l = 0; l < 64; ++l) {
+        const double qq = s_q[l][lane];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(s_w[l][16 * grp + q], qq, acc[q]);
+    }
+    // row-major stores, coalesced
+#pragma unroll
+    for (int q = 0; q < 16; ++q) g.q2[(size_t)(16 * grp + q) * np + c0 + lane] = acc[q];
+}
+
+// R1's columns of the pair's result: m2[i][k0 + j] = (P2 T1)[i][j] +
+// (T2 - E2)[i] (P2 T1)[R2][j] (T1 is M1's R1 block, Q2's R1 columns are its
+// rows at P2's pivots).  Runs after the update, which leaves those columns
+// to it.  One block per 64 rows; loads first, as above.  s_x holds (P2 T1)
+// first for the block's rows, then for R2's, each at s_x[row][col ^ row] (an
+// XOR swizzle: the row-wise stores and column-wise reads both spread over
+// the LDS banks).
+__global__ __launch_bounds__(kThreads) void k_gj_pair_fix(const GjDesc *__restrict__ descs, int np, int k0) {
+    __shared__ double s_a[64][64];  // (T2 - E2)[r0 + i][l] at s_a[l][i]
+    __shared__ double s_x[64][64];
+    const GjDesc g = descs[blockIdx.y];
+    const int r0 = blockIdx.x * 64, tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+    DSU_GLOBAL const double *pa = gmem<const double>(g.panel), *pb = gmem<const double>(g.panel_b);
+    double av[kPairLoads], x1[kPairLoads], x2[kPairLoads], acc[16];
+    const int rb = g.rowsrc_b[r0 + lane], rz = g.rowsrc_b[k0 + 64 + lane];
+#pragma unroll
+    for (int q = 0; q < kPairLoads; ++q) {
+        const int a = grp + 4 * q;
+        av[q] = pa[(size_t)a * np + r0 + lane];
+        x1[q] = pb[(size_t)a * np + rb];
+        x2[q] = pb[(size_t)a * np + rz];
+    }
+#pragma unroll
+    for (int q = 0; q < kPairLoads; ++q) {
+        const int a = grp + 4 * q;
+        s_a[a][lane] = av[q] - (r0 + lane == k0 + 64 + a ? 1.0 : 0.0);
+        s_x[lane][a ^ lane] = x1[q];
+    }
+    __syncthreads();
+    // lane = column, 16 rows a thread
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = s_x[16 * grp + q][lane ^ (16 * grp + q)];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPairLoads; ++q) {
+        const int a = grp + 4 * q;
+        s_x[lane][a ^ lane] = x2[q];
+    }
+    __syncthreads();
+    for (int l = 0; l < 64; ++l) {
+        const double z = s_x[l][lane ^ l];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(s_a[l][16 * grp + q], z, acc[q]);
+    }
+    // row-major stores, coalesced
+#pragma unroll
+    for (int q = 0; q < 16; ++q) g.m2[(size_t)(r0 + 16 * grp + q) * np + k0 + lane] = acc[q];
+}
+
 template <int RT, int CW>
 static void launch_gj_update(const GjDesc *descs_dev, int ndesc, int np, int nb, int k0, int w, hipStream_t s) {
     const int nblk = np / (64 * RT);
@@ -806,10 +1010,11 @@ static void launch_gj_update(const GjDesc *descs_dev, int ndesc, int np, int nb,
     else hipLaunchKernelGGL((k_gj_update<64, RT, CW>), grid, dim3(kThreads), 0, s, descs_dev, np, nblk, k0, w);
 }
 
+// gather = 0: the panel buffer already holds the panel's columns (a pair's second panel)
 template <int WS, int NPMAX, bool REG = false>
 static void launch_gj_panel2(const GjDesc *descs_dev, int ndesc, int n, int np, int nb, int k0, int w, int cpb,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_gj_gather, dim3(np / 64, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, w);
+                             hipStream_t s, bool gather = true) {
+    if (gather) hipLaunchKernelGGL(k_gj_gather, dim3(np / 64, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, w);
     for (int j0 = 0; j0 < w; j0 += WS) {
         const int ws = j0 + WS <= w ? WS : w - j0;
         if constexpr (REG)
@@ -853,11 +1058,13 @@ __global__ __launch_bounds__(kThreads) void k_gj_perm(const GjDesc *__restrict__
 }
 
 GjTiles gj_tiles_default(int n, int np) {
-    // measured on MI355X: 64-column panels from N = 512; 64-column update
-    // chunks where np pairs them up (3 % faster than 32 at N = 4096); four
-    // apply columns a workgroup from N = 2048 (one below: enough workgroups)
+    // measured on MI355X: 64-column panels from N = 512, in pairs from 1024
+    // (4096: 147 ms against 162 for 32 inverses; 512: 13.6 against 13.2 ms
+    // for 512); 64-column update chunks where np pairs them up (3 % faster
+    // than 32 at N = 4096); four apply columns a workgroup from N = 2048 (one
+    // below: enough workgroups)
     GjTiles t;
-    t.nb = n >= 512 ? 64 : (n >= 64 ? 32 : 16);
+    t.nb = n >= 1024 && np <= 4096 ? 128 : (n >= 512 ? 64 : (n >= 64 ? 32 : 16));
     t.cw = np % 128 == 0 ? 64 : 32;
     t.cpb = np >= 2048 ? 4 : 1;
     return t;
@@ -866,28 +1073,48 @@ GjTiles gj_tiles_default(int n, int np) {
 hipError_t launch_gj_invert(const GjDesc *set_a, const GjDesc *set_b, int ndesc, int n, int np, const GjTiles &tiles,
                             hipStream_t s, const GjDesc **final_set) {
     const int nb = tiles.nb, cw = tiles.cw, cpb = tiles.cpb;
-    if (nb != 16 && nb != 32 && nb != 64) return hipErrorInvalidValue;
+    if (nb != 16 && nb != 32 && nb != 64 && nb != 128) return hipErrorInvalidValue;
     if (np % 64) return hipErrorInvalidValue;  // the trailing update takes column chunks in pairs
     if (!(cw == 32 || (cw == 64 && np % 128 == 0)) || (cpb != 1 && cpb != 4)) return hipErrorInvalidValue;
+    const int pw = nb == 128 ? 64 : nb;  // columns factored at a time
+    const int in_lds = np <= 8192;       // row map in dynamic LDS (32 KB at most)
+    // factor the panel [k0, k0 + w): groups of 32 / 16 / 8 columns in registers up to np = 4096 (32 doubles a
+    // thread), then 2 columns in LDS up to 8192, else one column at a time
+    auto factor = [&](const GjDesc *d, int k0, int w, bool gather) {
+        if (np <= 1024) launch_gj_panel2<32, 1024, true>(d, ndesc, n, np, pw, k0, w, cpb, s, gather);
+        else if (np <= 2048) launch_gj_panel2<16, 2048, true>(d, ndesc, n, np, pw, k0, w, cpb, s, gather);
+        else if (np <= 4096) launch_gj_panel2<8, 4096, true>(d, ndesc, n, np, pw, k0, w, cpb, s, gather);
+        else if (np <= 8192) launch_gj_panel2<2, 8192>(d, ndesc, n, np, pw, k0, w, cpb, s, gather);
+        else hipLaunchKernelGGL(k_gj_panel, dim3(ndesc), dim3(kThreads), 0, s, d, n, np, pw, k0, k0 + w);
+    };
     const GjDesc *cur = set_a, *nxt = set_b;
-    for (int k0 = 0; k0 < n; k0 += nb) {
-        const int k1 = k0 + nb < n ? k0 + nb : n;
-        // factor the panel: groups of 32 / 16 / 8 columns in registers up to np = 4096 (32 doubles a
-        // thread), then 2 columns in LDS up to 8192, else one column at a time
-        if (np <= 1024) launch_gj_panel2<32, 1024, true>(cur, ndesc, n, np, nb, k0, k1 - k0, cpb, s);
-        else if (np <= 2048) launch_gj_panel2<16, 2048, true>(cur, ndesc, n, np, nb, k0, k1 - k0, cpb, s);
-        else if (np <= 4096) launch_gj_panel2<8, 4096, true>(cur, ndesc, n, np, nb, k0, k1 - k0, cpb, s);
-        else if (np <= 8192) launch_gj_panel2<2, 8192>(cur, ndesc, n, np, nb, k0, k1 - k0, cpb, s);
-        else hipLaunchKernelGGL(k_gj_panel, dim3(ndesc), dim3(kThreads), 0, s, cur, n, np, nb, k0, k1);
-        // row interchanges, pivot rows, then the trailing update into the other buffer
-        const int in_lds = np <= 8192;  // 32 KB of dynamic LDS at most
+    for (int k0 = 0; k0 < n;) {
+        const int k1 = k0 + pw < n ? k0 + pw : n;
+        // two whole 64-column panels share one trailing update (both row maps
+        // in LDS: np <= 4096); otherwise one panel at a time
+        const bool pair = nb == 128 && k0 + 128 <= n && np <= 4096;
+        factor(cur, k0, k1 - k0, true);
+        // row interchanges, then the trailing update into the other buffer
         hipLaunchKernelGGL(k_gj_rowsrc, dim3(ndesc), dim3(kThreads), in_lds ? np * sizeof(int) : 0, s, cur, np, k0,
                            k1, in_lds);
-        // (128-row workgroups, RT = 2, measured no faster than 64-row ones)
-        if (cw == 64)
-            launch_gj_update<1, 64>(cur, ndesc, np, nb, k0, k1 - k0, s);
-        else
-            launch_gj_update<1, 32>(cur, ndesc, np, nb, k0, k1 - k0, s);
+        if (pair) {
+            hipLaunchKernelGGL(k_gj_pair_slab, dim3(np / 64, ndesc), dim3(kThreads), 0, s, cur, np, k0);
+            factor(cur, k0 + 64, 64, false);
+            hipLaunchKernelGGL(k_gj_pair_rowsrc, dim3(ndesc), dim3(kThreads), (size_t)np * 2 * sizeof(int), s, cur, np,
+                               k0);
+            hipLaunchKernelGGL(k_gj_pair_q2, dim3(np / 64, ndesc), dim3(kThreads), 0, s, cur, np, k0);
+            hipLaunchKernelGGL((k_gj_update<128, 1, 32, true>), dim3(ndesc * (np / 64)), dim3(kThreads), 0, s, cur, np,
+                               np / 64, k0, 64);
+            hipLaunchKernelGGL(k_gj_pair_fix, dim3(np / 64, ndesc), dim3(kThreads), 0, s, cur, np, k0);
+            k0 += 128;
+        } else {
+            // (128-row workgroups, RT = 2, measured no faster than 64-row ones)
+            if (cw == 64)
+                launch_gj_update<1, 64>(cur, ndesc, np, pw, k0, k1 - k0, s);
+            else
+                launch_gj_update<1, 32>(cur, ndesc, np, pw, k0, k1 - k0, s);
+            k0 = k1;
+        }
         const GjDesc *t = cur;
         cur = nxt;
         nxt = t;

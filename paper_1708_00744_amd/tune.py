@@ -108,11 +108,17 @@ def recompute_key(n, walkers, precision):
 
 
 def recompute_candidates(n):
-    """Blockings of the FP64 recompute worth timing at this n: panel width,
-    update chunk (64 only where the padded size is a multiple of 128) and
-    apply columns per workgroup."""
+    """Blockings of the FP64 recompute worth timing at this n: panel width
+    (128 = pairs of 64-column panels sharing one trailing update, from n = 256
+    while the padded size is at most 4096), update chunk (64 only where the
+    padded size is a multiple of 128) and apply columns per workgroup."""
     np_ = -(-n // 64) * 64
-    panels = (32, 64) if n >= 64 else (16, 32)
+    if n < 64:
+        panels = (16, 32)
+    elif n >= 256 and np_ <= 4096:
+        panels = (32, 64, 128)
+    else:
+        panels = (32, 64)
     chunks = (32, 64) if np_ % 128 == 0 else (32,)
     return [(p, c, a) for p in panels for c in chunks for a in (1, 4)]
 

@@ -225,6 +225,32 @@ def test_fp64_recompute_full_size(n):
             cur[e] = rt
 
 
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_fp64_recompute_panel_pairs(n):
+    """The recompute with 64-column panels factored in pairs that share one
+    rank-128 trailing update, in FP64 at the headline sizes: sampled rows of
+    the inverse against LAPACK's within 1e-9 of their largest entry, the
+    log-determinant within 1e-9 and its sign, both device residuals within
+    FP64 rounding."""
+    require_gpu()
+    seed = 1000
+    pos = uniform(n, 1, seed)
+    a = oracle.pw_matrix(oracle.pw_kvectors(n), L, pos[0, 0])
+    ainv = np.linalg.inv(a)
+    s_np, l_np = np.linalg.slogdet(a)
+    with dsu.Batch(n, pos, [seed], [0], 0.002, 64, precision=dsu.FP64, box_l=L) as b:
+        b.set_recompute_tiles(128, 0, 0)
+        b.recompute()
+        st = b.stats()
+        assert st["sign"][0] == s_np and abs(st["logdet"][0] - l_np) < 1e-9
+        x = b.inverse(0)
+        rows = np.random.default_rng(4).choice(n, 64, replace=False)
+        err = np.abs(x[rows] - ainv[rows]).max() / np.abs(ainv[rows]).max()
+        right, left = b.residual(32)
+        print(f"n={n} pairs: inverse rows vs LAPACK {err:.2e}, residuals {right[0]:.2e} {left[0]:.2e}", flush=True)
+        assert err < 1e-9 and right[0] < 1e-10 and left[0] < 1e-10
+
+
 @pytest.mark.parametrize("n", [1024, 960, 300, 48])
 def test_recompute_tiles_agree(n):
     """Every blocking the autotuner may pick (panel width, update chunk, apply
@@ -232,7 +258,8 @@ def test_recompute_tiles_agree(n):
     same matrices to FP64 accuracy: sampled rows against LAPACK's inverse
     within 1e-9 of its largest entry, log|det| within 1e-9, the sign exact.
     Sizes: np a multiple of 128 (both chunks), 960 (np = 960: chunk 32 only),
-    ragged 300, and 48 (16-column panels)."""
+    ragged 300, and 48 (16-column panels); from 256 on also panel pairs (whole
+    pairs, then a single 64-column panel for the rest at 960 and 300)."""
     require_gpu()
     from paper_1708_00744_amd import tune
     walkers, seed = 2, 1000
@@ -266,8 +293,10 @@ def test_recompute_tiles_arguments():
     require_gpu()
     pos = uniform(960, 1, 1000)
     with dsu.Batch(960, pos, [1000], [0], 0.001, 16, precision=dsu.FP32_MIXED, box_l=L) as b:
-        for bad in [(48, 0, 0), (0, 64, 0), (0, 16, 0), (0, 0, 2)]:
+        for bad in [(48, 0, 0), (256, 0, 0), (0, 64, 0), (0, 16, 0), (0, 0, 2)]:
             with pytest.raises(dsu.DsuError):
                 b.set_recompute_tiles(*bad)
         b.set_recompute_tiles(16, 32, 4)
         assert b.recompute_tiles() == {"panel": 16, "chunk": 32, "apply_columns": 4}
+        b.set_recompute_tiles(128, 32, 1)
+        assert b.recompute_tiles() == {"panel": 128, "chunk": 32, "apply_columns": 1}
