@@ -1058,13 +1058,14 @@ __global__ __launch_bounds__(kThreads) void k_gj_perm(const GjDesc *__restrict__
 }
 
 GjTiles gj_tiles_default(int n, int np) {
-    // measured on MI355X: 64-column panels from N = 512, in pairs from 1024
-    // (4096: 147 ms against 162 for 32 inverses; 512: 13.6 against 13.2 ms
-    // for 512); 64-column update chunks where np pairs them up (3 % faster
-    // than 32 at N = 4096); four apply columns a workgroup from N = 2048 (one
-    // below: enough workgroups)
+    // measured on MI355X: 64-column panels from N = 512, in pairs from 2048
+    // (4096: 147 ms against 163 for 32 inverses, 2048: 47 against 48 ms for
+    // 64; at 1024 the two are within 1 %, at 512 single panels are faster);
+    // 64-column update chunks where np pairs them up (3 % faster than 32 at
+    // N = 4096); four apply columns a workgroup from N = 2048 (one below:
+    // enough workgroups)
     GjTiles t;
-    t.nb = n >= 1024 && np <= 4096 ? 128 : (n >= 512 ? 64 : (n >= 64 ? 32 : 16));
+    t.nb = n >= 2048 && np <= 4096 ? 128 : (n >= 512 ? 64 : (n >= 64 ? 32 : 16));
     t.cw = np % 128 == 0 ? 64 : 32;
     t.cpb = np >= 2048 ? 4 : 1;
     return t;
