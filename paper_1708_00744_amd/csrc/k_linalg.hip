@@ -774,7 +774,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_subr(const GjDesc *__restrict
 // s_0(s_1(...s_{ws-1}(r))), traced by one thread per involved row, so the
 // values move in one parallel round of loads and stores.  A workgroup takes
 // CPB columns, so each element of (E - S) it reads serves CPB of them.
-template <int CPB>
+template <int CPB, int RB>
 __global__ __launch_bounds__(kThreads) void k_gj_sub_apply(const GjDesc *__restrict__ descs, int np, int k0, int j0,
                                                            int ws, int w) {
     __shared__ int s_k[64], s_p[64], s_src[128];
@@ -812,20 +812,40 @@ __global__ __launch_bounds__(kThreads) void k_gj_sub_apply(const GjDesc *__restr
         if (on[q]) P[(size_t)(c0 + q) * np + r] = s_val[q][t];  // rows named twice receive the same value
     }
     __syncthreads();
-    // q[kk] = the value at row k0 + j0 + kk after the swaps = s_val[.][kk]
-    for (int i = tid; i < np; i += kThreads) {
-        double a[CPB];
+    // q[kk] = the value at row k0 + j0 + kk after the swaps = s_val[.][kk].
+    // RB rows a thread per pass, their loads all issued before the pass's
+    // stores (which may alias them for all the compiler knows): one memory
+    // latency per RB rows.  RB = 4 where the blocks are few (np >= 2048: 2 ms
+    // less per recompute of 32 x 4096); where they are many, the registers it
+    // takes cost more occupancy than it saves (RB = 1).
+    for (int i0 = tid; i0 < np; i0 += RB * kThreads) {
+        double a[RB][CPB];
 #pragma unroll
-        for (int q = 0; q < CPB; ++q) a[q] = on[q] ? P[(size_t)(c0 + q) * np + i] : 0.0;
+        for (int r = 0; r < RB; ++r) {
+            const int i = i0 + r * kThreads;
+#pragma unroll
+            for (int q = 0; q < CPB; ++q) a[r][q] = on[q] && i < np ? P[(size_t)(c0 + q) * np + i] : 0.0;
+        }
 #pragma unroll 8
         for (int kk = 0; kk < ws; ++kk) {
-            const double e = Wg[(size_t)kk * np + i];
+            double e[RB];
 #pragma unroll
-            for (int q = 0; q < CPB; ++q) a[q] -= e * s_val[q][kk];
+            for (int r = 0; r < RB; ++r) {
+                const int i = i0 + r * kThreads;
+                e[r] = i < np ? Wg[(size_t)kk * np + i] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int q = 0; q < CPB; ++q) a[r][q] -= e[r] * s_val[q][kk];
         }
 #pragma unroll
-        for (int q = 0; q < CPB; ++q)
-            if (on[q]) P[(size_t)(c0 + q) * np + i] = a[q];
+        for (int r = 0; r < RB; ++r) {
+            const int i = i0 + r * kThreads;
+#pragma unroll
+            for (int q = 0; q < CPB; ++q)
+                if (on[q] && i < np) P[(size_t)(c0 + q) * np + i] = a[r][q];
+        }
     }
 }
 
@@ -836,14 +856,17 @@ __global__ __launch_bounds__(kThreads) void k_gj_sub_apply(const GjDesc *__restr
 
 // After the first panel: R2's columns of M1 = P1 M + (T1 - E1) Q1 become the
 // second panel, and T1 moves to panel_b.  Rows are independent, so each block
-// rewrites the rows it read.  One block per 64 rows; every global load of a
-// thread is issued before its first store (the stores may alias the loads for
-// all the compiler knows, which would otherwise serialise them).
+// rewrites the rows it read.  One block per 64 rows.  In the three pair
+// kernels every global load of a thread is issued before its first store (the
+// stores may alias the loads for all the compiler knows, which would otherwise
+// serialise them), and the 64-term products run in two halves of 32 through
+// 32 KB of LDS (three blocks a compute unit instead of two).
 constexpr int kPairLoads = 64 * 64 / kThreads;  // elements of a 64 x 64 tile per thread
+constexpr int kPairHalf = kPairLoads / 2;       // element q holds index grp + 4 q: q < 8 is the first half
 
 __global__ __launch_bounds__(kThreads) void k_gj_pair_slab(const GjDesc *__restrict__ descs, int np, int k0) {
-    __shared__ double s_t[64][64];  // (T1 - E1)[r0 + i][l] at s_t[l][i]
-    __shared__ double s_q[64][64];  // Q1[l][R2 column j] at s_q[l][j]
+    __shared__ double s_t[32][64];  // (T1 - E1)[r0 + i][l] at s_t[l - 32 h][i], half h of l at a time
+    __shared__ double s_q[32][64];  // Q1[l][R2 column j] at s_q[l - 32 h][j]
     const GjDesc g = descs[blockIdx.y];
     const int r0 = blockIdx.x * 64, tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
     DSU_GLOBAL const double *m = gmem<const double>(g.m);
@@ -863,17 +886,22 @@ __global__ __launch_bounds__(kThreads) void k_gj_pair_slab(const GjDesc *__restr
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = mr[q];
 #pragma unroll
-    for (int q = 0; q < kPairLoads; ++q) {
-        const int a = grp + 4 * q;
-        pb[(size_t)a * np + r0 + lane] = tv[q];
-        s_t[a][lane] = tv[q] - (r0 + lane == k0 + a ? 1.0 : 0.0);
-        s_q[a][lane] = qv[q];
-    }
-    __syncthreads();
-    for (int l = 0; l < 64; ++l) {
-        const double t = s_t[l][lane];
+    for (int q = 0; q < kPairLoads; ++q) pb[(size_t)(grp + 4 * q) * np + r0 + lane] = tv[q];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(t, s_q[l][16 * grp + q], acc[q]);
+    for (int h = 0; h < 2; ++h) {
+        if (h) __syncthreads();  // the first half read by every wave
+#pragma unroll
+        for (int q = kPairHalf * h; q < kPairHalf * (h + 1); ++q) {
+            const int a = grp + 4 * q;
+            s_t[a - 32 * h][lane] = tv[q] - (r0 + lane == k0 + a ? 1.0 : 0.0);
+            s_q[a - 32 * h][lane] = qv[q];
+        }
+        __syncthreads();
+        for (int l = 0; l < 32; ++l) {
+            const double t = s_t[l][lane];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(t, s_q[l][16 * grp + q], acc[q]);
+        }
     }
     // column-major stores, coalesced
 #pragma unroll
@@ -913,10 +941,10 @@ __global__ __launch_bounds__(kThreads) void k_gj_pair_rowsrc(const GjDesc *__res
 
 // Q2[j] = M1[P2 row k0 + 64 + j] = M[rowsrc[k0 + 64 + j]] + (T1 - E1)[r_j] Q1,
 // r_j = rowsrc_b[k0 + 64 + j], for all columns (R1's and R2's are not used).
-// One block per 64 columns; loads first, as above.
+// One block per 64 columns; loads first and halves of 32, as above.
 __global__ __launch_bounds__(kThreads) void k_gj_pair_q2(const GjDesc *__restrict__ descs, int np, int k0) {
-    __shared__ double s_w[64][64];  // (T1 - E1)[r_j][l] at s_w[l][j]
-    __shared__ double s_q[64][64];  // Q1[l][c0 + c] at s_q[l][c]
+    __shared__ double s_w[32][64];  // (T1 - E1)[r_j][l] at s_w[l - 32 h][j]
+    __shared__ double s_q[32][64];  // Q1[l][c0 + c] at s_q[l - 32 h][c]
     const GjDesc g = descs[blockIdx.y];
     const int c0 = blockIdx.x * 64, tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
     DSU_GLOBAL const double *m = gmem<const double>(g.m), *pb = gmem<const double>(g.panel_b);
@@ -936,16 +964,20 @@ __global__ __launch_bounds__(kThreads) void k_gj_pair_q2(const GjDesc *__restric
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = m[(size_t)sr[q] * np + c0 + lane];
 #pragma unroll
-    for (int q = 0; q < kPairLoads; ++q) {
-        const int a = grp + 4 * q;
-        s_q[a][lane] = qv[q];
-        s_w[a][lane] = wv[q] - (r == k0 + a ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    for (int l = 0; l < 64; ++l) {
-        const double qq = s_q[l][lane];
+    for (int h = 0; h < 2; ++h) {
+        if (h) __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(s_w[l][16 * grp + q], qq, acc[q]);
+        for (int q = kPairHalf * h; q < kPairHalf * (h + 1); ++q) {
+            const int a = grp + 4 * q;
+            s_q[a - 32 * h][lane] = qv[q];
+            s_w[a - 32 * h][lane] = wv[q] - (r == k0 + a ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        for (int l = 0; l < 32; ++l) {
+            const double qq = s_q[l][lane];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(s_w[l][16 * grp + q], qq, acc[q]);
+        }
     }
     // row-major stores, coalesced
 #pragma unroll
@@ -955,13 +987,13 @@ __global__ __launch_bounds__(kThreads) void k_gj_pair_q2(const GjDesc *__restric
 // R1's columns of the pair's result: m2[i][k0 + j] = (P2 T1)[i][j] +
 // (T2 - E2)[i] (P2 T1)[R2][j] (T1 is M1's R1 block, Q2's R1 columns are its
 // rows at P2's pivots).  Runs after the update, which leaves those columns
-// to it.  One block per 64 rows; loads first, as above.  s_x holds (P2 T1)
-// first for the block's rows, then for R2's, each at s_x[row][col ^ row] (an
-// XOR swizzle: the row-wise stores and column-wise reads both spread over
-// the LDS banks).
+// to it.  One block per 64 rows; loads first, as above.  The 32 KB of LDS
+// first hold (P2 T1) of the block's rows at [i][j ^ i] (an XOR swizzle: the
+// row-wise stores and column-wise reads both spread over the LDS banks), then
+// per half h of l: (T2 - E2)[r0 + i][l] at [l - 32 h][i] in the first 16 KB
+// and (P2 T1)[R2 row l][j] at [l - 32 h][j ^ l] in the second.
 __global__ __launch_bounds__(kThreads) void k_gj_pair_fix(const GjDesc *__restrict__ descs, int np, int k0) {
-    __shared__ double s_a[64][64];  // (T2 - E2)[r0 + i][l] at s_a[l][i]
-    __shared__ double s_x[64][64];
+    __shared__ double s_buf[64 * 64];
     const GjDesc g = descs[blockIdx.y];
     const int r0 = blockIdx.x * 64, tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
     DSU_GLOBAL const double *pa = gmem<const double>(g.panel), *pb = gmem<const double>(g.panel_b);
@@ -977,25 +1009,42 @@ __global__ __launch_bounds__(kThreads) void k_gj_pair_fix(const GjDesc *__restri
 #pragma unroll
     for (int q = 0; q < kPairLoads; ++q) {
         const int a = grp + 4 * q;
-        s_a[a][lane] = av[q] - (r0 + lane == k0 + 64 + a ? 1.0 : 0.0);
-        s_x[lane][a ^ lane] = x1[q];
+        s_buf[lane * 64 + (a ^ lane)] = x1[q];
     }
     __syncthreads();
     // lane = column, 16 rows a thread
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = s_x[16 * grp + q][lane ^ (16 * grp + q)];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kPairLoads; ++q) {
-        const int a = grp + 4 * q;
-        s_x[lane][a ^ lane] = x2[q];
+    for (int q = 0; q < 16; ++q) {
+        const int i = 16 * grp + q;
+        acc[q] = s_buf[i * 64 + (lane ^ i)];
     }
-    __syncthreads();
-    for (int l = 0; l < 64; ++l) {
-        const double z = s_x[l][lane ^ l];
+    double *s_a = s_buf, *s_z = s_buf + 32 * 64;
+    // half h of l (a compile-time constant, so every register index is fixed)
+    auto half = [&](auto h_c) __attribute__((always_inline)) {
+        constexpr int h = decltype(h_c)::value;
+        __syncthreads();  // every wave done with the previous contents
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(s_a[l][16 * grp + q], z, acc[q]);
-    }
+        for (int q = kPairHalf * h; q < kPairHalf * (h + 1); ++q) {
+            const int a = grp + 4 * q;
+            s_a[(a - 32 * h) * 64 + lane] = av[q] - (r0 + lane == k0 + 64 + a ? 1.0 : 0.0);
+        }
+        if ((lane >> 5) == h)
+#pragma unroll
+            for (int q = 0; q < kPairLoads; ++q) {
+                const int a = grp + 4 * q;
+                s_z[(lane - 32 * h) * 64 + (a ^ lane)] = x2[q];
+            }
+        __syncthreads();
+#pragma unroll 4
+        for (int l = 0; l < 32; ++l) {
+            const int la = 32 * h + l;
+            const double z = s_z[l * 64 + (lane ^ la)];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(s_a[l * 64 + 16 * grp + q], z, acc[q]);
+        }
+    };
+    half(std::integral_constant<int, 0>{});
+    half(std::integral_constant<int, 1>{});
     // row-major stores, coalesced
 #pragma unroll
     for (int q = 0; q < 16; ++q) g.m2[(size_t)(r0 + 16 * grp + q) * np + k0 + lane] = acc[q];
@@ -1023,11 +1072,15 @@ static void launch_gj_panel2(const GjDesc *descs_dev, int ndesc, int n, int np, 
         else
             hipLaunchKernelGGL((k_gj_sub<WS, NPMAX>), dim3(ndesc), dim3(kGjThreads), 0, s, descs_dev, n, np, k0, j0,
                                ws);
-        if (w > ws && cpb == 4)
-            hipLaunchKernelGGL((k_gj_sub_apply<4>), dim3((w + 3) / 4, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0,
-                               j0, ws, w);
+        if (w > ws && cpb == 4 && np >= 2048)
+            hipLaunchKernelGGL((k_gj_sub_apply<4, 4>), dim3((w + 3) / 4, ndesc), dim3(kThreads), 0, s, descs_dev, np,
+                               k0, j0, ws, w);
+        else if (w > ws && cpb == 4)
+            hipLaunchKernelGGL((k_gj_sub_apply<4, 1>), dim3((w + 3) / 4, ndesc), dim3(kThreads), 0, s, descs_dev, np,
+                               k0, j0, ws, w);
         else if (w > ws)
-            hipLaunchKernelGGL((k_gj_sub_apply<1>), dim3(w, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, j0, ws, w);
+            hipLaunchKernelGGL((k_gj_sub_apply<1, 1>), dim3(w, ndesc), dim3(kThreads), 0, s, descs_dev, np, k0, j0, ws,
+                               w);
     }
 }
 
@@ -1058,14 +1111,14 @@ __global__ __launch_bounds__(kThreads) void k_gj_perm(const GjDesc *__restrict__
 }
 
 GjTiles gj_tiles_default(int n, int np) {
-    // measured on MI355X: 64-column panels from N = 512, in pairs from 2048
-    // (4096: 147 ms against 163 for 32 inverses, 2048: 47 against 48 ms for
-    // 64; at 1024 the two are within 1 %, at 512 single panels are faster);
-    // 64-column update chunks where np pairs them up (3 % faster than 32 at
-    // N = 4096); four apply columns a workgroup from N = 2048 (one below:
-    // enough workgroups)
+    // measured on MI355X: 64-column panels from N = 512, in pairs from 1024
+    // (4096: 146 ms against 162 for 32 inverses, 2048: 45 against 47 ms for
+    // 64, 1024: 26.2 against 26.8 ms for 256; at 512 single panels are
+    // faster); 64-column update chunks where np pairs them up (3 % faster
+    // than 32 at N = 4096); four apply columns a workgroup from N = 2048 (one
+    // below: enough workgroups)
     GjTiles t;
-    t.nb = n >= 2048 && np <= 4096 ? 128 : (n >= 512 ? 64 : (n >= 64 ? 32 : 16));
+    t.nb = n >= 1024 && np <= 4096 ? 128 : (n >= 512 ? 64 : (n >= 64 ? 32 : 16));
     t.cw = np % 128 == 0 ? 64 : 32;
     t.cpb = np >= 2048 ? 4 : 1;
     return t;
